@@ -1,0 +1,66 @@
+"""Input recipes: SplitMix64 against its published first outputs, and the
+numpy and C host builds of every recipe against each other."""
+import numpy as np
+import pytest
+
+import inputgen
+from inputgen import native
+
+
+def test_splitmix64_published_outputs():
+    # first three outputs of SplitMix64 seeded with 0, as published with the
+    # reference implementation of the generator
+    h = inputgen.splitmix64(0, 0, 3)
+    assert [int(x) for x in h] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_splitmix64_indexable():
+    a = inputgen.splitmix64(123, 0, 1000)
+    b = inputgen.splitmix64(123, 400, 600)
+    assert np.array_equal(a[400:], b)
+
+
+@pytest.mark.parametrize("kind", sorted(inputgen.KIND_DTYPE))
+def test_host_c_matches_numpy(kind):
+    cdf = inputgen.zipf_cdf(1.1, 10 ** 6) if kind in (inputgen.KIND_ZIPF_I64, inputgen.KIND_ZIPF_F32,
+                                                     inputgen.KIND_ZIPF_I32) else None
+    n, start, n_total = 100_003, 77, 1 << 20
+    a = inputgen.generate(kind, 99, n, start=start, n_total=n_total, cdf=cdf)
+    b = native.host_fill(kind, 99, n, start=start, n_total=n_total, cdf=cdf, nthreads=4)
+    assert a.dtype == b.dtype
+    assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def test_uniform_ranges():
+    x = inputgen.generate(inputgen.KIND_U_F32, 5, 1 << 16)
+    assert x.min() >= 0.0 and x.max() < 1.0
+    assert np.all(x * np.float32(2 ** 24) == np.floor(x * np.float32(2 ** 24)))
+    y = inputgen.generate(inputgen.KIND_U_I32, 5, 1 << 16)
+    assert y.min() >= 0
+
+
+def test_zipf_frequencies():
+    cdf = inputgen.zipf_cdf(1.1, 10 ** 6)
+    assert cdf[-1] == 1.0
+    r = inputgen.generate(inputgen.KIND_ZIPF_I64, 7, 1 << 20, cdf=cdf)
+    assert r.min() >= 1 and r.max() <= 10 ** 6
+    h = np.sum(np.arange(1, 10 ** 6 + 1, dtype=np.float64) ** -1.1)
+    p1 = 1.0 / h
+    f1 = np.mean(r == 1)
+    assert abs(f1 - p1) < 5 * np.sqrt(p1 * (1 - p1) / len(r))
+
+
+def test_presorted_closed_form():
+    n = 1 << 12
+    x = inputgen.generate(inputgen.KIND_SORTED_F32, 0, n, n_total=1 << 28)
+    assert np.all(np.diff(x) >= 0)
+    full = inputgen.generate(inputgen.KIND_SORTED_F32, 0, 64, n_total=1 << 28)
+    assert np.array_equal(full, (np.arange(64) >> 4).astype(np.float32) * np.float32(2 ** -24))
+
+
+def test_batched_query_shapes():
+    off, k, o = inputgen.batched_queries(4096)
+    n = np.diff(off.astype(np.int64))
+    assert n.min() >= 2 ** 10 and n.max() < 2 ** 24
+    assert k.min() >= 1 and k.max() <= 4096 and np.all(k <= n)
+    assert int(o.sum()) == 2048
