@@ -1,0 +1,129 @@
+/* mitopk — key-only Top-K selection on MI355X (gfx950).
+ *
+ * The ordering primitive of "GPU-Augmented OLAP Execution Engine: GPU
+ * Offloading" (arXiv 2601.19911): sec. III-A defines LIMIT-based Top-K as
+ * key-only transfer, partial or radix-based selection on the GPU, and a return
+ * of the Top-K pointers; sec. II-C states the key-only contract (only (Key,
+ * Pointer(RowID)) pairs cross to the device, the device returns only sorted
+ * pointers, the host late-materializes the few returned rows); sec. V-B gives
+ * the query template ORDER BY value DESC LIMIT 100.
+ *
+ * Result definition (every entry point computes exactly this):
+ *   pair a comes before pair b
+ *     TK_DESC: key_a > key_b, or key_a == key_b and rowid_a < rowid_b
+ *     TK_ASC:  key_a < key_b, or key_a == key_b and rowid_a < rowid_b
+ *   with numeric order for int32/int64 keys and IEEE 754-2019 totalOrder
+ *   (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN) for float32 keys.
+ *   The output is the first K_eff = min(k, n) pairs in that order, best
+ *   first: out_keys[j] holds the original key bits, out_rowids[j] its row-id.
+ *
+ * Conventions for all calls:
+ *   - Keys and row-ids are separate arrays (structure of arrays).  rowids may
+ *     be NULL: row-id i is then the index i (for rid type u32, n <= 2^32).
+ *   - Device pointers are plain HIP device (or host-mapped) addresses; the
+ *     caller owns every buffer: inputs, outputs and workspace.  The library
+ *     owns only its opaque objects (tk_plan, tk_server).
+ *   - Stream-ordered and asynchronous: tk_topk enqueues work on `stream`
+ *     (a hipStream_t, NULL = the default stream) and returns without waiting.
+ *     Outputs are valid once the stream has reached that point.
+ *   - Errors: argument errors are returned at once (negative tk_status_t) and
+ *     nothing is enqueued.  Failures found on the device afterwards (which
+ *     correct use never produces) are kept in the workspace and reported by
+ *     tk_query_info after the stream is synchronized.
+ *   - Reentrant when calls use distinct workspaces.
+ */
+#ifndef MITOPK_H
+#define MITOPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { TK_KEY_I32 = 0, TK_KEY_I64 = 1, TK_KEY_F32 = 2 } tk_key_t;
+typedef enum { TK_RID_U32 = 0, TK_RID_U64 = 1 } tk_rid_t;
+typedef enum { TK_DESC = 0, TK_ASC = 1 } tk_order_t;
+
+typedef enum {
+  TK_OK = 0,
+  TK_EINVAL = -1,        /* bad argument: null pointer with n > 0, bad enum, small workspace */
+  TK_ENOMEM = -2,        /* host allocation failed */
+  TK_EHIP = -3,          /* a HIP runtime call failed */
+  TK_EUNSUPPORTED = -4,  /* no usable gfx950 device, or a size beyond the limits */
+  TK_EDEVICE = -5,       /* the device reported a failure (see tk_query_info) */
+  TK_EAGAIN = 1          /* not finished yet (serving poll) */
+} tk_status_t;
+
+/* Bytes of device workspace tk_topk needs for a query of n keys and limit k
+ * (any k; it is capped at n).  Depends only on (n, min(k, n), key type,
+ * row-id type) and the current tuning.  Never 0. */
+size_t tk_workspace_size(uint64_t n, uint64_t k, int key_type, int rid_type);
+
+/* One Top-K query (paper sec. III-A): selects the best min(k, n) (key,
+ * row-id) pairs and writes them best first.
+ *   keys        device array of n keys (int32, int64 or float32 bits)
+ *   rowids      device array of n row-ids of rid_type, or NULL (row-id = index)
+ *   out_keys    device array of >= min(k, n) keys, or NULL (row-ids only)
+ *   out_rowids  device array of >= min(k, n) row-ids of rid_type, or NULL
+ *   out_count   host pointer, set to min(k, n) before return (may be NULL)
+ *   workspace   device buffer of >= tk_workspace_size(...) bytes, 256-byte
+ *               aligned; contents need no initialization and are scratch
+ *               until the stream passes the call
+ *   stream      hipStream_t (NULL: default stream)
+ * k = 0 or n = 0 is valid and enqueues nothing.  Returns TK_OK or an error. */
+int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int key_type,
+            int rid_type, int order, void* out_keys, void* out_rowids, uint64_t* out_count,
+            void* workspace, size_t workspace_bytes, void* stream);
+
+/* What the device did for the last tk_topk that used `workspace`.  Copies a
+ * few words from the device synchronously; call after the stream has passed
+ * the query. */
+typedef struct {
+  uint32_t path;        /* 1 one-workgroup, 2 sample+filter+LDS tail, 3 sample+filter+
+                           exact on survivors, 4 exact fallback over the input,
+                           5 exact radix select over the input */
+  uint32_t status;      /* 0, or device failure bits (1: a grid barrier timed out) */
+  uint64_t survivors;   /* keys that passed the sampled threshold (paths 2-4) */
+  uint64_t threshold_key;  /* sampled threshold, order-preserving key image */
+} tk_info;
+int tk_query_info(const void* workspace, tk_info* info);
+
+/* Process-wide tuning and test knobs; values <= 0 leave a field unchanged.
+ * Not thread-safe against concurrent tk_topk calls. */
+typedef struct {
+  double sample_sigma;       /* margin of the sampled threshold (std devs), default 3 */
+  double cap_sigma;          /* survivor capacity margin (std devs), default 6 */
+  int32_t max_sample_log2;   /* largest sample, default 20 */
+  int32_t filter_grid;       /* workgroups of the streaming pass, default 8 per CU */
+  int64_t force_cap;         /* > 0: fixed survivor capacity (forces the fallback) */
+  int32_t force_exact;       /* 1: always the exact radix select, 2: back to default */
+} tk_tuning;
+int tk_set_tuning(const tk_tuning* t);
+
+/* Multithreaded CPU Top-K over host arrays: the CPU route of the cost gate
+ * (paper sec. II-B) with the same result definition.  nthreads <= 0 uses
+ * every core in the process affinity mask.  Synchronous. */
+int tk_cpu_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int key_type,
+                int rid_type, int order, void* out_keys, void* out_rowids, uint64_t* out_count,
+                int nthreads);
+
+/* Kernel timing for roofline reports.  Between tk_profile_begin and
+ * tk_profile_end, every streaming pass over the keys (the dominant kernel:
+ * the filter of tk_topk, the persistent kernel of tk_plan_launch) is
+ * bracketed by a HIP event pair recorded on the caller's stream, for at most
+ * max_launches launches.  tk_profile_end waits for the recorded events and
+ * returns the summed kernel time in milliseconds and the number of launches
+ * timed.  Process-wide; for measurement, not for concurrent use. */
+int tk_profile_begin(uint32_t max_launches);
+int tk_profile_end(double* total_ms, uint64_t* launches);
+
+/* Human-readable name of a tk_status_t value. */
+const char* tk_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MITOPK_H */

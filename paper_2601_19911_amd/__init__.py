@@ -1,0 +1,209 @@
+"""Python binding of libmitopk.so: key-only Top-K on MI355X.
+
+Argument marshalling only: every step of the selection runs in the HIP
+kernels behind the C ABI declared in include/mitopk.h.  PyTorch supplies
+device memory and streams.  There is no fallback: if the library is missing
+or no GPU is present, the GPU entry points raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmitopk.so")
+
+TK_KEY_I32, TK_KEY_I64, TK_KEY_F32 = 0, 1, 2
+TK_RID_U32, TK_RID_U64 = 0, 1
+TK_DESC, TK_ASC = 0, 1
+
+_lib = None
+
+
+class TopKError(RuntimeError):
+    pass
+
+
+class tk_info(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_uint32), ("status", ctypes.c_uint32),
+                ("survivors", ctypes.c_uint64), ("threshold_key", ctypes.c_uint64)]
+
+
+class tk_tuning(ctypes.Structure):
+    _fields_ = [("sample_sigma", ctypes.c_double), ("cap_sigma", ctypes.c_double),
+                ("max_sample_log2", ctypes.c_int32), ("filter_grid", ctypes.c_int32),
+                ("force_cap", ctypes.c_int64), ("force_exact", ctypes.c_int32)]
+
+
+def lib():
+    """The loaded libmitopk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TopKError(f"{LIB_PATH} is missing: build it with python -m paper_2601_19911_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+        L.tk_workspace_size.argtypes = [u64, u64, i32, i32]
+        L.tk_workspace_size.restype = ctypes.c_size_t
+        L.tk_topk.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, ctypes.POINTER(u64), vp,
+                              ctypes.c_size_t, vp]
+        L.tk_topk.restype = i32
+        L.tk_query_info.argtypes = [vp, ctypes.POINTER(tk_info)]
+        L.tk_query_info.restype = i32
+        L.tk_set_tuning.argtypes = [ctypes.POINTER(tk_tuning)]
+        L.tk_set_tuning.restype = i32
+        L.tk_cpu_topk.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, ctypes.POINTER(u64), i32]
+        L.tk_cpu_topk.restype = i32
+        L.tk_profile_begin.argtypes = [ctypes.c_uint32]
+        L.tk_profile_begin.restype = i32
+        L.tk_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]
+        L.tk_profile_end.restype = i32
+        L.tk_status_string.argtypes = [i32]
+        L.tk_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str = "call"):
+    if rc != 0:
+        msg = lib().tk_status_string(rc).decode()
+        raise TopKError(f"{what} failed: {msg} ({rc})")
+
+
+# ---- dtype codes -------------------------------------------------------------------------------
+
+def key_code(dtype) -> int:
+    import torch
+    m = {torch.int32: TK_KEY_I32, torch.int64: TK_KEY_I64, torch.float32: TK_KEY_F32,
+         np.dtype(np.int32): TK_KEY_I32, np.dtype(np.int64): TK_KEY_I64,
+         np.dtype(np.float32): TK_KEY_F32}
+    if dtype not in m:
+        raise TypeError(f"unsupported key dtype {dtype}")
+    return m[dtype]
+
+
+def rid_code(dtype) -> int:
+    import torch
+    m = {torch.int32: TK_RID_U32, torch.uint32: TK_RID_U32, torch.int64: TK_RID_U64,
+         torch.uint64: TK_RID_U64, np.dtype(np.uint32): TK_RID_U32,
+         np.dtype(np.uint64): TK_RID_U64}
+    if dtype not in m:
+        raise TypeError(f"unsupported row-id dtype {dtype}")
+    return m[dtype]
+
+
+def order_code(order) -> int:
+    if order in (TK_DESC, "desc", "DESC"):
+        return TK_DESC
+    if order in (TK_ASC, "asc", "ASC"):
+        return TK_ASC
+    raise ValueError(f"order must be 'desc' or 'asc', not {order!r}")
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream) -> int | None:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+# ---- single query ---------------------------------------------------------------------------
+
+def workspace_size(n: int, k: int, key_type: int, rid_type: int) -> int:
+    return int(lib().tk_workspace_size(n, k, key_type, rid_type))
+
+
+def topk(keys, k: int, rowids=None, order="desc", out_keys=None, out_rowids=None,
+         rid_dtype=None, workspace=None, stream=None, want_keys: bool = True):
+    """Top-K of device tensor ``keys`` (int32, int64 or float32), best first.
+
+    ``rowids``: device tensor of uint32/uint64 row-ids, or None for the index.
+    Returns ``(out_keys, out_rowids)``; tensors are allocated when not given.
+    """
+    import torch
+    if not keys.is_cuda:
+        raise TopKError("keys must be a device tensor")
+    keys = keys.contiguous()
+    n = keys.shape[0]
+    kc = key_code(keys.dtype)
+    if rowids is not None:
+        rowids = rowids.contiguous()
+        assert rowids.shape[0] == n and rowids.is_cuda
+        rc_ = rid_code(rowids.dtype)
+        rdt = rowids.dtype
+    else:
+        rdt = rid_dtype if rid_dtype is not None else (torch.uint32 if n <= (1 << 32) else torch.uint64)
+        rc_ = rid_code(rdt)
+    oc = order_code(order)
+    k_eff = min(int(k), n)
+    dev = keys.device
+    if out_keys is None and want_keys:
+        out_keys = torch.empty(k_eff, dtype=keys.dtype, device=dev)
+    if out_rowids is None:
+        out_rowids = torch.empty(k_eff, dtype=rdt, device=dev)
+    ws_bytes = workspace_size(n, k, kc, rc_)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    cnt = ctypes.c_uint64(0)
+    rc = lib().tk_topk(_ptr(keys) if n else None, _ptr(rowids), n, int(k), kc, rc_, oc,
+                       _ptr(out_keys), _ptr(out_rowids), ctypes.byref(cnt),
+                       workspace.data_ptr(), workspace.numel(), _stream_handle(stream))
+    check(rc, "tk_topk")
+    return out_keys, out_rowids
+
+
+def query_info(workspace) -> dict:
+    info = tk_info()
+    rc = lib().tk_query_info(workspace.data_ptr(), ctypes.byref(info))
+    return {"rc": rc, "path": info.path, "status": info.status, "survivors": info.survivors,
+            "threshold_key": info.threshold_key}
+
+
+def set_tuning(sample_sigma=0.0, cap_sigma=0.0, max_sample_log2=0, filter_grid=0, force_cap=0,
+               force_exact=0):
+    """Process-wide knobs; 0 leaves a field unchanged (force_cap=-1 and
+    force_exact=2 restore the defaults)."""
+    t = tk_tuning(sample_sigma, cap_sigma, max_sample_log2, filter_grid, force_cap, force_exact)
+    check(lib().tk_set_tuning(ctypes.byref(t)), "tk_set_tuning")
+
+
+def profile_begin(max_launches: int = 4096):
+    check(lib().tk_profile_begin(max_launches), "tk_profile_begin")
+
+
+def profile_end():
+    """(total_ms, launches) of the streaming passes timed since profile_begin."""
+    ms = ctypes.c_double(0)
+    n = ctypes.c_uint64(0)
+    check(lib().tk_profile_end(ctypes.byref(ms), ctypes.byref(n)), "tk_profile_end")
+    return ms.value, n.value
+
+
+# ---- CPU route ------------------------------------------------------------------------------
+
+def cpu_topk(keys: np.ndarray, k: int, rowids: np.ndarray | None = None, order="desc",
+             rid_dtype=np.uint32, nthreads: int = 0):
+    """Multithreaded host Top-K (the CPU route of the gate) over numpy arrays."""
+    keys = np.ascontiguousarray(keys)
+    n = keys.shape[0]
+    if rowids is not None:
+        rowids = np.ascontiguousarray(rowids)
+        rid_dtype = rowids.dtype
+    k_eff = min(int(k), n)
+    ok = np.empty(k_eff, dtype=keys.dtype)
+    orr = np.empty(k_eff, dtype=rid_dtype)
+    cnt = ctypes.c_uint64(0)
+    rc = lib().tk_cpu_topk(keys.ctypes.data if n else None,
+                           None if rowids is None else rowids.ctypes.data, n, int(k),
+                           key_code(keys.dtype), rid_code(np.dtype(rid_dtype)), order_code(order),
+                           ok.ctypes.data if k_eff else None, orr.ctypes.data if k_eff else None,
+                           ctypes.byref(cnt), int(nthreads))
+    check(rc, "tk_cpu_topk")
+    return ok, orr

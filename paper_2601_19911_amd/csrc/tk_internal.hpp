@@ -1,0 +1,53 @@
+// Declarations shared between the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "tk_device.hpp"
+#include "tk_plan.hpp"
+
+namespace tk {
+
+// Start of every single-query workspace.  All counters are reset by the first
+// kernel of each query, so the workspace needs no initialization by the caller.
+struct Header {
+  unsigned long long surv_count;  // keys that passed the sampled threshold
+  unsigned long long sel_gt;      // exact select: writes of composites above the boundary
+  unsigned long long sel_eq;      // exact select: writes of copies of the boundary
+  unsigned long long thr_k;       // sampled threshold (key image)
+  unsigned long long thr_f;       // sampled threshold (flipped row-id)
+  uint32_t status;                // device failure bits (1: barrier timeout)
+  uint32_t path;                  // path taken, see tk_info
+  GridSync gs;                    // grid barrier of the tail kernel
+  uint32_t pad[4];
+  unsigned long long hist[3][256];  // exact select: global digit histograms
+};
+static_assert(sizeof(Header) <= HEADER_BYTES, "header must fit its reserved bytes");
+
+inline int device_cus(int dev) {
+  static std::mutex mu;
+  static std::vector<int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (cache[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
+      v = 1;
+    cache[dev] = v;
+  }
+  return cache[dev];
+}
+
+Tuning current_tuning();
+void profile_mark(hipStream_t st, bool begin);
+
+template <int KT, int RT>
+int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, int order,
+               void* out_keys, void* out_rids, void* ws, size_t ws_bytes, hipStream_t st,
+               const Tuning& tun);
+
+}  // namespace tk

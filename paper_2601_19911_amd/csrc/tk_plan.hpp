@@ -1,0 +1,96 @@
+// Host-side planning shared by the single-query and batched paths: sample
+// size, sample rank, survivor capacity and workspace layout.  Pure arithmetic,
+// no HIP calls, so it also builds into the host unit tests.
+#pragma once
+
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tk {
+
+// LDS capacity (elements) of the one-workgroup select/sort stage for a
+// composite of `cb` bytes (key image + row-id): 128 KiB of LDS.
+inline uint32_t lds_cap_for(uint32_t cb) { return cb <= 8 ? 16384u : 8192u; }
+
+constexpr uint32_t SAMPLE_CHUNK = 16;        // contiguous keys per sample chunk
+constexpr uint32_t SAMPLE_PER_BLOCK = 1024;  // sample keys per local-select block
+constexpr uint32_t SAMPLE_FINAL_MAX = 16384; // candidates the final select can hold
+
+struct SamplePlan {
+  bool fast = false;     // sample -> filter -> tail; else exact radix select
+  uint32_t S = 0;        // sample size (multiple of SAMPLE_PER_BLOCK)
+  uint32_t blocks = 0;   // S / SAMPLE_PER_BLOCK
+  uint32_t r1 = 0;       // sample rank (1-based) used as the threshold
+  uint64_t cap = 0;      // survivor capacity
+};
+
+struct Tuning {
+  double sample_sigma = 3.0;   // safety margin on the sample rank, in std devs
+  double cap_sigma = 6.0;      // survivor capacity margin, in std devs
+  uint32_t max_sample_log2 = 20;
+  uint32_t min_sample_log2 = 14;
+  uint32_t filter_grid = 0;    // 0: automatic
+  uint64_t force_cap = 0;      // >0: override the survivor capacity (tests)
+  int force_exact = 0;         // 1: always take the exact radix path (tests)
+};
+
+// Chooses the sample for a query of n keys and k_eff results.  The threshold
+// is the r1-th best of S sampled keys; survivors ~ r1 * n / S.  The sample is
+// as large as allowed while the final select still fits one workgroup.
+inline SamplePlan plan_sample(uint64_t n, uint64_t k_eff, const Tuning& t) {
+  SamplePlan p;
+  if (t.force_exact || k_eff == 0 || n < (1ull << t.min_sample_log2) * 16 || k_eff * 16 > n)
+    return p;
+  for (int lg = (int)t.max_sample_log2; lg >= (int)t.min_sample_log2; --lg) {
+    const uint64_t S = 1ull << lg;
+    if (S * 16 > n) continue;
+    const double m = (double)k_eff * (double)S / (double)n;
+    const uint64_t r1 = (uint64_t)ceil(m + t.sample_sigma * sqrt(m) + 3.0);
+    const uint64_t blocks = S / SAMPLE_PER_BLOCK;
+    if (r1 > 256 || r1 * blocks > SAMPLE_FINAL_MAX) continue;
+    p.fast = true;
+    p.S = (uint32_t)S;
+    p.blocks = (uint32_t)blocks;
+    p.r1 = (uint32_t)r1;
+    const double unit = (double)n / (double)S;
+    double cap = ((double)r1 + t.cap_sigma * sqrt((double)r1) + 12.0) * unit + 4096.0;
+    if ((double)k_eff * 2.0 + 4096.0 > cap) cap = (double)k_eff * 2.0 + 4096.0;
+    if (cap > (double)n) cap = (double)n;
+    p.cap = t.force_cap ? t.force_cap : (uint64_t)cap;
+    return p;
+  }
+  return p;
+}
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr size_t HEADER_BYTES = 8192;
+
+// Byte offsets inside the caller's workspace for one query.
+struct WsLayout {
+  size_t sample = 0;   // sample candidates: blocks * r1 composites
+  size_t surv = 0;     // survivors: cap composites (key image, flipped row-id), SoA
+  size_t cand = 0;     // exact selection: k_eff composites, SoA
+  size_t tmp = 0;      // merge ping-pong: k_eff composites, SoA
+  size_t total = 0;
+};
+
+inline WsLayout ws_layout(uint64_t n, uint64_t k_eff, uint32_t kb, uint32_t rb, const SamplePlan& p) {
+  WsLayout L;
+  size_t off = HEADER_BYTES;
+  L.sample = off;
+  off = align_up(off + (size_t)p.blocks * p.r1 * (kb + rb) + 64, 256);
+  L.surv = off;
+  off = align_up(off + (size_t)p.cap * (kb + rb) + 64, 256);
+  L.cand = off;
+  off = align_up(off + (size_t)k_eff * (kb + rb) + 64, 256);
+  L.tmp = off;
+  const uint32_t cap = lds_cap_for(kb + rb);
+  if (k_eff > cap) off = align_up(off + (size_t)k_eff * (kb + rb) + 64, 256);
+  L.total = off;
+  (void)n;
+  return L;
+}
+
+}  // namespace tk

@@ -1,0 +1,831 @@
+// Single-query key-only Top-K (ordering primitive, paper sec. III-A) for
+// gfx950, plus the shared kernels the batched and served forms reuse.
+//
+// Large queries run four kernels on the caller's stream:
+//   1. k_sample_local  many workgroups read a stratified sample (16-key chunks)
+//                      and keep their local best r1 composites;
+//   2. k_sample_final  one workgroup picks the r1-th best of those: the
+//                      threshold T;
+//   3. k_filter        the one streaming pass over the keys: keys whose
+//                      composite is >= T are appended to a survivor buffer
+//                      (wave ballot + one atomic per wave with survivors);
+//   4. k_tail          cooperative grid.  If K <= survivors <= capacity and
+//                      they fit LDS, one workgroup selects the best K by
+//                      bisection and bitonic-sorts them in LDS.  Otherwise
+//                      every workgroup runs an exact 8-bit-digit radix select
+//                      (over the survivors, or over the whole input when the
+//                      sample misjudged), then the K results are sorted.
+// The sampled threshold only decides how much work the tail has: any
+// threshold with at least K survivors yields the exact answer, and a bad one
+// falls back to the exact select, so the result never depends on the sample.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "mitopk.h"
+#include "tk_device.hpp"
+#include "tk_internal.hpp"
+#include "tk_plan.hpp"
+
+namespace tk {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ---- sources of composites ----------------------------------------------------------------
+
+template <int KT, int RT>
+struct InputSrc {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  const typename Key<KT>::Raw* keys;
+  const R* rids;
+  U dmask;
+  __device__ __forceinline__ U key(uint64_t i) const { return Key<KT>::enc(keys[i]) ^ dmask; }
+  __device__ __forceinline__ R flip(uint64_t i) const { return ~(rids ? rids[i] : (R)i); }
+};
+
+template <typename U, typename R>
+struct BufSrc {
+  const U* k;
+  const R* f;
+  __device__ __forceinline__ U key(uint64_t i) const { return k[i]; }
+  __device__ __forceinline__ R flip(uint64_t i) const { return f[i]; }
+};
+
+// ---- kernel 0: header reset (exact-only path) ----------------------------------------------
+
+__global__ void k_init(Header* h) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(h);
+  for (uint32_t i = threadIdx.x; i < sizeof(Header) / 4; i += blockDim.x) w[i] = 0u;
+}
+
+__device__ __forceinline__ void header_reset_block(Header* h) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(h);
+  for (uint32_t i = threadIdx.x; i < sizeof(Header) / 4; i += blockDim.x) w[i] = 0u;
+}
+
+// ---- kernel 1: local sample select -----------------------------------------------------------
+
+template <int KT, int RT>
+__global__ __launch_bounds__(256) void k_sample_local(const typename Key<KT>::Raw* keys,
+                                                      const typename Rid<RT>::R* rids, uint64_t n,
+                                                      typename Key<KT>::U dmask, uint32_t S,
+                                                      uint32_t r1, Header* h,
+                                                      typename Key<KT>::U* ck,
+                                                      typename Rid<RT>::R* cf) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr int NT = 256, E = 4;
+  __shared__ uint64_t red[2 * NT / 64];
+  __shared__ uint32_t ws[NT / 64];
+  if (blockIdx.x == 0) header_reset_block(h);
+  const InputSrc<KT, RT> src{keys, rids, dmask};
+  const uint64_t nchunks = S / SAMPLE_CHUNK;
+  const uint64_t stride = n / nchunks;  // >= 16 because n >= 16 * S
+  const uint64_t off0 = (stride - SAMPLE_CHUNK) / 2;
+  U k[E];
+  R f[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint64_t j = (uint64_t)blockIdx.x * SAMPLE_PER_BLOCK + (uint64_t)e * NT + threadIdx.x;
+    const uint64_t pos = (j / SAMPLE_CHUNK) * stride + off0 + (j % SAMPLE_CHUNK);
+    k[e] = src.key(pos);
+    f[e] = src.flip(pos);
+  }
+  int parity = 0;
+  U Tk;
+  R Tf;
+  block_select<U, R, E, NT>(k, f, E, r1, Tk, Tf, red, parity);
+  block_emit_top<U, R, E, NT>(k, f, E, r1, Tk, Tf, ck + (uint64_t)blockIdx.x * r1,
+                              cf + (uint64_t)blockIdx.x * r1, ws);
+}
+
+// ---- kernel 2: final sample select -----------------------------------------------------------
+
+template <int KT, int RT>
+__global__ __launch_bounds__(1024) void k_sample_final(Header* h, const typename Key<KT>::U* ck,
+                                                       const typename Rid<RT>::R* cf, uint32_t m,
+                                                       uint32_t r1) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr int NT = 1024, E = SAMPLE_FINAL_MAX / NT;
+  __shared__ uint64_t red[2 * NT / 64];
+  U k[E];
+  R f[E];
+  int nv = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t j = (uint32_t)e * NT + threadIdx.x;
+    if (j < m) {
+      k[e] = ck[j];
+      f[e] = cf[j];
+      nv = e + 1;
+    } else {
+      k[e] = 0;
+      f[e] = 0;
+    }
+  }
+  int parity = 0;
+  U Tk;
+  R Tf;
+  block_select<U, R, E, NT>(k, f, nv, r1, Tk, Tf, red, parity);
+  if (threadIdx.x == 0) {
+    h->thr_k = (uint64_t)Tk;
+    h->thr_f = (uint64_t)Tf;
+  }
+}
+
+// ---- kernel 3: streaming filter ----------------------------------------------------------------
+
+template <typename U, typename R>
+__device__ __forceinline__ void emit_survivor(bool pass, U kk, R ff, Header* h, U* sk, R* sf,
+                                              uint64_t cap) {
+  const uint64_t m = ballot(pass);
+  if (m == 0) return;
+  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+  uint64_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(&h->surv_count, (unsigned long long)__popcll(m));
+  base = __shfl(base, (int)leader, 64);
+  if (pass) {
+    const uint64_t pos = base + lanes_below(m);
+    if (pos < cap) {
+      sk[pos] = kk;
+      sf[pos] = ff;
+    }
+  }
+}
+
+template <int KT, int RT, int VEC, int UNR>
+__global__ __launch_bounds__(256) void k_filter(const typename Key<KT>::Raw* keys,
+                                                const typename Rid<RT>::R* rids, uint64_t n,
+                                                typename Key<KT>::U dmask, Header* h,
+                                                typename Key<KT>::U* sk, typename Rid<RT>::R* sf,
+                                                uint64_t cap) {
+  using Raw = typename Key<KT>::Raw;
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr int NT = 256;
+  static_assert(VEC * sizeof(Raw) == 16 || VEC == 1, "vector loads are 16 bytes");
+  const U Tk = (U)h->thr_k;
+  const R Tf = (R)h->thr_f;
+  const InputSrc<KT, RT> src{keys, rids, dmask};
+  constexpr uint64_t TILE = (uint64_t)NT * VEC * UNR;
+  const uint64_t ntiles = n / TILE;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t base = t * TILE;
+    Raw v[UNR][VEC];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const uint64_t i0 = base + ((uint64_t)u * NT + threadIdx.x) * VEC;
+      if constexpr (VEC * sizeof(Raw) == 16) {
+        const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(keys + i0));
+        if constexpr (sizeof(Raw) == 4) {
+          v[u][0] = q.x; v[u][1] = q.y; v[u][2] = q.z; v[u][3] = q.w;
+        } else {
+          v[u][0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+          v[u][1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
+        }
+      } else {
+        v[u][0] = keys[i0];
+      }
+    }
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) any |= (Key<KT>::enc(v[u][e]) ^ dmask) >= Tk;
+    if (ballot(any) == 0) continue;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const uint64_t i = base + ((uint64_t)u * NT + threadIdx.x) * VEC + e;
+        const U kk = Key<KT>::enc(v[u][e]) ^ dmask;
+        bool pass = kk > Tk;
+        R ff = 0;
+        if (kk >= Tk) {
+          ff = src.flip(i);
+          pass = pass || ff >= Tf;
+        }
+        emit_survivor<U, R>(pass, kk, ff, h, sk, sf, cap);
+      }
+  }
+  // remainder (fewer than one tile)
+  const uint64_t stride = (uint64_t)gridDim.x * NT;
+  for (uint64_t i = ntiles * TILE + (uint64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+    const U kk = src.key(i);
+    bool pass = kk > Tk;
+    R ff = 0;
+    if (kk >= Tk) {
+      ff = src.flip(i);
+      pass = pass || ff >= Tf;
+    }
+    emit_survivor<U, R>(pass, kk, ff, h, sk, sf, cap);
+  }
+}
+
+// ---- one-workgroup select + sort in LDS ------------------------------------------------------
+
+template <int KT, int RT>
+struct LdsTile {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  static constexpr uint32_t CAP = (sizeof(U) + sizeof(R)) <= 8 ? 16384u : 8192u;
+  U k[CAP];
+  R f[CAP];
+};
+
+template <int KT, int RT>
+__device__ __forceinline__ void write_out(uint64_t j, typename Key<KT>::U kk,
+                                          typename Rid<RT>::R ff, typename Key<KT>::U dmask,
+                                          void* out_keys, void* out_rids) {
+  if (out_keys) static_cast<typename Key<KT>::Raw*>(out_keys)[j] = Key<KT>::dec(kk ^ dmask);
+  if (out_rids) static_cast<typename Rid<RT>::R*>(out_rids)[j] = ~ff;
+}
+
+// Selects the best k_eff of cnt (<= CAP) composites from `src` and writes them
+// sorted to the outputs.  Whole workgroup of NT threads.
+template <int KT, int RT, int NT, typename Src>
+__device__ void lds_select_sort(const Src& src, uint32_t cnt, uint32_t k_eff,
+                                typename Key<KT>::U dmask, void* out_keys, void* out_rids,
+                                LdsTile<KT, RT>& t, uint64_t* red, uint32_t* ws) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
+  constexpr int E = CAP / NT;
+  U k[E];
+  R f[E];
+  int nv = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t j = (uint32_t)e * NT + threadIdx.x;
+    if (j < cnt) {
+      k[e] = src.key(j);
+      f[e] = src.flip(j);
+      nv = e + 1;
+    } else {
+      k[e] = 0;
+      f[e] = 0;
+    }
+  }
+  int parity = 0;
+  U Tk;
+  R Tf;
+  block_select<U, R, E, NT>(k, f, nv, k_eff, Tk, Tf, red, parity);
+  block_emit_top<U, R, E, NT>(k, f, nv, k_eff, Tk, Tf, t.k, t.f, ws);
+  uint32_t P = 1;
+  while (P < k_eff) P <<= 1;
+  for (uint32_t i = k_eff + threadIdx.x; i < P; i += NT) {
+    t.k[i] = 0;
+    t.f[i] = 0;
+  }
+  bitonic_desc<U, R, NT>(t.k, t.f, P);
+  for (uint32_t j = threadIdx.x; j < k_eff; j += NT) write_out<KT, RT>(j, t.k[j], t.f[j], dmask, out_keys, out_rids);
+}
+
+// ---- kernel: whole query in one workgroup (n <= LDS capacity) -------------------------------
+
+template <int KT, int RT>
+__global__ __launch_bounds__(1024) void k_small(const typename Key<KT>::Raw* keys,
+                                                const typename Rid<RT>::R* rids, uint32_t n,
+                                                uint32_t k_eff, typename Key<KT>::U dmask,
+                                                void* out_keys, void* out_rids) {
+  constexpr int NT = 1024;
+  __shared__ LdsTile<KT, RT> t;
+  __shared__ uint64_t red[2 * NT / 64];
+  __shared__ uint32_t ws[NT / 64];
+  const InputSrc<KT, RT> src{keys, rids, dmask};
+  lds_select_sort<KT, RT, NT>(src, n, k_eff, dmask, out_keys, out_rids, t, red, ws);
+}
+
+// ---- kernel 4: tail (cooperative) -----------------------------------------------------------
+
+struct TailArgs {
+  const void* keys;
+  const void* rids;
+  uint64_t n;
+  uint64_t dmask;
+  Header* h;
+  void* sk;
+  void* sf;
+  uint64_t cap;
+  void* ck;
+  void* cf;
+  void* tk;
+  void* tf;
+  uint64_t k_eff;
+  void* out_keys;
+  void* out_rids;
+  int exact_only;
+};
+
+template <typename U, typename R>
+struct SelState {
+  U Pk;
+  R Pf;
+  uint64_t need;  // elements still to take from the boundary bucket
+  int dup;        // 1: all bits resolved, `need` copies of (Pk, Pf) are taken
+};
+
+// Exact radix select over src[0..n) by all blocks: 8-bit digits of the key
+// image from the top, then of the flipped row-id, each digit found from a
+// global histogram.  Writes exactly k_eff composites to (ck, cf), unsorted.
+// Returns false if a grid barrier failed.
+template <int NT, typename U, typename R, typename Src>
+__device__ bool exact_select(const Src& src, uint64_t n, uint64_t k_eff, Header* h, U* ck, R* cf,
+                             uint32_t* lh, unsigned long long* lh64, uint32_t* sh_u32,
+                             int* s_flag) {
+  const uint32_t G = gridDim.x;
+  const uint64_t lo = n * blockIdx.x / G, hi = n * (blockIdx.x + 1) / G;
+  constexpr int WU = (int)sizeof(U) * 8, WR = (int)sizeof(R) * 8;
+  U Pk = 0, mk = 0;
+  R Pf = 0, mf = 0;
+  uint64_t need = k_eff;
+  bool rid_phase = false;
+  int shift = WU - 8;
+  int dup = 0;
+  for (int pass = 0;; ++pass) {
+    for (uint32_t d = threadIdx.x; d < 256; d += NT) lh[d] = 0;
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += NT) {
+      const U u = src.key(i);
+      if (!rid_phase) {
+        if ((u & mk) == Pk) atomicAdd(&lh[(uint32_t)(u >> shift) & 0xFFu], 1u);
+      } else if (u == Pk) {
+        const R f = src.flip(i);
+        if ((f & mf) == Pf) atomicAdd(&lh[(uint32_t)(f >> shift) & 0xFFu], 1u);
+      }
+    }
+    __syncthreads();
+    unsigned long long* gh = h->hist[pass % 3];
+    for (uint32_t d = threadIdx.x; d < 256; d += NT)
+      if (lh[d]) atomicAdd(&gh[d], (unsigned long long)lh[d]);
+    if (!grid_sync(&h->gs, G, &h->status, s_flag)) return false;
+    if (blockIdx.x == 0) {
+      unsigned long long* old = h->hist[(pass + 2) % 3];
+      for (uint32_t d = threadIdx.x; d < 256; d += NT) old[d] = 0;
+    }
+    for (uint32_t d = threadIdx.x; d < 256; d += NT)
+      lh64[d] = __hip_atomic_load(&gh[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t cum = 0;
+      int d = 255;
+      for (; d > 0; --d) {
+        if (cum + lh64[d] >= need) break;
+        cum += lh64[d];
+      }
+      sh_u32[0] = (uint32_t)d;
+      sh_u32[1] = (uint32_t)cum;
+      sh_u32[2] = (uint32_t)(cum >> 32);
+    }
+    __syncthreads();
+    const uint32_t d = sh_u32[0];
+    const uint64_t above = (uint64_t)sh_u32[1] | ((uint64_t)sh_u32[2] << 32);
+    const uint64_t bucket = lh64[d];
+    __syncthreads();
+    need -= above;
+    if (!rid_phase) {
+      Pk |= (U)d << shift;
+      mk |= (U)0xFF << shift;
+    } else {
+      Pf |= (R)d << shift;
+      mf |= (R)0xFF << shift;
+    }
+    if (bucket == need) break;  // the whole bucket is taken: boundary resolved
+    if (shift == 0) {
+      if (!rid_phase) {
+        rid_phase = true;
+        shift = WR - 8;
+      } else {
+        dup = 1;  // identical composites straddle the boundary
+        break;
+      }
+    } else {
+      shift -= 8;
+    }
+  }
+  // compaction: c > B (or >= B when resolved) to the front, copies of B after
+  const uint64_t n_gt = k_eff - need;
+  const uint64_t gt_end = dup ? n_gt : k_eff;
+  for (uint64_t i0 = lo; i0 < hi; i0 += NT) {
+    const uint64_t i = i0 + threadIdx.x;
+    bool take = false, eq = false;
+    U u = 0;
+    R f = 0;
+    if (i < hi) {
+      u = src.key(i);
+      if (u >= Pk) {
+        f = src.flip(i);
+        if (dup) {
+          take = cgt(u, f, Pk, Pf);
+          eq = (u == Pk && f == Pf);
+        } else {
+          take = cge(u, f, Pk, Pf);
+        }
+      }
+    }
+    const uint64_t mt = ballot(take);
+    if (mt) {
+      const uint32_t leader = (uint32_t)__builtin_ctzll(mt);
+      uint64_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(&h->sel_gt, (unsigned long long)__popcll(mt));
+      base = __shfl(base, (int)leader, 64);
+      if (take) {
+        const uint64_t pos = base + lanes_below(mt);
+        if (pos < gt_end) {
+          ck[pos] = u;
+          cf[pos] = f;
+        }
+      }
+    }
+    const uint64_t me = ballot(eq);
+    if (me) {
+      const uint32_t leader = (uint32_t)__builtin_ctzll(me);
+      uint64_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(&h->sel_eq, (unsigned long long)__popcll(me));
+      base = __shfl(base, (int)leader, 64);
+      if (eq) {
+        const uint64_t pos = n_gt + base + lanes_below(me);
+        if (pos < k_eff) {
+          ck[pos] = u;
+          cf[pos] = f;
+        }
+      }
+    }
+  }
+  return grid_sync(&h->gs, G, &h->status, s_flag);
+}
+
+// merge-path split: number of elements of A among the first d outputs of
+// merge(A, B), best first, ties taken from A
+template <typename U, typename R>
+__device__ __forceinline__ uint64_t merge_split(const U* ak, const R* af, uint64_t na, const U* bk,
+                                                const R* bf, uint64_t nb, uint64_t d) {
+  uint64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) / 2;
+    if (cge(ak[mid], af[mid], bk[d - 1 - mid], bf[d - 1 - mid])) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Sorts ck/cf[0..m) best first with all blocks and writes the outputs.
+template <int KT, int RT, int NT>
+__device__ bool sort_and_write(uint64_t m, typename Key<KT>::U* ck, typename Rid<RT>::R* cf,
+                               typename Key<KT>::U* tk, typename Rid<RT>::R* tf,
+                               typename Key<KT>::U dmask, void* out_keys, void* out_rids,
+                               Header* h, LdsTile<KT, RT>& t, int* s_flag) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
+  const uint32_t G = gridDim.x;
+  if (m <= CAP) {
+    if (blockIdx.x != 0) return true;
+    uint32_t P = 1;
+    while (P < m) P <<= 1;
+    for (uint32_t i = threadIdx.x; i < P; i += NT) {
+      t.k[i] = i < m ? ck[i] : (U)0;
+      t.f[i] = i < m ? cf[i] : (R)0;
+    }
+    bitonic_desc<U, R, NT>(t.k, t.f, P);
+    for (uint32_t j = threadIdx.x; j < m; j += NT) write_out<KT, RT>(j, t.k[j], t.f[j], dmask, out_keys, out_rids);
+    return true;
+  }
+  // 1) sort tiles of CAP in LDS
+  const uint64_t ntiles = (m + CAP - 1) / CAP;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += G) {
+    const uint64_t base = tile * CAP;
+    const uint64_t len = m - base < CAP ? m - base : CAP;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < CAP; i += NT) {
+      t.k[i] = i < len ? ck[base + i] : (U)0;
+      t.f[i] = i < len ? cf[base + i] : (R)0;
+    }
+    bitonic_desc<U, R, NT>(t.k, t.f, CAP);
+    for (uint32_t i = threadIdx.x; i < len; i += NT) {
+      ck[base + i] = t.k[i];
+      cf[base + i] = t.f[i];
+    }
+  }
+  if (!grid_sync(&h->gs, G, &h->status, s_flag)) return false;
+  // 2) merge runs pairwise until one run is left
+  U* sk = ck;
+  R* sf = cf;
+  U* dk = tk;
+  R* df = tf;
+  constexpr uint64_t ITEMS = 8;
+  for (uint64_t run = CAP; run < m; run <<= 1) {
+    for (uint64_t o0 = ((uint64_t)blockIdx.x * NT + threadIdx.x) * ITEMS; o0 < m;
+         o0 += (uint64_t)G * NT * ITEMS) {
+      const uint64_t s = o0 / (2 * run) * (2 * run);
+      const uint64_t amid = s + run < m ? s + run : m;
+      const uint64_t aend = s + 2 * run < m ? s + 2 * run : m;
+      const uint64_t na = amid - s, nb = aend - amid;
+      const uint64_t d = o0 - s;
+      uint64_t i = merge_split<U, R>(sk + s, sf + s, na, sk + amid, sf + amid, nb, d);
+      uint64_t j = d - i;
+      const uint64_t cnt = aend - o0 < ITEMS ? aend - o0 : ITEMS;
+      for (uint64_t q = 0; q < cnt; ++q) {
+        bool from_a;
+        if (i >= na) from_a = false;
+        else if (j >= nb) from_a = true;
+        else from_a = cge(sk[s + i], sf[s + i], sk[amid + j], sf[amid + j]);
+        if (from_a) {
+          dk[o0 + q] = sk[s + i];
+          df[o0 + q] = sf[s + i];
+          ++i;
+        } else {
+          dk[o0 + q] = sk[amid + j];
+          df[o0 + q] = sf[amid + j];
+          ++j;
+        }
+      }
+    }
+    if (!grid_sync(&h->gs, G, &h->status, s_flag)) return false;
+    U* xk = sk; sk = dk; dk = xk;
+    R* xf = sf; sf = df; df = xf;
+  }
+  for (uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x; j < m; j += (uint64_t)G * NT)
+    write_out<KT, RT>(j, sk[j], sf[j], dmask, out_keys, out_rids);
+  return true;
+}
+
+template <int KT, int RT>
+__global__ __launch_bounds__(1024) void k_tail(TailArgs a) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr int NT = 1024;
+  __shared__ LdsTile<KT, RT> t;
+  __shared__ uint64_t red[2 * NT / 64];
+  __shared__ uint32_t ws[NT / 64];
+  __shared__ uint32_t lh[256];
+  __shared__ unsigned long long lh64[256];
+  __shared__ uint32_t sh_u32[4];
+  __shared__ int s_flag;
+  Header* h = a.h;
+  const U dmask = (U)a.dmask;
+  const uint64_t C = h->surv_count;
+  int path;
+  if (a.exact_only) path = 5;
+  else if (C < a.k_eff || C > a.cap) path = 4;
+  else if (C <= LdsTile<KT, RT>::CAP) path = 2;
+  else path = 3;
+  if (blockIdx.x == 0 && threadIdx.x == 0) h->path = (uint32_t)path;
+  if (path == 2) {
+    if (blockIdx.x != 0) return;
+    const BufSrc<U, R> src{(const U*)a.sk, (const R*)a.sf};
+    lds_select_sort<KT, RT, NT>(src, (uint32_t)C, (uint32_t)a.k_eff, dmask, a.out_keys, a.out_rids,
+                                t, red, ws);
+    return;
+  }
+  bool ok;
+  if (path == 3) {
+    const BufSrc<U, R> src{(const U*)a.sk, (const R*)a.sf};
+    ok = exact_select<NT, U, R>(src, C, a.k_eff, h, (U*)a.ck, (R*)a.cf, lh, lh64, sh_u32, &s_flag);
+  } else {
+    const InputSrc<KT, RT> src{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, dmask};
+    ok = exact_select<NT, U, R>(src, a.n, a.k_eff, h, (U*)a.ck, (R*)a.cf, lh, lh64, sh_u32, &s_flag);
+  }
+  if (!ok) return;
+  sort_and_write<KT, RT, NT>(a.k_eff, (U*)a.ck, (R*)a.cf, (U*)a.tk, (R*)a.tf, dmask, a.out_keys,
+                             a.out_rids, h, t, &s_flag);
+}
+
+// ---- host side -------------------------------------------------------------------------------
+
+namespace {
+
+std::mutex g_mu;
+Tuning g_tuning;
+
+// Event pairs around the streaming pass, recorded while profiling is on.
+struct Profile {
+  std::mutex mu;
+  bool on = false;
+  uint32_t max = 0;
+  std::vector<hipEvent_t> ev;  // 2 per launch
+  uint32_t used = 0;
+} g_prof;
+
+template <typename T>
+T* ws_ptr(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+template <int KT, int RT>
+int coop_grid_tail(int dev) {
+  static std::mutex mu;
+  static std::vector<int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (cache[dev] == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_tail<KT, RT>, 1024, 0) !=
+            hipSuccess ||
+        nb < 1)
+      nb = 1;
+    cache[dev] = nb * device_cus(dev);
+  }
+  return cache[dev];
+}
+
+}  // namespace
+
+// Records the start (begin=true) or end of a profiled kernel on `st`.
+void profile_mark(hipStream_t st, bool begin) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (!g_prof.on) return;
+  if (begin && g_prof.used + 2 > g_prof.ev.size()) return;
+  const uint32_t slot = begin ? g_prof.used : g_prof.used + 1;
+  if (!begin && slot >= g_prof.ev.size()) return;
+  hipEventRecord(g_prof.ev[slot], st);
+  if (!begin) g_prof.used += 2;
+}
+
+int profile_begin(uint32_t max_launches) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (auto e : g_prof.ev) hipEventDestroy(e);
+  g_prof.ev.assign(2 * (size_t)max_launches, nullptr);
+  for (auto& e : g_prof.ev)
+    if (hipEventCreate(&e) != hipSuccess) return TK_EHIP;
+  g_prof.used = 0;
+  g_prof.max = max_launches;
+  g_prof.on = true;
+  return TK_OK;
+}
+
+int profile_end(double* total_ms, uint64_t* launches) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = false;
+  double tot = 0;
+  for (uint32_t i = 0; i + 1 < g_prof.used; i += 2) {
+    if (hipEventSynchronize(g_prof.ev[i + 1]) != hipSuccess) return TK_EHIP;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, g_prof.ev[i], g_prof.ev[i + 1]) != hipSuccess) return TK_EHIP;
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = g_prof.used / 2;
+  return TK_OK;
+}
+
+Tuning current_tuning() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_tuning;
+}
+
+void set_tuning(const tk_tuning* t) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (t->sample_sigma > 0) g_tuning.sample_sigma = t->sample_sigma;
+  if (t->cap_sigma > 0) g_tuning.cap_sigma = t->cap_sigma;
+  if (t->max_sample_log2 > 0) g_tuning.max_sample_log2 = (uint32_t)t->max_sample_log2;
+  if (t->filter_grid > 0) g_tuning.filter_grid = (uint32_t)t->filter_grid;
+  if (t->force_cap > 0) g_tuning.force_cap = (uint64_t)t->force_cap;
+  if (t->force_cap < 0) g_tuning.force_cap = 0;
+  if (t->force_exact == 1) g_tuning.force_exact = 1;
+  if (t->force_exact == 2) g_tuning.force_exact = 0;
+}
+
+size_t single_ws_bytes(uint64_t n, uint64_t k_eff, uint32_t kb, uint32_t rb, const Tuning& t) {
+  const SamplePlan p = plan_sample(n, k_eff, t);
+  return ws_layout(n, k_eff, kb, rb, p).total;
+}
+
+template <int KT, int RT>
+int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, int order,
+               void* out_keys, void* out_rids, void* ws, size_t ws_bytes, hipStream_t st,
+               const Tuning& tun) {
+  using Raw = typename Key<KT>::Raw;
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  const U dmask = order == TK_ASC ? (U)~(U)0 : (U)0;
+  constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
+  if (n <= CAP && !tun.force_exact) {
+    hipLaunchKernelGGL((k_small<KT, RT>), dim3(1), dim3(1024), 0, st, (const Raw*)keys,
+                       (const R*)rids, (uint32_t)n, (uint32_t)k_eff, dmask, out_keys, out_rids);
+    return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
+  }
+  const SamplePlan p = plan_sample(n, k_eff, tun);
+  const WsLayout L = ws_layout(n, k_eff, sizeof(U), sizeof(R), p);
+  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return TK_EINVAL;
+  Header* h = ws_ptr<Header>(ws, 0);
+  U* sample_k = ws_ptr<U>(ws, L.sample);
+  R* sample_f = ws_ptr<R>(ws, L.sample + align_up((size_t)p.blocks * p.r1 * sizeof(U), 16));
+  U* surv_k = ws_ptr<U>(ws, L.surv);
+  R* surv_f = ws_ptr<R>(ws, L.surv + align_up((size_t)p.cap * sizeof(U), 16));
+  U* cand_k = ws_ptr<U>(ws, L.cand);
+  R* cand_f = ws_ptr<R>(ws, L.cand + align_up((size_t)k_eff * sizeof(U), 16));
+  U* tmp_k = ws_ptr<U>(ws, L.tmp);
+  R* tmp_f = ws_ptr<R>(ws, L.tmp + align_up((size_t)k_eff * sizeof(U), 16));
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TK_EHIP;
+  if (p.fast) {
+    hipLaunchKernelGGL((k_sample_local<KT, RT>), dim3(p.blocks), dim3(256), 0, st, (const Raw*)keys,
+                       (const R*)rids, n, dmask, p.S, p.r1, h, sample_k, sample_f);
+    hipLaunchKernelGGL((k_sample_final<KT, RT>), dim3(1), dim3(1024), 0, st, h,
+                       (const U*)sample_k, (const R*)sample_f, p.blocks * p.r1, p.r1);
+    const uint32_t grid = tun.filter_grid ? tun.filter_grid : (uint32_t)device_cus(dev) * 8u;
+    profile_mark(st, true);
+    if (((uintptr_t)keys & 15u) == 0) {
+      constexpr int VEC = 16 / sizeof(Raw);
+      hipLaunchKernelGGL((k_filter<KT, RT, VEC, 4>), dim3(grid), dim3(256), 0, st, (const Raw*)keys,
+                         (const R*)rids, n, dmask, h, surv_k, surv_f, p.cap);
+    } else {
+      hipLaunchKernelGGL((k_filter<KT, RT, 1, 8>), dim3(grid), dim3(256), 0, st, (const Raw*)keys,
+                         (const R*)rids, n, dmask, h, surv_k, surv_f, p.cap);
+    }
+    profile_mark(st, false);
+  } else {
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, h);
+  }
+  if (hipGetLastError() != hipSuccess) return TK_EHIP;
+  TailArgs a{keys, rids, n, (uint64_t)dmask, h, surv_k, surv_f, p.cap, cand_k, cand_f,
+             tmp_k, tmp_f, k_eff, out_keys, out_rids, p.fast ? 0 : 1};
+  void* args[] = {&a};
+  const int grid = coop_grid_tail<KT, RT>(dev);
+  if (hipLaunchCooperativeKernel((const void*)k_tail<KT, RT>, dim3(grid), dim3(1024), args, 0, st) !=
+      hipSuccess)
+    return TK_EHIP;
+  return TK_OK;
+}
+
+template int run_single<KEY_I32, RID_U32>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
+template int run_single<KEY_I32, RID_U64>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
+template int run_single<KEY_F32, RID_U32>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
+template int run_single<KEY_F32, RID_U64>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
+template int run_single<KEY_I64, RID_U32>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
+template int run_single<KEY_I64, RID_U64>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
+
+}  // namespace tk
+
+// ---- C ABI -----------------------------------------------------------------------------------
+
+using namespace tk;
+
+extern "C" size_t tk_workspace_size(uint64_t n, uint64_t k, int key_type, int rid_type) {
+  const uint64_t k_eff = k < n ? k : n;
+  const uint32_t kb = key_type == TK_KEY_I64 ? 8 : 4, rb = rid_type == TK_RID_U64 ? 8 : 4;
+  return single_ws_bytes(n, k_eff, kb, rb, current_tuning());
+}
+
+extern "C" int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int key_type,
+                       int rid_type, int order, void* out_keys, void* out_rowids,
+                       uint64_t* out_count, void* workspace, size_t workspace_bytes, void* stream) {
+  if (key_type < 0 || key_type > 2 || rid_type < 0 || rid_type > 1 || order < 0 || order > 1)
+    return TK_EINVAL;
+  const uint64_t k_eff = k < n ? k : n;
+  if (n > 0 && !keys) return TK_EINVAL;
+  if (!rowids && rid_type == TK_RID_U32 && n > (1ull << 32)) return TK_EINVAL;
+  if (n >= (1ull << 40)) return TK_EUNSUPPORTED;
+  if (out_count) *out_count = k_eff;
+  if (k_eff == 0) return TK_OK;
+  const Tuning t = current_tuning();
+  hipStream_t st = (hipStream_t)stream;
+#define TK_RUN(KT, RT) \
+  return run_single<KT, RT>(keys, rowids, n, k_eff, order, out_keys, out_rowids, workspace, workspace_bytes, st, t)
+  if (key_type == TK_KEY_I32) { if (rid_type == TK_RID_U32) TK_RUN(KEY_I32, RID_U32); TK_RUN(KEY_I32, RID_U64); }
+  if (key_type == TK_KEY_F32) { if (rid_type == TK_RID_U32) TK_RUN(KEY_F32, RID_U32); TK_RUN(KEY_F32, RID_U64); }
+  if (rid_type == TK_RID_U32) TK_RUN(KEY_I64, RID_U32);
+  TK_RUN(KEY_I64, RID_U64);
+#undef TK_RUN
+}
+
+extern "C" int tk_query_info(const void* workspace, tk_info* info) {
+  if (!workspace || !info) return TK_EINVAL;
+  Header h;
+  if (hipMemcpy(&h, workspace, sizeof(Header), hipMemcpyDeviceToHost) != hipSuccess) return TK_EHIP;
+  info->path = h.path;
+  info->status = h.status;
+  info->survivors = h.surv_count;
+  info->threshold_key = h.thr_k;
+  return h.status ? TK_EDEVICE : TK_OK;
+}
+
+extern "C" int tk_set_tuning(const tk_tuning* t) {
+  if (!t) return TK_EINVAL;
+  set_tuning(t);
+  return TK_OK;
+}
+
+extern "C" int tk_profile_begin(uint32_t max_launches) { return profile_begin(max_launches); }
+
+extern "C" int tk_profile_end(double* total_ms, uint64_t* launches) {
+  return profile_end(total_ms, launches);
+}
+
+extern "C" const char* tk_status_string(int s) {
+  switch (s) {
+    case TK_OK: return "ok";
+    case TK_EINVAL: return "invalid argument";
+    case TK_ENOMEM: return "out of host memory";
+    case TK_EHIP: return "HIP runtime error";
+    case TK_EUNSUPPORTED: return "unsupported device or size";
+    case TK_EDEVICE: return "device-side failure";
+    case TK_EAGAIN: return "not finished";
+    default: return "unknown status";
+  }
+}

@@ -1,0 +1,72 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry
+point its headers declare, and rejects bad arguments before touching the
+device."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2601_19911_amd as tk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(tk_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("tk_topk", "tk_workspace_size", "tk_query_info", "tk_cpu_topk", "tk_status_string"):
+        assert must in names
+
+
+@pytest.mark.parametrize("name", declared_functions())
+def test_library_exports(name):
+    L = ctypes.CDLL(tk.LIB_PATH)
+    assert hasattr(L, name), f"{name} declared in include/ but not exported"
+
+
+def test_status_strings():
+    L = tk.lib()
+    for code in (0, -1, -2, -3, -4, -5, 1):
+        assert len(L.tk_status_string(code)) > 0
+
+
+def test_argument_errors_before_device_work():
+    L = tk.lib()
+    cnt = ctypes.c_uint64(99)
+    # bad key type, bad row-id type, bad order
+    assert L.tk_topk(None, None, 0, 1, 7, 0, 0, None, None, ctypes.byref(cnt), None, 0, None) == -1
+    assert L.tk_topk(None, None, 0, 1, 0, 5, 0, None, None, ctypes.byref(cnt), None, 0, None) == -1
+    assert L.tk_topk(None, None, 0, 1, 0, 0, 3, None, None, ctypes.byref(cnt), None, 0, None) == -1
+    # null keys with n > 0
+    assert L.tk_topk(None, None, 10, 1, 0, 0, 0, None, None, ctypes.byref(cnt), None, 0, None) == -1
+    # n = 0 and k = 0 are valid and enqueue nothing
+    assert L.tk_topk(None, None, 0, 5, 0, 0, 0, None, None, ctypes.byref(cnt), None, 0, None) == 0
+    assert cnt.value == 0
+    assert L.tk_topk(ctypes.c_void_p(16), None, 100, 0, 0, 0, 0, None, None, ctypes.byref(cnt),
+                     None, 0, None) == 0
+    assert cnt.value == 0
+    # implicit uint32 row-ids cannot index more than 2^32 keys
+    assert L.tk_topk(ctypes.c_void_p(16), None, (1 << 32) + 1, 5, 0, 0, 0, None, None,
+                     ctypes.byref(cnt), None, 0, None) == -1
+
+
+def test_workspace_size_is_pure_arithmetic():
+    for (n, k) in [(0, 0), (1, 1), (1 << 20, 100), (1 << 28, 1000), (1 << 28, 100000), (1 << 24, 1 << 23)]:
+        for kt in (0, 1, 2):
+            for rt in (0, 1):
+                s = tk.workspace_size(n, k, kt, rt)
+                assert s >= 8192 and s % 256 == 0
+    # grows with k
+    assert tk.workspace_size(1 << 28, 100000, 2, 0) > tk.workspace_size(1 << 28, 1000, 2, 0)

@@ -1,0 +1,189 @@
+"""Parity of the single-query HIP path (tk_topk) with the CPU oracle.
+
+Every case runs the library through its C ABI on the GPU and compares keys
+and row-ids bit for bit with the oracle on the same seeded input, at sizes
+that span several tiles, ragged tails, all three key types, both row-id
+widths, implicit row-ids, both orders, every execution path (one workgroup,
+sample+filter+LDS tail, exact select on survivors, forced fallback, exact
+select over the input) and the tie-heavy and special-value inputs.
+"""
+import numpy as np
+import pytest
+
+import inputgen
+import oracle
+from tests.gpu_util import assert_same, order_code, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+import paper_2601_19911_amd as tk
+
+KINDS = {"int32": inputgen.KIND_U_I32, "float32": inputgen.KIND_U_F32, "int64": inputgen.KIND_U_I64}
+
+
+def run(keys, rids, k, order, rid_dtype=np.uint32, workspace=None, offset=0):
+    import torch
+    say(f"case n={len(keys)} dtype={keys.dtype} k={k} order={order} "
+        f"rids={'none' if rids is None else rids.dtype} offset={offset}")
+    kd = to_dev(keys)
+    if offset:
+        base = to_dev(np.concatenate([np.zeros(offset, dtype=keys.dtype), keys]))
+        kd = base[offset:]
+    rd = None if rids is None else to_dev(rids)
+    tdt = torch.uint32 if np.dtype(rid_dtype) == np.uint32 else torch.uint64
+    ok, orr = tk.topk(kd, k, rowids=rd, order=order, rid_dtype=tdt, workspace=workspace)
+    torch.cuda.synchronize()
+    got = (to_np(ok), to_np(orr))
+    exp = oracle.topk(keys, rids, k, order_code(order), rid_dtype=rid_dtype)
+    assert_same(got[0], got[1], exp[0], exp[1], what=f"n={len(keys)} k={k} {order}")
+    return got
+
+
+def test_config_c1_uniform_int32():
+    """N = 2^20 int32 uniform in [0, 2^31), row-ids 0..N-1, K = 100."""
+    n = 1 << 20
+    keys = inputgen.generate(inputgen.KIND_U_I32, inputgen.config_seed(1), n)
+    rids = np.arange(n, dtype=np.uint32)
+    for order in ("desc", "asc"):
+        run(keys, rids, 100, order)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "float32", "int64"])
+@pytest.mark.parametrize("n", [1, 777, 16384, 16385, 100_003, (1 << 18) + 1, (1 << 20) + 7])
+@pytest.mark.parametrize("k", [1, 100, 1000, 5000])
+def test_sweep(dtype, n, k):
+    keys = inputgen.generate(KINDS[dtype], 1000 + n, n)
+    rids = np.random.default_rng(n).permutation(n).astype(np.uint32)
+    run(keys, rids, k, "desc")
+    run(keys, None, k, "asc")
+
+
+@pytest.mark.parametrize("dtype", ["int32", "float32", "int64"])
+def test_u64_rowids(dtype):
+    n = (1 << 20) + 3
+    keys = inputgen.generate(KINDS[dtype], 5, n)
+    rids = (np.random.default_rng(1).permutation(n).astype(np.uint64) << np.uint64(20)) + np.uint64(7)
+    for order in ("desc", "asc"):
+        run(keys, rids, 1000, order, rid_dtype=np.uint64)
+    run(keys, None, 1000, "desc", rid_dtype=np.uint64)
+
+
+def test_all_equal_keys():
+    n = 1 << 20
+    keys = np.full(n, 5, dtype=np.int32)
+    rids = np.random.default_rng(2).permutation(n).astype(np.uint32)
+    for k in (1, 1000, 20000):
+        for order in ("desc", "asc"):
+            run(keys, rids, k, order)
+
+
+def test_presorted_closed_form():
+    n = 1 << 20
+    keys = (np.arange(n) >> 4).astype(np.float32) * np.float32(2 ** -24)
+    rids = np.arange(n, dtype=np.uint32)
+    got = run(keys, rids, 1000, "desc")
+    j = np.arange(1000)
+    g = n // 16
+    assert np.array_equal(got[1], 16 * (g - 1 - j // 16) + (j % 16))
+    got = run(keys, rids, 1000, "asc")
+    assert np.array_equal(got[1], j)
+
+
+@pytest.mark.parametrize("k", [10, 1000, 10000])
+def test_zipf_both_orders(k):
+    cdf = inputgen.zipf_cdf(1.1, 10 ** 6)
+    n = 1 << 21
+    keys = inputgen.generate(inputgen.KIND_ZIPF_F32, 8, n, cdf=cdf)
+    rids = np.arange(n, dtype=np.uint32)
+    run(keys, rids, k, "desc")
+    got = run(keys, rids, k, "asc")
+    assert np.array_equal(got[1], np.flatnonzero(keys == 1.0)[:k])
+
+
+def test_float_special_values():
+    specials = np.array([0xFFFFFFFF, 0xFFC00001, 0xFF800001, 0xFF800000, 0xFF7FFFFF, 0xBF800000,
+                         0x80000001, 0x80000000, 0x00000000, 0x00000001, 0x3F800000, 0x7F7FFFFF,
+                         0x7F800000, 0x7F800001, 0x7FC00000, 0x7FFFFFFF], dtype=np.uint32)
+    rng = np.random.default_rng(4)
+    for n in (5000, 1 << 19):
+        keys = specials[rng.integers(0, len(specials), n)].view(np.float32)
+        rids = rng.permutation(n).astype(np.uint32)
+        for k in (1, 17, 3000):
+            run(keys, rids, k, "desc")
+            run(keys, rids, k, "asc")
+
+
+def test_k_at_least_n():
+    for n in (1000, 50_000):
+        keys = inputgen.generate(inputgen.KIND_U_F32, 3, n)
+        run(keys, None, n, "desc")
+        run(keys, None, n + 5, "asc")
+
+
+def test_large_k_paths():
+    # survivors beyond one workgroup's LDS, and K beyond one LDS tile
+    n = 1 << 22
+    keys = inputgen.generate(inputgen.KIND_U_I32, 9, n)
+    rids = np.arange(n, dtype=np.uint32)
+    run(keys, rids, 20000, "desc")
+    run(keys, rids, 100_000, "asc")
+    keys64 = inputgen.generate(inputgen.KIND_U_I64, 9, n)
+    run(keys64, None, 100_000, "desc", rid_dtype=np.uint64)
+
+
+def test_unaligned_keys():
+    n = (1 << 20) + 1
+    keys = inputgen.generate(inputgen.KIND_U_F32, 12, n)
+    run(keys, None, 1000, "desc", offset=1)
+    keys64 = inputgen.generate(inputgen.KIND_U_I64, 12, n)
+    run(keys64, None, 1000, "asc", offset=1, rid_dtype=np.uint64)
+
+
+def test_paths_are_taken_and_exact():
+    import torch
+    n = 1 << 20
+    keys = inputgen.generate(inputgen.KIND_U_F32, 21, n)
+    kd = to_dev(keys)
+    exp = oracle.topk(keys, None, 1000, oracle.DESC)
+
+    def go(expect_path):
+        ws = torch.empty(tk.workspace_size(n, 1000, tk.TK_KEY_F32, tk.TK_RID_U32), dtype=torch.uint8,
+                         device="cuda")
+        ok, orr = tk.topk(kd, 1000, workspace=ws)
+        torch.cuda.synchronize()
+        info = tk.query_info(ws)
+        say(f"path {info}")
+        assert info["status"] == 0
+        assert info["path"] == expect_path
+        assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"path {expect_path}")
+
+    go(2)
+    try:
+        tk.set_tuning(force_cap=64)      # survivors overflow: exact fallback over the input
+        go(4)
+        tk.set_tuning(force_cap=-1, force_exact=1)
+        go(5)
+    finally:
+        tk.set_tuning(force_cap=-1, force_exact=2)
+    go(2)
+
+
+def test_workspace_reuse_across_queries():
+    import torch
+    ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(5)
+    for i in range(6):
+        n = int(rng.integers(1 << 18, 1 << 21))
+        keys = inputgen.generate(inputgen.KIND_U_I64, 50 + i, n)
+        run(keys, None, int(rng.integers(1, 3000)), "desc" if i % 2 else "asc",
+            rid_dtype=np.uint64, workspace=ws)
+
+
+def test_repeatable():
+    import torch
+    n = 1 << 21
+    keys = inputgen.generate(inputgen.KIND_U_F32, 77, n)
+    a = run(keys, None, 777, "desc")
+    for _ in range(3):
+        b = run(keys, None, 777, "desc")
+        assert np.array_equal(a[1], b[1])
