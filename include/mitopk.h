@@ -81,10 +81,12 @@ int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int ke
  * few words from the device synchronously; call after the stream has passed
  * the query. */
 typedef struct {
-  uint32_t path;        /* 1 one-workgroup, 2 sample+filter+LDS tail, 3 sample+filter+
-                           exact on survivors, 4 exact fallback over the input,
-                           5 exact radix select over the input */
-  uint32_t status;      /* 0, or device failure bits (1: a grid barrier timed out) */
+  uint32_t path;        /* 2 sampled: streaming filter, then select + sort of the
+                           survivors; 4 sampled, but the sample misjudged: exact select
+                           over the input; 5 exact radix select over the input
+                           (K a large share of N); 0 after a one-workgroup query */
+  uint32_t status;      /* 0, or device failure bits (1: a grid barrier timed out,
+                           2: a wait between engine items timed out) */
   uint64_t survivors;   /* keys that passed the sampled threshold (paths 2-4) */
   uint64_t threshold_key;  /* sampled threshold, order-preserving key image */
 } tk_info;
@@ -101,6 +103,58 @@ typedef struct {
   int32_t force_exact;       /* 1: always the exact radix select, 2: back to default */
 } tk_tuning;
 int tk_set_tuning(const tk_tuning* t);
+
+/* ---- Batched form ----------------------------------------------------------------------------
+ * Q independent Top-K queries over one packed device key buffer: query i
+ * covers keys[offsets[i] .. offsets[i+1]) with its own k[i] and order[i]
+ * (0 descending, 1 ascending).  Row-ids are the local index inside the query
+ * when rowids is NULL at launch, else rowids[offsets[i] + j].  Results are
+ * packed: query i's min(k[i], n_i) results start at element out_offsets[i]
+ * (exclusive prefix sum, see tk_plan_output_offsets).  The plan classifies
+ * every query (sampled streaming pass, or one-workgroup radix select for
+ * small ones), lays out its workspace and builds one work queue; a launch is
+ * three kernels (state reset, sample workgroups, persistent engine), captured
+ * in a hipGraph the first time a pointer set is seen and replayed after.
+ * Results equal tk_topk on each query alone. */
+typedef struct tk_plan tk_plan;
+typedef struct {
+  uint32_t tile_keys;        /* keys per streaming tile; 0: 256 KiB of keys */
+  uint32_t engine_grid;      /* persistent workgroups; 0: as many as fit */
+  uint32_t min_sample_log2;  /* smallest sample; queries under 16x it take the exact select; 0: 12 */
+  uint32_t max_sample_log2;  /* largest sample; 0: 20 */
+  double sample_sigma;       /* margin of the sampled threshold; 0: 3 */
+  int32_t use_graph;         /* >= 0: capture launches in a hipGraph; < 0: launch directly */
+} tk_plan_params;
+
+/* Workspace bytes for a plan (0 on invalid arguments).  Host arrays:
+ * offsets[q+1] (non-decreasing), ks[q], orders[q].  params may be NULL. */
+size_t tk_plan_workspace_size(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders,
+                              uint32_t q, int key_type, int rid_type, const tk_plan_params* params);
+/* Creates a plan bound to `workspace` (device, 256-byte aligned, at least
+ * tk_plan_workspace_size bytes, owned by the caller and reserved for the
+ * plan until tk_plan_destroy).  Uploads descriptors on `stream` and waits
+ * for them.  *plan receives an object owned by the library. */
+int tk_plan_create(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders, uint32_t q,
+                   int key_type, int rid_type, const tk_plan_params* params, void* workspace,
+                   size_t workspace_bytes, void* stream, tk_plan** plan);
+/* out_offsets[q+1]: where each query's results start in the packed outputs. */
+int tk_plan_output_offsets(const tk_plan* plan, uint64_t* out_offsets);
+/* How many queries take the sampled and the exact route, and queue length. */
+int tk_plan_info(const tk_plan* plan, uint32_t* n_sampled, uint32_t* n_exact, uint32_t* n_items);
+/* Runs every query of the plan on `stream` (asynchronous).  keys: the packed
+ * device key buffer; rowids: packed row-ids or NULL; out_keys/out_rowids:
+ * packed outputs (out_keys may be NULL).  Calls on one plan must not
+ * overlap on the device. */
+int tk_plan_launch(tk_plan* plan, const void* keys, const void* rowids, void* out_keys,
+                   void* out_rowids, void* stream);
+/* After the stream has passed a launch: seconds from the launch's start to
+ * each query's result being written (device clock), -1 if unfinished, 0 for
+ * empty queries.  Synchronous copy of q small records. */
+int tk_plan_query_times(const tk_plan* plan, double* seconds);
+/* After a launch: queries whose sample misjudged (exact select over the
+ * input ran instead) and queries left unfinished (must be 0). */
+int tk_plan_stats(const tk_plan* plan, uint32_t* fallbacks, uint32_t* unfinished);
+void tk_plan_destroy(tk_plan* plan);
 
 /* Multithreaded CPU Top-K over host arrays: the CPU route of the cost gate
  * (paper sec. II-B) with the same result definition.  nthreads <= 0 uses

@@ -17,7 +17,7 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmitopk.so")
 HIPCC = "/opt/rocm/bin/hipcc"
 
-SOURCES = ["tk_single.hip", "tk_batched.hip", "tk_serve.cpp", "tk_cpu.cpp"]
+SOURCES = ["tk_single.hip", "tk_sampled.hip", "tk_engine.hip", "tk_batched.hip", "tk_serve.cpp", "tk_cpu.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 # packed fp32 instructions are switched off for all device code
@@ -42,7 +42,7 @@ def build(verbose: bool = False) -> str:
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp", "-lpthread"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp", "-lpthread", "-Wl,--no-undefined"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("linking libmitopk.so failed:\n" + r.stderr)

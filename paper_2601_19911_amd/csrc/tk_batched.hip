@@ -1,0 +1,340 @@
+// Batched Top-K plans: thousands of independent queries of uneven N and K
+// over one packed key buffer, run by the batch engine (tk_engine.hip) as one
+// hipGraph-captured sequence of launches.  Host code only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "mitopk.h"
+#include "tk_engine.hpp"
+#include "tk_internal.hpp"
+#include "tk_plan.hpp"
+
+using namespace tk;
+
+struct tk_plan {
+  int key_type = 0, rid_type = 0;
+  uint32_t q = 0;
+  tk_plan_params params{};
+  Tuning tun;
+  std::vector<QDesc> qd;
+  std::vector<Item> items;
+  std::vector<uint2> prep;
+  std::vector<uint64_t> out_off;  // q + 1 entries
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t off_qs = 0, off_qd = 0, off_items = 0, off_prep = 0, scratch_end = 0;
+  uint32_t n_sampled = 0, n_exact = 0;
+  // descriptors on the device match this pointer set
+  bool uploaded = false;
+  uint64_t u_keys = 0, u_rids = 0, u_ok = 0, u_or = 0;
+  // graph cache for one (bases, stream) combination
+  bool have_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  uint64_t g_keys = 0, g_rids = 0, g_ok = 0, g_or = 0;
+  hipStream_t g_stream = nullptr;
+  std::mutex mu;
+};
+
+namespace {
+
+Tuning plan_tuning(const tk_plan_params* p) {
+  Tuning t = current_tuning();
+  t.force_exact = 0;
+  t.force_cap = 0;
+  t.min_sample_log2 = 12;
+  if (p) {
+    if (p->min_sample_log2) t.min_sample_log2 = p->min_sample_log2;
+    if (p->max_sample_log2) t.max_sample_log2 = p->max_sample_log2;
+    if (p->sample_sigma > 0) t.sample_sigma = p->sample_sigma;
+  }
+  return t;
+}
+
+// Builds descriptors, queue and layout; returns the workspace bytes needed.
+size_t build(tk_plan& P, const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders) {
+  const uint32_t kb = P.key_type == TK_KEY_I64 ? 8 : 4, rb = P.rid_type == TK_RID_U64 ? 8 : 4;
+  const uint32_t q = P.q;
+  P.qd.assign(q, QDesc{});
+  P.out_off.assign(q + 1, 0);
+  for (uint32_t i = 0; i < q; ++i) {
+    const uint64_t n = offsets[i + 1] - offsets[i];
+    P.out_off[i + 1] = P.out_off[i] + std::min<uint64_t>(ks[i], n);
+  }
+  size_t off = sizeof(EngineCtl);
+  P.off_qs = off;
+  off = align_up(off + (size_t)q * sizeof(QState), 256);
+  P.off_qd = off;
+  off = align_up(off + (size_t)q * sizeof(QDesc), 256);
+  // classify, count items
+  std::vector<SamplePlan> sp(q);
+  uint64_t nitems = 0, nprep = 0;
+  const uint32_t tile = P.params.tile_keys ? P.params.tile_keys : tile_len_for(kb);
+  for (uint32_t i = 0; i < q; ++i) {
+    QDesc& d = P.qd[i];
+    d.n = offsets[i + 1] - offsets[i];
+    d.k_eff = (uint32_t)std::min<uint64_t>(ks[i], d.n);
+    d.order = orders[i] ? 1 : 0;
+    d.key_type = (uint8_t)P.key_type;
+    d.keys = offsets[i] * kb;
+    d.rids = offsets[i] * rb;
+    d.rid_base = 0;
+    d.out_keys = P.out_off[i] * kb;
+    d.out_rids = P.out_off[i] * rb;
+    if (d.k_eff == 0) {
+      d.cls = CLS_EMPTY;
+      continue;
+    }
+    sp[i] = plan_sample(d.n, d.k_eff, P.tun);
+    if (sp[i].fast) {
+      d.cls = CLS_SAMPLED;
+      d.r1 = sp[i].r1;
+      d.S = sp[i].S;
+      d.samp_blocks = sp[i].blocks;
+      d.cap = sp[i].cap;
+      d.tile_len = tile;
+      d.ntiles = (uint32_t)((d.n + tile - 1) / tile);
+      nitems += d.ntiles;
+      nprep += d.samp_blocks;
+      ++P.n_sampled;
+    } else {
+      d.cls = CLS_EXACT;
+      nitems += 1;
+      ++P.n_exact;
+    }
+  }
+  P.off_items = off;
+  off = align_up(off + nitems * sizeof(Item), 256);
+  P.off_prep = off;
+  off = align_up(off + nprep * sizeof(uint2), 256);
+  for (uint32_t i = 0; i < q; ++i)
+    if (P.qd[i].cls != CLS_EMPTY) off += layout_query(P.qd[i], off, kb, rb, sp[i]);
+  P.scratch_end = off;
+  // queue: sampled queries by decreasing size (their tiles contiguous), then
+  // the exact queries by decreasing size to fill the gaps at the end
+  std::vector<uint32_t> order(q);
+  std::iota(order.begin(), order.end(), 0u);
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+    const QDesc& a = P.qd[x];
+    const QDesc& b = P.qd[y];
+    if (a.cls != b.cls) return a.cls < b.cls;
+    return a.n > b.n;
+  });
+  P.items.clear();
+  P.prep.clear();
+  for (uint32_t i : order) {
+    const QDesc& d = P.qd[i];
+    if (d.cls == CLS_SAMPLED) {
+      for (uint32_t t = 0; t < d.ntiles; ++t) P.items.push_back(Item{ITEM_TILE, i, t, 0});
+      for (uint32_t b = 0; b < d.samp_blocks; ++b) P.prep.push_back(make_uint2(i, b));
+    } else if (d.cls == CLS_EXACT) {
+      P.items.push_back(Item{ITEM_EXACT, i, 0, 0});
+    }
+  }
+  return align_up(off, 256);
+}
+
+EngineArgs plan_args(const tk_plan& P, const void* keys, const void* rids, void* ok, void* orr) {
+  EngineArgs a{};
+  a.qd = reinterpret_cast<const QDesc*>(P.ws + P.off_qd);
+  a.qs = reinterpret_cast<QState*>(P.ws + P.off_qs);
+  a.ctl = reinterpret_cast<EngineCtl*>(P.ws);
+  a.items = reinterpret_cast<const Item*>(P.ws + P.off_items);
+  a.prep = reinterpret_cast<const uint2*>(P.ws + P.off_prep);
+  a.scratch = P.ws;
+  a.nitems = (uint32_t)P.items.size();
+  a.nq = P.q;
+  a.nprep = (uint32_t)P.prep.size();
+  a.keys_base = (uint64_t)(uintptr_t)keys;
+  a.rids_base = (uint64_t)(uintptr_t)rids;
+  a.out_keys_base = (uint64_t)(uintptr_t)ok;
+  a.out_rids_base = (uint64_t)(uintptr_t)orr;
+  return a;
+}
+
+bool valid_inputs(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders, uint32_t q,
+                  int key_type, int rid_type) {
+  if (!offsets || !ks || !orders || q == 0) return false;
+  if (key_type < 0 || key_type > 2 || rid_type < 0 || rid_type > 1) return false;
+  for (uint32_t i = 0; i < q; ++i) {
+    if (offsets[i + 1] < offsets[i]) return false;
+    if (orders[i] > 1) return false;
+    if (rid_type == TK_RID_U32 && offsets[i + 1] - offsets[i] > (1ull << 32)) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" size_t tk_plan_workspace_size(const uint64_t* offsets, const uint32_t* ks,
+                                         const uint8_t* orders, uint32_t q, int key_type,
+                                         int rid_type, const tk_plan_params* params) {
+  if (!valid_inputs(offsets, ks, orders, q, key_type, rid_type)) return 0;
+  tk_plan P;
+  P.key_type = key_type;
+  P.rid_type = rid_type;
+  P.q = q;
+  if (params) P.params = *params;
+  P.tun = plan_tuning(params);
+  return build(P, offsets, ks, orders);
+}
+
+extern "C" int tk_plan_create(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders,
+                              uint32_t q, int key_type, int rid_type,
+                              const tk_plan_params* params, void* workspace,
+                              size_t workspace_bytes, void* stream, tk_plan** out) {
+  if (!out || !valid_inputs(offsets, ks, orders, q, key_type, rid_type)) return TK_EINVAL;
+  if (!workspace || ((uintptr_t)workspace & 255u)) return TK_EINVAL;
+  tk_plan* P = new (std::nothrow) tk_plan;
+  if (!P) return TK_ENOMEM;
+  P->key_type = key_type;
+  P->rid_type = rid_type;
+  P->q = q;
+  if (params) P->params = *params;
+  P->tun = plan_tuning(params);
+  const size_t need = build(*P, offsets, ks, orders);
+  if (workspace_bytes < need) {
+    delete P;
+    return TK_EINVAL;
+  }
+  P->ws = static_cast<char*>(workspace);
+  P->ws_bytes = workspace_bytes;
+  hipStream_t st = (hipStream_t)stream;
+  // descriptors, queue and sample map go to the device once
+  if (hipMemcpyAsync(P->ws + P->off_qd, P->qd.data(), P->qd.size() * sizeof(QDesc),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      (!P->items.empty() &&
+       hipMemcpyAsync(P->ws + P->off_items, P->items.data(), P->items.size() * sizeof(Item),
+                      hipMemcpyHostToDevice, st) != hipSuccess) ||
+      (!P->prep.empty() &&
+       hipMemcpyAsync(P->ws + P->off_prep, P->prep.data(), P->prep.size() * sizeof(uint2),
+                      hipMemcpyHostToDevice, st) != hipSuccess) ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    delete P;
+    return TK_EHIP;
+  }
+  *out = P;
+  return TK_OK;
+}
+
+extern "C" int tk_plan_output_offsets(const tk_plan* P, uint64_t* out_offsets) {
+  if (!P || !out_offsets) return TK_EINVAL;
+  std::memcpy(out_offsets, P->out_off.data(), P->out_off.size() * sizeof(uint64_t));
+  return TK_OK;
+}
+
+extern "C" int tk_plan_info(const tk_plan* P, uint32_t* n_sampled, uint32_t* n_exact,
+                            uint32_t* n_items) {
+  if (!P) return TK_EINVAL;
+  if (n_sampled) *n_sampled = P->n_sampled;
+  if (n_exact) *n_exact = P->n_exact;
+  if (n_items) *n_items = (uint32_t)P->items.size();
+  return TK_OK;
+}
+
+extern "C" int tk_plan_launch(tk_plan* P, const void* keys, const void* rowids, void* out_keys,
+                              void* out_rowids, void* stream) {
+  if (!P || !keys) return TK_EINVAL;
+  std::lock_guard<std::mutex> lk(P->mu);
+  hipStream_t st = (hipStream_t)stream;
+  const EngineArgs a = plan_args(*P, keys, rowids, out_keys, out_rowids);
+  const uint64_t gk = (uint64_t)(uintptr_t)keys, gr = (uint64_t)(uintptr_t)rowids,
+                 go = (uint64_t)(uintptr_t)out_keys, gq = (uint64_t)(uintptr_t)out_rowids;
+  // which inputs and outputs exist is part of the descriptors
+  if (!P->uploaded || (P->u_rids == 0) != (gr == 0) || (P->u_ok == 0) != (go == 0) ||
+      (P->u_or == 0) != (gq == 0)) {
+    for (QDesc& d : P->qd) {
+      d.has_rids = rowids != nullptr;
+      d.has_out_keys = out_keys != nullptr;
+      d.has_out_rids = out_rowids != nullptr;
+    }
+    if (hipMemcpyAsync(P->ws + P->off_qd, P->qd.data(), P->qd.size() * sizeof(QDesc),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return TK_EHIP;
+    P->uploaded = true;
+    P->u_keys = gk;
+    P->u_rids = gr;
+    P->u_ok = go;
+    P->u_or = gq;
+  }
+  const bool same = P->have_graph && P->g_keys == gk && P->g_rids == gr && P->g_ok == go &&
+                    P->g_or == gq && P->g_stream == st;
+  const bool graph = P->params.use_graph >= 0;
+  if (!graph) return engine_launch(a, P->rid_type, P->key_type, P->params.engine_grid, st);
+  if (!same) {
+    if (P->have_graph) {
+      hipGraphExecDestroy(P->gexec);
+      hipGraphDestroy(P->graph);
+      P->have_graph = false;
+    }
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TK_EHIP;
+    const int rc = engine_launch(a, P->rid_type, P->key_type, P->params.engine_grid, st);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != TK_OK || e != hipSuccess || !g) return TK_EHIP;
+    if (hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(g);
+      return TK_EHIP;
+    }
+    P->graph = g;
+    P->have_graph = true;
+    P->g_keys = gk;
+    P->g_rids = gr;
+    P->g_ok = go;
+    P->g_or = gq;
+    P->g_stream = st;
+  }
+  return hipGraphLaunch(P->gexec, st) == hipSuccess ? TK_OK : TK_EHIP;
+}
+
+extern "C" int tk_plan_query_times(const tk_plan* P, double* seconds) {
+  if (!P || !seconds) return TK_EINVAL;
+  std::vector<QState> qs(P->q);
+  EngineCtl ctl;
+  if (hipMemcpy(qs.data(), P->ws + P->off_qs, qs.size() * sizeof(QState), hipMemcpyDeviceToHost) !=
+          hipSuccess ||
+      hipMemcpy(&ctl, P->ws, sizeof(ctl), hipMemcpyDeviceToHost) != hipSuccess)
+    return TK_EHIP;
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  for (uint32_t i = 0; i < P->q; ++i) {
+    const QDesc& d = P->qd[i];
+    if (d.cls == CLS_EMPTY) seconds[i] = 0.0;
+    else if (!qs[i].done) seconds[i] = -1.0;
+    else seconds[i] = (double)(qs[i].t_done - ctl.t_start) / ((double)khz * 1e3);
+  }
+  return TK_OK;
+}
+
+extern "C" int tk_plan_stats(const tk_plan* P, uint32_t* fallbacks, uint32_t* unfinished) {
+  if (!P) return TK_EINVAL;
+  std::vector<QState> qs(P->q);
+  if (hipMemcpy(qs.data(), P->ws + P->off_qs, qs.size() * sizeof(QState), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return TK_EHIP;
+  uint32_t fb = 0, un = 0;
+  for (uint32_t i = 0; i < P->q; ++i) {
+    if (qs[i].status & 1u) ++fb;
+    if (P->qd[i].cls != CLS_EMPTY && !qs[i].done) ++un;
+  }
+  if (fallbacks) *fallbacks = fb;
+  if (unfinished) *unfinished = un;
+  return TK_OK;
+}
+
+extern "C" void tk_plan_destroy(tk_plan* P) {
+  if (!P) return;
+  if (P->have_graph) {
+    hipGraphExecDestroy(P->gexec);
+    hipGraphDestroy(P->graph);
+  }
+  delete P;
+}

@@ -22,8 +22,9 @@ struct Header {
   unsigned long long thr_f;       // sampled threshold (flipped row-id)
   uint32_t status;                // device failure bits (1: barrier timeout)
   uint32_t path;                  // path taken, see tk_info
-  GridSync gs;                    // grid barrier of the tail kernel
-  uint32_t pad[4];
+  GridSync gs;                    // grid barrier of the exact-select kernel
+  uint32_t samp_ticket;           // sample workgroups finished (reset by the last one)
+  uint32_t pad[3];
   unsigned long long hist[3][256];  // exact select: global digit histograms
 };
 static_assert(sizeof(Header) <= HEADER_BYTES, "header must fit its reserved bytes");
@@ -44,6 +45,11 @@ inline int device_cus(int dev) {
 
 Tuning current_tuning();
 void profile_mark(hipStream_t st, bool begin);
+
+template <int KT, int RT>
+int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, int order,
+                void* out_keys, void* out_rids, void* ws, size_t ws_bytes, hipStream_t st,
+                const Tuning& tun, const SamplePlan& p);
 
 template <int KT, int RT>
 int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, int order,

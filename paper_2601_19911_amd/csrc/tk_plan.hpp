@@ -33,6 +33,8 @@ struct Tuning {
   uint32_t filter_grid = 0;    // 0: automatic
   uint64_t force_cap = 0;      // >0: override the survivor capacity (tests)
   int force_exact = 0;         // 1: always take the exact radix path (tests)
+  uint32_t tile_len = 0;       // keys per streaming tile of the engine (0: 256 KiB of keys)
+  uint32_t engine_grid = 0;    // engine workgroups (0: as many as fit)
 };
 
 // Chooses the sample for a query of n keys and k_eff results.  The threshold

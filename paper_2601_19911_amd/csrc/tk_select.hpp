@@ -1,0 +1,421 @@
+// One-workgroup radix select and sort building blocks of the engine.
+//
+// block_radix_select finds the boundary of the best `target` composites
+// among the elements a visitor presents (registers of the workgroup, or an
+// array in global memory).  Digits are 8 bits of d = u - base, starting at
+// the most significant set bit of max(d): the range of the candidates, not of
+// the key type, sets the first digit, so keys that share their high bits
+// (floats in [0, 1), survivors above a threshold) still split in the first
+// round.  Each round builds an LDS histogram of the digit over the
+// candidates that match the prefix so far and picks the bucket holding rank
+// `need` with a wave-wide suffix scan.  When the key image is exhausted and
+// the boundary bucket still holds more elements than needed, the flipped
+// row-id is digitized the same way.
+#pragma once
+
+#include "tk_device.hpp"
+
+namespace tk {
+
+enum SelKind { SEL_KEY = 0, SEL_RID = 1, SEL_DUP = 2 };
+
+template <typename U, typename R>
+struct Sel {
+  U base;      // every candidate has u >= base
+  U P;         // resolved digits of d = u - base
+  R Pf;        // resolved digits of the flipped row-id (SEL_RID / SEL_DUP)
+  int kind;    // SelKind
+  uint64_t need;  // SEL_DUP: copies of the exact boundary composite to take
+};
+
+// u in the selection iff its composite is at or above the boundary
+template <typename U, typename R>
+__device__ __forceinline__ bool sel_take(const Sel<U, R>& s, U u, R f) {
+  if (u < s.base) return false;
+  const U d = u - s.base;
+  if (s.kind == SEL_KEY) return d >= s.P;
+  if (s.kind == SEL_RID) return d > s.P || (d == s.P && f >= s.Pf);
+  return d > s.P || (d == s.P && f > s.Pf);
+}
+template <typename U, typename R>
+__device__ __forceinline__ bool sel_is_boundary_copy(const Sel<U, R>& s, U u, R f) {
+  return s.kind == SEL_DUP && u >= s.base && u - s.base == s.P && f == s.Pf;
+}
+// whether u might be selected (so f has to be read)
+template <typename U, typename R>
+__device__ __forceinline__ bool sel_maybe(const Sel<U, R>& s, U u) {
+  return u >= s.base && u - s.base >= s.P;
+}
+
+struct SelScratch {
+  uint32_t hist[256];
+  unsigned long long red[16];
+  uint32_t res[4];
+  uint32_t cnt[2];
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const T w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const T w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+template <int NT, typename T>
+__device__ __forceinline__ T block_max(T v, SelScratch& sc) {
+  v = wave_max(v);
+  __syncthreads();
+  if (lane_id() == 0) sc.red[threadIdx.x >> 6] = (unsigned long long)v;
+  __syncthreads();
+  T m = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const T w = (T)sc.red[i];
+    m = w > m ? w : m;
+  }
+  return m;
+}
+template <int NT, typename T>
+__device__ __forceinline__ T block_min(T v, SelScratch& sc) {
+  v = wave_min(v);
+  __syncthreads();
+  if (lane_id() == 0) sc.red[threadIdx.x >> 6] = (unsigned long long)v;
+  __syncthreads();
+  T m = (T)~(T)0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const T w = (T)sc.red[i];
+    m = w < m ? w : m;
+  }
+  return m;
+}
+
+// After the histogram is complete: finds digit b with (sum of bins above b) <
+// need <= (that sum + hist[b]).  Wave 0 scans; everyone reads the result.
+template <int NT>
+__device__ __forceinline__ void find_bucket(SelScratch& sc, uint64_t need, uint32_t& digit,
+                                            uint64_t& above, uint64_t& cnt) {
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const uint32_t L = threadIdx.x;
+    const uint32_t h0 = sc.hist[4 * L], h1 = sc.hist[4 * L + 1], h2 = sc.hist[4 * L + 2],
+                   h3 = sc.hist[4 * L + 3];
+    const uint64_t s = (uint64_t)h0 + h1 + h2 + h3;
+    uint64_t x = s;  // sum over lanes L..63
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t y = __shfl_down(x, o, 64);
+      if (L + o < 64) x += y;
+    }
+    const uint64_t excl = x - s;
+    if (excl < need && need <= x) {
+      uint64_t c = excl;
+      uint32_t d = 4 * L;
+      uint32_t hb = h0;
+      if (c + h3 >= need) { d = 4 * L + 3; hb = h3; }
+      else if ((c += h3) + h2 >= need) { d = 4 * L + 2; hb = h2; }
+      else if ((c += h2) + h1 >= need) { d = 4 * L + 1; hb = h1; }
+      else { c += h1; d = 4 * L; hb = h0; }
+      sc.res[0] = d;
+      sc.res[1] = (uint32_t)c;
+      sc.res[2] = (uint32_t)(c >> 32);
+      sc.res[3] = hb;
+    }
+  }
+  __syncthreads();
+  digit = sc.res[0];
+  above = (uint64_t)sc.res[1] | ((uint64_t)sc.res[2] << 32);
+  cnt = sc.res[3];
+}
+
+template <int NT>
+__device__ __forceinline__ void hist_clear(SelScratch& sc) {
+  for (uint32_t i = threadIdx.x; i < 256; i += NT) sc.hist[i] = 0;
+  __syncthreads();
+}
+
+// Visitors present each thread's share of the candidates.
+// Registers: E composites per thread, the first nv valid.
+template <typename U, typename R, int E>
+struct RegElems {
+  U (&k)[E];
+  R (&f)[E];
+  int nv;
+  template <typename Fn>
+  __device__ __forceinline__ void each(Fn&& fn) const {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (e < nv) fn(k[e], [&]() { return f[e]; });
+  }
+};
+
+// A global array seen through a source (key image and flipped row-id by index).
+template <int NT, typename Src>
+struct GlobElems {
+  const Src& src;
+  uint64_t n;
+  template <typename Fn>
+  __device__ __forceinline__ void each(Fn&& fn) const {
+    for (uint64_t i = threadIdx.x; i < n; i += NT) fn(src.key(i), [&]() { return src.flip(i); });
+  }
+};
+
+template <typename U>
+__device__ __forceinline__ int bitlen(U x) {
+  if (x == 0) return 0;
+  if constexpr (sizeof(U) == 8) return 64 - __builtin_clzll((unsigned long long)x);
+  else return 32 - __builtin_clz((unsigned)x);
+}
+
+// Boundary of the best `target` candidates (every candidate has u >= base and
+// there are at least `target` of them).
+template <int NT, typename U, typename R, typename Elems>
+__device__ Sel<U, R> block_radix_select(const Elems& el, uint64_t target, U base, SelScratch& sc) {
+  Sel<U, R> s;
+  s.base = base;
+  s.P = 0;
+  s.Pf = 0;
+  s.kind = SEL_KEY;
+  U lmax = 0;
+  el.each([&](U u, auto) {
+    if (u >= base && u - base > lmax) lmax = u - base;
+  });
+  const U dmax = block_max<NT, U>(lmax, sc);
+  const int hb = bitlen(dmax);
+  uint64_t need = target;
+  U M = 0;
+  for (int sh = hb - 8;; sh -= 8) {
+    const int s0 = sh < 0 ? 0 : sh;
+    hist_clear<NT>(sc);
+    el.each([&](U u, auto) {
+      if (u >= base) {
+        const U d = u - base;
+        if ((d & M) == s.P) atomicAdd(&sc.hist[(uint32_t)(d >> s0) & 0xFFu], 1u);
+      }
+    });
+    uint32_t dig;
+    uint64_t above, cnt;
+    find_bucket<NT>(sc, need, dig, above, cnt);
+    need -= above;
+    s.P |= (U)dig << s0;
+    M |= (U)0xFF << s0;
+    if (cnt == need) {
+      s.need = need;
+      return s;
+    }
+    if (s0 == 0) break;
+  }
+  // the key image is resolved; order the boundary key's copies by row-id
+  s.kind = SEL_RID;
+  R Mf = 0;
+  constexpr int WR = (int)sizeof(R) * 8;
+  for (int s0 = WR - 8; s0 >= 0; s0 -= 8) {
+    hist_clear<NT>(sc);
+    el.each([&](U u, auto getf) {
+      if (u >= base && u - base == s.P) {
+        const R f = getf();
+        if ((f & Mf) == s.Pf) atomicAdd(&sc.hist[(uint32_t)(f >> s0) & 0xFFu], 1u);
+      }
+    });
+    uint32_t dig;
+    uint64_t above, cnt;
+    find_bucket<NT>(sc, need, dig, above, cnt);
+    need -= above;
+    s.Pf |= (R)dig << s0;
+    Mf |= (R)0xFF << s0;
+    if (cnt == need) {
+      s.need = need;
+      return s;
+    }
+  }
+  s.kind = SEL_DUP;
+  s.need = need;
+  return s;
+}
+
+// Writes the selected composites to (dk, df): the ones above the boundary in
+// any order at [0, target - need) and, for SEL_DUP, `need` boundary copies
+// after them.  Every thread must call these (their loops are
+// workgroup-uniform).
+template <int NT, typename U, typename R, int E, typename KOut, typename FOut>
+__device__ void block_compact_regs(const RegElems<U, R, E>& el, const Sel<U, R>& s,
+                                   uint64_t target, KOut dk, FOut df, SelScratch& sc) {
+  if (threadIdx.x == 0) { sc.cnt[0] = 0; sc.cnt[1] = 0; }
+  __syncthreads();
+  const uint64_t n_gt = s.kind == SEL_DUP ? target - s.need : target;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const bool valid = e < el.nv;
+    const U u = valid ? el.k[e] : (U)0;
+    const R f = valid ? el.f[e] : (R)0;
+    const bool take = valid && sel_take(s, u, f);
+    const bool eq = valid && sel_is_boundary_copy(s, u, f);
+    const uint64_t mt = ballot(take), me = ballot(eq);
+    if (mt) {
+      const uint32_t leader = (uint32_t)__builtin_ctzll(mt);
+      uint32_t b = 0;
+      if (lane_id() == leader) b = atomicAdd(&sc.cnt[0], (uint32_t)__popcll(mt));
+      b = __shfl(b, (int)leader, 64);
+      if (take) {
+        const uint64_t pos = b + lanes_below(mt);
+        if (pos < n_gt) { dk[pos] = u; df[pos] = f; }
+      }
+    }
+    if (me) {
+      const uint32_t leader = (uint32_t)__builtin_ctzll(me);
+      uint32_t b = 0;
+      if (lane_id() == leader) b = atomicAdd(&sc.cnt[1], (uint32_t)__popcll(me));
+      b = __shfl(b, (int)leader, 64);
+      if (eq) {
+        const uint64_t pos = n_gt + b + lanes_below(me);
+        if (pos < target) { dk[pos] = u; df[pos] = f; }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int NT, typename U, typename R, typename Src, typename KOut, typename FOut>
+__device__ void block_compact_glob(const Src& src, uint64_t n, const Sel<U, R>& s, uint64_t target,
+                                   KOut dk, FOut df, SelScratch& sc) {
+  if (threadIdx.x == 0) { sc.cnt[0] = 0; sc.cnt[1] = 0; }
+  __syncthreads();
+  const uint64_t n_gt = s.kind == SEL_DUP ? target - s.need : target;
+  for (uint64_t i0 = 0; i0 < n; i0 += NT) {
+    const uint64_t i = i0 + threadIdx.x;
+    bool take = false, eq = false;
+    U u = 0;
+    R f = 0;
+    if (i < n) {
+      u = src.key(i);
+      if (sel_maybe(s, u)) {
+        f = src.flip(i);
+        take = sel_take(s, u, f);
+        eq = sel_is_boundary_copy(s, u, f);
+      }
+    }
+    const uint64_t mt = ballot(take), me = ballot(eq);
+    if (mt) {
+      const uint32_t leader = (uint32_t)__builtin_ctzll(mt);
+      uint32_t b = 0;
+      if (lane_id() == leader) b = atomicAdd(&sc.cnt[0], (uint32_t)__popcll(mt));
+      b = __shfl(b, (int)leader, 64);
+      if (take) {
+        const uint64_t pos = b + lanes_below(mt);
+        if (pos < n_gt) { dk[pos] = u; df[pos] = f; }
+      }
+    }
+    if (me) {
+      const uint32_t leader = (uint32_t)__builtin_ctzll(me);
+      uint32_t b = 0;
+      if (lane_id() == leader) b = atomicAdd(&sc.cnt[1], (uint32_t)__popcll(me));
+      b = __shfl(b, (int)leader, 64);
+      if (eq) {
+        const uint64_t pos = n_gt + b + lanes_below(me);
+        if (pos < target) { dk[pos] = u; df[pos] = f; }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// merge-path split: number of elements of A among the first d outputs of
+// merge(A, B), best first, ties taken from A
+template <typename U, typename R>
+__device__ __forceinline__ uint64_t merge_split(const U* ak, const R* af, uint64_t na, const U* bk,
+                                                const R* bf, uint64_t nb, uint64_t d) {
+  uint64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) / 2;
+    if (cge(ak[mid], af[mid], bk[d - 1 - mid], bf[d - 1 - mid])) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One workgroup sorts m selected composites best first and hands each to
+// emit(j, u, f).  in_lds: the composites sit at the start of the LDS tile
+// (lk, lf) of CAP elements and m <= CAP.  Otherwise they are in (ck, cf) in
+// global memory: tiles of CAP are bitonic-sorted in LDS, then merged pairwise
+// through (tk, tf) with merge-path splits.
+template <int NT, typename U, typename R, typename Emit>
+__device__ void block_sort_emit(uint64_t m, bool in_lds, U* lk, R* lf, uint32_t CAP, U* ck, R* cf,
+                                U* tk, R* tf, Emit&& emit) {
+  if (in_lds) {
+    uint32_t P = 1;
+    while (P < m) P <<= 1;
+    for (uint32_t i = (uint32_t)m + threadIdx.x; i < P; i += NT) {
+      lk[i] = 0;
+      lf[i] = 0;
+    }
+    bitonic_desc<U, R, NT>(lk, lf, P);
+    for (uint32_t j = threadIdx.x; j < m; j += NT) emit((uint64_t)j, lk[j], lf[j]);
+    __syncthreads();
+    return;
+  }
+  for (uint64_t base = 0; base < m; base += CAP) {
+    const uint64_t len = m - base < CAP ? m - base : CAP;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < CAP; i += NT) {
+      lk[i] = i < len ? ck[base + i] : (U)0;
+      lf[i] = i < len ? cf[base + i] : (R)0;
+    }
+    bitonic_desc<U, R, NT>(lk, lf, CAP);
+    for (uint32_t i = threadIdx.x; i < len; i += NT) {
+      ck[base + i] = lk[i];
+      cf[base + i] = lf[i];
+    }
+  }
+  __syncthreads();
+  U* sk = ck;
+  R* sf = cf;
+  U* dk = tk;
+  R* df = tf;
+  constexpr uint64_t ITEMS = 8;
+  for (uint64_t run = CAP; run < m; run <<= 1) {
+    for (uint64_t s = 0; s < m; s += 2 * run) {
+      const uint64_t amid = s + run < m ? s + run : m;
+      const uint64_t aend = s + 2 * run < m ? s + 2 * run : m;
+      const uint64_t na = amid - s, nb = aend - amid;
+      for (uint64_t o0 = (uint64_t)threadIdx.x * ITEMS; o0 < na + nb; o0 += (uint64_t)NT * ITEMS) {
+        uint64_t i = merge_split<U, R>(sk + s, sf + s, na, sk + amid, sf + amid, nb, o0);
+        uint64_t j = o0 - i;
+        const uint64_t cnt = na + nb - o0 < ITEMS ? na + nb - o0 : ITEMS;
+        for (uint64_t q = 0; q < cnt; ++q) {
+          bool from_a;
+          if (i >= na) from_a = false;
+          else if (j >= nb) from_a = true;
+          else from_a = cge(sk[s + i], sf[s + i], sk[amid + j], sf[amid + j]);
+          if (from_a) {
+            dk[s + o0 + q] = sk[s + i];
+            df[s + o0 + q] = sf[s + i];
+            ++i;
+          } else {
+            dk[s + o0 + q] = sk[amid + j];
+            df[s + o0 + q] = sf[amid + j];
+            ++j;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    U* xk = sk; sk = dk; dk = xk;
+    R* xf = sf; sf = df; df = xf;
+  }
+  for (uint64_t j = threadIdx.x; j < m; j += NT) emit(j, sk[j], sf[j]);
+  __syncthreads();
+}
+
+}  // namespace tk

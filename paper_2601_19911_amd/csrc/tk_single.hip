@@ -1,23 +1,14 @@
-// Single-query key-only Top-K (ordering primitive, paper sec. III-A) for
-// gfx950, plus the shared kernels the batched and served forms reuse.
-//
-// Large queries run four kernels on the caller's stream:
-//   1. k_sample_local  many workgroups read a stratified sample (16-key chunks)
-//                      and keep their local best r1 composites;
-//   2. k_sample_final  one workgroup picks the r1-th best of those: the
-//                      threshold T;
-//   3. k_filter        the one streaming pass over the keys: keys whose
-//                      composite is >= T are appended to a survivor buffer
-//                      (wave ballot + one atomic per wave with survivors);
-//   4. k_tail          cooperative grid.  If K <= survivors <= capacity and
-//                      they fit LDS, one workgroup selects the best K by
-//                      bisection and bitonic-sorts them in LDS.  Otherwise
-//                      every workgroup runs an exact 8-bit-digit radix select
-//                      (over the survivors, or over the whole input when the
-//                      sample misjudged), then the K results are sorted.
-// The sampled threshold only decides how much work the tail has: any
-// threshold with at least K survivors yields the exact answer, and a bad one
-// falls back to the exact select, so the result never depends on the sample.
+// Single-query entry point of key-only Top-K (ordering primitive, paper
+// sec. III-A) and the two paths that do not go through the engine:
+//   - queries that fit one workgroup (k_small): the keys are loaded once,
+//     the best K found by radix select and bitonic-sorted in LDS;
+//   - queries whose K is a large share of N (or forced, for tests): an exact
+//     radix select over the whole input by a cooperative grid (k_tail with
+//     exact_only): 8-bit digits of the key image from the top, then of the
+//     flipped row-id, each digit found from a global histogram; then the
+//     selected composites are sorted (one LDS tile, or tiles plus
+//     merge-path merges).
+// Every other query takes the sampled path (tk_sampled.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,31 +19,10 @@
 #include "tk_device.hpp"
 #include "tk_internal.hpp"
 #include "tk_plan.hpp"
+#include "tk_select.hpp"
+#include "tk_src.hpp"
 
 namespace tk {
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// ---- sources of composites ----------------------------------------------------------------
-
-template <int KT, int RT>
-struct InputSrc {
-  using U = typename Key<KT>::U;
-  using R = typename Rid<RT>::R;
-  const typename Key<KT>::Raw* keys;
-  const R* rids;
-  U dmask;
-  __device__ __forceinline__ U key(uint64_t i) const { return Key<KT>::enc(keys[i]) ^ dmask; }
-  __device__ __forceinline__ R flip(uint64_t i) const { return ~(rids ? rids[i] : (R)i); }
-};
-
-template <typename U, typename R>
-struct BufSrc {
-  const U* k;
-  const R* f;
-  __device__ __forceinline__ U key(uint64_t i) const { return k[i]; }
-  __device__ __forceinline__ R flip(uint64_t i) const { return f[i]; }
-};
 
 // ---- kernel 0: header reset (exact-only path) ----------------------------------------------
 
@@ -66,184 +36,7 @@ __device__ __forceinline__ void header_reset_block(Header* h) {
   for (uint32_t i = threadIdx.x; i < sizeof(Header) / 4; i += blockDim.x) w[i] = 0u;
 }
 
-// ---- kernel 1: local sample select -----------------------------------------------------------
-
-template <int KT, int RT>
-__global__ __launch_bounds__(256) void k_sample_local(const typename Key<KT>::Raw* keys,
-                                                      const typename Rid<RT>::R* rids, uint64_t n,
-                                                      typename Key<KT>::U dmask, uint32_t S,
-                                                      uint32_t r1, Header* h,
-                                                      typename Key<KT>::U* ck,
-                                                      typename Rid<RT>::R* cf) {
-  using U = typename Key<KT>::U;
-  using R = typename Rid<RT>::R;
-  constexpr int NT = 256, E = 4;
-  __shared__ uint64_t red[2 * NT / 64];
-  __shared__ uint32_t ws[NT / 64];
-  if (blockIdx.x == 0) header_reset_block(h);
-  const InputSrc<KT, RT> src{keys, rids, dmask};
-  const uint64_t nchunks = S / SAMPLE_CHUNK;
-  const uint64_t stride = n / nchunks;  // >= 16 because n >= 16 * S
-  const uint64_t off0 = (stride - SAMPLE_CHUNK) / 2;
-  U k[E];
-  R f[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const uint64_t j = (uint64_t)blockIdx.x * SAMPLE_PER_BLOCK + (uint64_t)e * NT + threadIdx.x;
-    const uint64_t pos = (j / SAMPLE_CHUNK) * stride + off0 + (j % SAMPLE_CHUNK);
-    k[e] = src.key(pos);
-    f[e] = src.flip(pos);
-  }
-  int parity = 0;
-  U Tk;
-  R Tf;
-  block_select<U, R, E, NT>(k, f, E, r1, Tk, Tf, red, parity);
-  block_emit_top<U, R, E, NT>(k, f, E, r1, Tk, Tf, ck + (uint64_t)blockIdx.x * r1,
-                              cf + (uint64_t)blockIdx.x * r1, ws);
-}
-
-// ---- kernel 2: final sample select -----------------------------------------------------------
-
-template <int KT, int RT>
-__global__ __launch_bounds__(1024) void k_sample_final(Header* h, const typename Key<KT>::U* ck,
-                                                       const typename Rid<RT>::R* cf, uint32_t m,
-                                                       uint32_t r1) {
-  using U = typename Key<KT>::U;
-  using R = typename Rid<RT>::R;
-  constexpr int NT = 1024, E = SAMPLE_FINAL_MAX / NT;
-  __shared__ uint64_t red[2 * NT / 64];
-  U k[E];
-  R f[E];
-  int nv = 0;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const uint32_t j = (uint32_t)e * NT + threadIdx.x;
-    if (j < m) {
-      k[e] = ck[j];
-      f[e] = cf[j];
-      nv = e + 1;
-    } else {
-      k[e] = 0;
-      f[e] = 0;
-    }
-  }
-  int parity = 0;
-  U Tk;
-  R Tf;
-  block_select<U, R, E, NT>(k, f, nv, r1, Tk, Tf, red, parity);
-  if (threadIdx.x == 0) {
-    h->thr_k = (uint64_t)Tk;
-    h->thr_f = (uint64_t)Tf;
-  }
-}
-
-// ---- kernel 3: streaming filter ----------------------------------------------------------------
-
-template <typename U, typename R>
-__device__ __forceinline__ void emit_survivor(bool pass, U kk, R ff, Header* h, U* sk, R* sf,
-                                              uint64_t cap) {
-  const uint64_t m = ballot(pass);
-  if (m == 0) return;
-  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
-  uint64_t base = 0;
-  if (lane_id() == leader) base = atomicAdd(&h->surv_count, (unsigned long long)__popcll(m));
-  base = __shfl(base, (int)leader, 64);
-  if (pass) {
-    const uint64_t pos = base + lanes_below(m);
-    if (pos < cap) {
-      sk[pos] = kk;
-      sf[pos] = ff;
-    }
-  }
-}
-
-template <int KT, int RT, int VEC, int UNR>
-__global__ __launch_bounds__(256) void k_filter(const typename Key<KT>::Raw* keys,
-                                                const typename Rid<RT>::R* rids, uint64_t n,
-                                                typename Key<KT>::U dmask, Header* h,
-                                                typename Key<KT>::U* sk, typename Rid<RT>::R* sf,
-                                                uint64_t cap) {
-  using Raw = typename Key<KT>::Raw;
-  using U = typename Key<KT>::U;
-  using R = typename Rid<RT>::R;
-  constexpr int NT = 256;
-  static_assert(VEC * sizeof(Raw) == 16 || VEC == 1, "vector loads are 16 bytes");
-  const U Tk = (U)h->thr_k;
-  const R Tf = (R)h->thr_f;
-  const InputSrc<KT, RT> src{keys, rids, dmask};
-  constexpr uint64_t TILE = (uint64_t)NT * VEC * UNR;
-  const uint64_t ntiles = n / TILE;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint64_t base = t * TILE;
-    Raw v[UNR][VEC];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const uint64_t i0 = base + ((uint64_t)u * NT + threadIdx.x) * VEC;
-      if constexpr (VEC * sizeof(Raw) == 16) {
-        const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(keys + i0));
-        if constexpr (sizeof(Raw) == 4) {
-          v[u][0] = q.x; v[u][1] = q.y; v[u][2] = q.z; v[u][3] = q.w;
-        } else {
-          v[u][0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
-          v[u][1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
-        }
-      } else {
-        v[u][0] = keys[i0];
-      }
-    }
-    bool any = false;
-#pragma unroll
-    for (int u = 0; u < UNR; ++u)
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) any |= (Key<KT>::enc(v[u][e]) ^ dmask) >= Tk;
-    if (ballot(any) == 0) continue;
-#pragma unroll
-    for (int u = 0; u < UNR; ++u)
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const uint64_t i = base + ((uint64_t)u * NT + threadIdx.x) * VEC + e;
-        const U kk = Key<KT>::enc(v[u][e]) ^ dmask;
-        bool pass = kk > Tk;
-        R ff = 0;
-        if (kk >= Tk) {
-          ff = src.flip(i);
-          pass = pass || ff >= Tf;
-        }
-        emit_survivor<U, R>(pass, kk, ff, h, sk, sf, cap);
-      }
-  }
-  // remainder (fewer than one tile)
-  const uint64_t stride = (uint64_t)gridDim.x * NT;
-  for (uint64_t i = ntiles * TILE + (uint64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
-    const U kk = src.key(i);
-    bool pass = kk > Tk;
-    R ff = 0;
-    if (kk >= Tk) {
-      ff = src.flip(i);
-      pass = pass || ff >= Tf;
-    }
-    emit_survivor<U, R>(pass, kk, ff, h, sk, sf, cap);
-  }
-}
-
 // ---- one-workgroup select + sort in LDS ------------------------------------------------------
-
-template <int KT, int RT>
-struct LdsTile {
-  using U = typename Key<KT>::U;
-  using R = typename Rid<RT>::R;
-  static constexpr uint32_t CAP = (sizeof(U) + sizeof(R)) <= 8 ? 16384u : 8192u;
-  U k[CAP];
-  R f[CAP];
-};
-
-template <int KT, int RT>
-__device__ __forceinline__ void write_out(uint64_t j, typename Key<KT>::U kk,
-                                          typename Rid<RT>::R ff, typename Key<KT>::U dmask,
-                                          void* out_keys, void* out_rids) {
-  if (out_keys) static_cast<typename Key<KT>::Raw*>(out_keys)[j] = Key<KT>::dec(kk ^ dmask);
-  if (out_rids) static_cast<typename Rid<RT>::R*>(out_rids)[j] = ~ff;
-}
 
 // Selects the best k_eff of cnt (<= CAP) composites from `src` and writes them
 // sorted to the outputs.  Whole workgroup of NT threads.
@@ -308,9 +101,6 @@ struct TailArgs {
   uint64_t n;
   uint64_t dmask;
   Header* h;
-  void* sk;
-  void* sf;
-  uint64_t cap;
   void* ck;
   void* cf;
   void* tk;
@@ -459,20 +249,6 @@ __device__ bool exact_select(const Src& src, uint64_t n, uint64_t k_eff, Header*
   return grid_sync(&h->gs, G, &h->status, s_flag);
 }
 
-// merge-path split: number of elements of A among the first d outputs of
-// merge(A, B), best first, ties taken from A
-template <typename U, typename R>
-__device__ __forceinline__ uint64_t merge_split(const U* ak, const R* af, uint64_t na, const U* bk,
-                                                const R* bf, uint64_t nb, uint64_t d) {
-  uint64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
-  while (lo < hi) {
-    const uint64_t mid = (lo + hi) / 2;
-    if (cge(ak[mid], af[mid], bk[d - 1 - mid], bf[d - 1 - mid])) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
 // Sorts ck/cf[0..m) best first with all blocks and writes the outputs.
 template <int KT, int RT, int NT>
 __device__ bool sort_and_write(uint64_t m, typename Key<KT>::U* ck, typename Rid<RT>::R* cf,
@@ -568,28 +344,10 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs a) {
   __shared__ int s_flag;
   Header* h = a.h;
   const U dmask = (U)a.dmask;
-  const uint64_t C = h->surv_count;
-  int path;
-  if (a.exact_only) path = 5;
-  else if (C < a.k_eff || C > a.cap) path = 4;
-  else if (C <= LdsTile<KT, RT>::CAP) path = 2;
-  else path = 3;
-  if (blockIdx.x == 0 && threadIdx.x == 0) h->path = (uint32_t)path;
-  if (path == 2) {
-    if (blockIdx.x != 0) return;
-    const BufSrc<U, R> src{(const U*)a.sk, (const R*)a.sf};
-    lds_select_sort<KT, RT, NT>(src, (uint32_t)C, (uint32_t)a.k_eff, dmask, a.out_keys, a.out_rids,
-                                t, red, ws);
-    return;
-  }
-  bool ok;
-  if (path == 3) {
-    const BufSrc<U, R> src{(const U*)a.sk, (const R*)a.sf};
-    ok = exact_select<NT, U, R>(src, C, a.k_eff, h, (U*)a.ck, (R*)a.cf, lh, lh64, sh_u32, &s_flag);
-  } else {
-    const InputSrc<KT, RT> src{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, dmask};
-    ok = exact_select<NT, U, R>(src, a.n, a.k_eff, h, (U*)a.ck, (R*)a.cf, lh, lh64, sh_u32, &s_flag);
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) h->path = 5u;
+  const InputSrc<KT, RT> src{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, dmask};
+  const bool ok =
+      exact_select<NT, U, R>(src, a.n, a.k_eff, h, (U*)a.ck, (R*)a.cf, lh, lh64, sh_u32, &s_flag);
   if (!ok) return;
   sort_and_write<KT, RT, NT>(a.k_eff, (U*)a.ck, (R*)a.cf, (U*)a.tk, (R*)a.tf, dmask, a.out_keys,
                              a.out_rids, h, t, &s_flag);
@@ -710,41 +468,22 @@ int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, i
     return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
   }
   const SamplePlan p = plan_sample(n, k_eff, tun);
+  if (p.fast)
+    return run_sampled<KT, RT>(keys, rids, n, k_eff, order, out_keys, out_rids, ws, ws_bytes, st,
+                               tun, p);
   const WsLayout L = ws_layout(n, k_eff, sizeof(U), sizeof(R), p);
   if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return TK_EINVAL;
   Header* h = ws_ptr<Header>(ws, 0);
-  U* sample_k = ws_ptr<U>(ws, L.sample);
-  R* sample_f = ws_ptr<R>(ws, L.sample + align_up((size_t)p.blocks * p.r1 * sizeof(U), 16));
-  U* surv_k = ws_ptr<U>(ws, L.surv);
-  R* surv_f = ws_ptr<R>(ws, L.surv + align_up((size_t)p.cap * sizeof(U), 16));
   U* cand_k = ws_ptr<U>(ws, L.cand);
   R* cand_f = ws_ptr<R>(ws, L.cand + align_up((size_t)k_eff * sizeof(U), 16));
   U* tmp_k = ws_ptr<U>(ws, L.tmp);
   R* tmp_f = ws_ptr<R>(ws, L.tmp + align_up((size_t)k_eff * sizeof(U), 16));
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return TK_EHIP;
-  if (p.fast) {
-    hipLaunchKernelGGL((k_sample_local<KT, RT>), dim3(p.blocks), dim3(256), 0, st, (const Raw*)keys,
-                       (const R*)rids, n, dmask, p.S, p.r1, h, sample_k, sample_f);
-    hipLaunchKernelGGL((k_sample_final<KT, RT>), dim3(1), dim3(1024), 0, st, h,
-                       (const U*)sample_k, (const R*)sample_f, p.blocks * p.r1, p.r1);
-    const uint32_t grid = tun.filter_grid ? tun.filter_grid : (uint32_t)device_cus(dev) * 8u;
-    profile_mark(st, true);
-    if (((uintptr_t)keys & 15u) == 0) {
-      constexpr int VEC = 16 / sizeof(Raw);
-      hipLaunchKernelGGL((k_filter<KT, RT, VEC, 4>), dim3(grid), dim3(256), 0, st, (const Raw*)keys,
-                         (const R*)rids, n, dmask, h, surv_k, surv_f, p.cap);
-    } else {
-      hipLaunchKernelGGL((k_filter<KT, RT, 1, 8>), dim3(grid), dim3(256), 0, st, (const Raw*)keys,
-                         (const R*)rids, n, dmask, h, surv_k, surv_f, p.cap);
-    }
-    profile_mark(st, false);
-  } else {
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, h);
-  }
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, h);
   if (hipGetLastError() != hipSuccess) return TK_EHIP;
-  TailArgs a{keys, rids, n, (uint64_t)dmask, h, surv_k, surv_f, p.cap, cand_k, cand_f,
-             tmp_k, tmp_f, k_eff, out_keys, out_rids, p.fast ? 0 : 1};
+  TailArgs a{keys, rids, n, (uint64_t)dmask, h, cand_k, cand_f, tmp_k, tmp_f, k_eff, out_keys,
+             out_rids, 1};
   void* args[] = {&a};
   const int grid = coop_grid_tail<KT, RT>(dev);
   if (hipLaunchCooperativeKernel((const void*)k_tail<KT, RT>, dim3(grid), dim3(1024), args, 0, st) !=
