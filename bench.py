@@ -91,7 +91,7 @@ def main():
     k_eff = min(k, n)
     out_k = torch.empty(k_eff, dtype=dt, device=dev)
     out_r = torch.empty(k_eff, dtype=rid_t, device=dev)
-    ws = torch.empty(tk.workspace_size(n, k, kc, rc), dtype=torch.uint8, device=dev)
+    ws = tk.new_workspace(n, k, kc, rc, device=dev)
     torch.cuda.synchronize()
 
     def step():

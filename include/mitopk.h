@@ -69,8 +69,11 @@ size_t tk_workspace_size(uint64_t n, uint64_t k, int key_type, int rid_type);
  *   out_rowids  device array of >= min(k, n) row-ids of rid_type, or NULL
  *   out_count   host pointer, set to min(k, n) before return (may be NULL)
  *   workspace   device buffer of >= tk_workspace_size(...) bytes, 256-byte
- *               aligned; contents need no initialization and are scratch
- *               until the stream passes the call
+ *               aligned, scratch until the stream passes the call.  Zero-fill
+ *               it once before its first use: every query leaves it ready for
+ *               the next one.  Results are exact whatever it holds; a buffer
+ *               that was never zeroed only costs its first query the slower
+ *               exact path
  *   stream      hipStream_t (NULL: default stream)
  * k = 0 or n = 0 is valid and enqueues nothing.  Returns TK_OK or an error. */
 int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int key_type,
@@ -123,7 +126,9 @@ typedef struct {
   uint32_t min_sample_log2;  /* smallest sample; queries under 16x it take the exact select; 0: 12 */
   uint32_t max_sample_log2;  /* largest sample; 0: 20 */
   double sample_sigma;       /* margin of the sampled threshold; 0: 3 */
-  int32_t use_graph;         /* >= 0: capture launches in a hipGraph; < 0: launch directly */
+  int32_t use_graph;         /* >= 0: capture launches on a created stream in a hipGraph and
+                                replay it (the default stream is never captured: launches
+                                there are direct); < 0: always launch directly */
 } tk_plan_params;
 
 /* Workspace bytes for a plan (0 on invalid arguments).  Host arrays:
@@ -155,6 +160,62 @@ int tk_plan_query_times(const tk_plan* plan, double* seconds);
  * input ran instead) and queries left unfinished (must be 0). */
 int tk_plan_stats(const tk_plan* plan, uint32_t* fallbacks, uint32_t* unfinished);
 void tk_plan_destroy(tk_plan* plan);
+
+/* ---- Served form -----------------------------------------------------------------------------
+ * Continuous batching of Top-K requests over device-resident key columns
+ * with the cost gate of the paper (sec. II-B): a request is offloaded only
+ * when the estimated CPU cost exceeds the estimated GPU cost (transfer +
+ * kernel + result return) by more than a margin; otherwise it runs on the
+ * host CPU path over the column's host mirror.  A batcher thread forms
+ * micro-batches of one key type whenever one of `slots` stream slots is free,
+ * admitting requests while the slot's share of the arena has room; batches
+ * on different slots overlap on the device.  Row-ids are the global row
+ * index in the column (uint64).  Every result equals tk_topk on the same
+ * keys, whichever route and batch it took. */
+typedef struct tk_server tk_server;
+typedef struct {
+  uint32_t max_batch;   /* requests per micro-batch; 0: 256 */
+  uint32_t slots;       /* micro-batches in flight; 0: 2 */
+  double window_us;     /* wait this long for a batch to fill; 0: no wait */
+  int32_t gate;         /* 0 always GPU, 1 cost gate, 2 always CPU */
+  double margin_ms;     /* gate margin */
+  int32_t cpu_threads;  /* CPU-route workers; 0: 4 */
+  /* cost model, seconds: C_cpu = cpu_a*N + cpu_b*K*log2(K+1) + cpu_c,
+   * C_gpu = gpu_a*N + gpu_b*K + gpu_c */
+  double cpu_a, cpu_b, cpu_c, gpu_a, gpu_b, gpu_c;
+} tk_server_cfg;
+typedef struct {
+  uint64_t t_submit_ns, t_start_ns, t_done_ns;  /* host steady clock */
+  int32_t route;   /* 0 GPU, 1 CPU */
+  int32_t status;
+  uint64_t count;  /* results written */
+} tk_req_info;
+typedef struct {
+  uint64_t submitted, completed, routed_gpu, routed_cpu, batches, batched_requests;
+} tk_server_counters;
+
+/* arena: caller-owned device buffer (256-byte aligned) split among the
+ * slots; it bounds how much one micro-batch may hold. */
+int tk_server_create(const tk_server_cfg* cfg, void* arena, size_t arena_bytes, tk_server** server);
+/* d_keys: device column of n keys; h_keys: its host mirror (NULL: GPU only). */
+int tk_server_add_column(tk_server* server, const void* d_keys, const void* h_keys, uint64_t n,
+                         int key_type, uint32_t* col_id);
+/* Top-K of rows [offset, offset + n) of a column; returns at once. */
+int tk_server_submit(tk_server* server, uint32_t col, uint64_t offset, uint64_t n, uint32_t k,
+                     int order, uint64_t* req_id);
+/* Copies a finished request's keys and row-ids to host memory; TK_EAGAIN
+ * while it runs. */
+int tk_server_result(tk_server* server, uint64_t req_id, void* h_keys, uint64_t* h_rowids,
+                     tk_req_info* info);
+/* Submits `count` requests at t_arrival_s[i] seconds after the call (an
+ * open-loop arrival trace, e.g. Poisson) from the calling thread. */
+int tk_server_replay(tk_server* server, uint64_t count, const double* t_arrival_s,
+                     const uint32_t* cols, const uint64_t* offsets, const uint64_t* ns,
+                     const uint32_t* ks, const uint8_t* orders, uint64_t* req_ids);
+/* Waits until every submitted request has finished. */
+int tk_server_drain(tk_server* server);
+int tk_server_stats(tk_server* server, tk_server_counters* stats);
+void tk_server_destroy(tk_server* server);
 
 /* Multithreaded CPU Top-K over host arrays: the CPU route of the cost gate
  * (paper sec. II-B) with the same result definition.  nthreads <= 0 uses

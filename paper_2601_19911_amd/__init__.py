@@ -120,6 +120,12 @@ def workspace_size(n: int, k: int, key_type: int, rid_type: int) -> int:
     return int(lib().tk_workspace_size(n, k, key_type, rid_type))
 
 
+def new_workspace(n: int, k: int, key_type: int, rid_type: int, device="cuda"):
+    """A zero-filled workspace for tk_topk (zeroed once; queries keep it ready)."""
+    import torch
+    return torch.zeros(workspace_size(n, k, key_type, rid_type), dtype=torch.uint8, device=device)
+
+
 def topk(keys, k: int, rowids=None, order="desc", out_keys=None, out_rowids=None,
          rid_dtype=None, workspace=None, stream=None, want_keys: bool = True):
     """Top-K of device tensor ``keys`` (int32, int64 or float32), best first.
@@ -150,7 +156,7 @@ def topk(keys, k: int, rowids=None, order="desc", out_keys=None, out_rowids=None
         out_rowids = torch.empty(k_eff, dtype=rdt, device=dev)
     ws_bytes = workspace_size(n, k, kc, rc_)
     if workspace is None or workspace.numel() < ws_bytes:
-        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        workspace = torch.zeros(ws_bytes, dtype=torch.uint8, device=dev)
     cnt = ctypes.c_uint64(0)
     rc = lib().tk_topk(_ptr(keys) if n else None, _ptr(rowids), n, int(k), kc, rc_, oc,
                        _ptr(out_keys), _ptr(out_rowids), ctypes.byref(cnt),

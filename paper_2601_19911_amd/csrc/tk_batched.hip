@@ -265,7 +265,8 @@ extern "C" int tk_plan_launch(tk_plan* P, const void* keys, const void* rowids, 
   }
   const bool same = P->have_graph && P->g_keys == gk && P->g_rids == gr && P->g_ok == go &&
                     P->g_or == gq && P->g_stream == st;
-  const bool graph = P->params.use_graph >= 0;
+  // stream capture needs a created stream; on the default stream launch directly
+  const bool graph = P->params.use_graph >= 0 && st != nullptr;
   if (!graph) return engine_launch(a, P->rid_type, P->key_type, P->params.engine_grid, st);
   if (!same) {
     if (P->have_graph) {

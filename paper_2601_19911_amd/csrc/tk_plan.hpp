@@ -15,7 +15,7 @@ inline uint32_t lds_cap_for(uint32_t cb) { return cb <= 8 ? 16384u : 8192u; }
 
 constexpr uint32_t SAMPLE_CHUNK = 16;        // contiguous keys per sample chunk
 constexpr uint32_t SAMPLE_PER_BLOCK = 1024;  // sample keys per local-select block
-constexpr uint32_t SAMPLE_FINAL_MAX = 16384; // candidates the final select can hold
+constexpr uint32_t SAMPLE_FINAL_MAX = 4096;  // candidates the final select holds in registers
 
 struct SamplePlan {
   bool fast = false;     // sample -> filter -> tail; else exact radix select

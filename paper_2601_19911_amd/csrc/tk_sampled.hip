@@ -120,15 +120,28 @@ __device__ void sample_body(const SampArgs& a, SelScratch& sc) {
   __syncthreads();
   if (!last) return;
   __threadfence();
-  const uint64_t m = (uint64_t)gridDim.x * a.r1;
-  const BufSrc<U, R> cs{ck, cf};
+  // at most SAMPLE_FINAL_MAX candidates: 16 per thread, held in registers
+  constexpr int EF = SAMPLE_FINAL_MAX / NT;
+  const uint32_t m = gridDim.x * a.r1;
+  U k2[EF];
+  R f2[EF];
+  int nv = 0;
   U cmin = (U)~(U)0;
-  for (uint64_t i = threadIdx.x; i < m; i += NT) {
-    const U u = cs.key(i);
-    cmin = u < cmin ? u : cmin;
+#pragma unroll
+  for (int e = 0; e < EF; ++e) {
+    const uint32_t j = (uint32_t)e * NT + threadIdx.x;
+    if (j < m) {
+      k2[e] = ck[j];
+      f2[e] = cf[j];
+      nv = e + 1;
+      cmin = k2[e] < cmin ? k2[e] : cmin;
+    } else {
+      k2[e] = 0;
+      f2[e] = 0;
+    }
   }
   const U base2 = block_min<NT, U>(cmin, sc);
-  const GlobElems<NT, BufSrc<U, R>> el2{cs, m};
+  const RegElems<U, R, EF> el2{k2, f2, nv};
   const Sel<U, R> s2 = block_radix_select<NT, U, R>(el2, a.r1, base2, sc);
   if (threadIdx.x == 0) {
     h->thr_k = (unsigned long long)(U)(s2.base + s2.P);
@@ -257,6 +270,50 @@ __device__ void select_sort_write(const TailArgs1& a, const Src& src, uint64_t n
   }
 }
 
+// Survivors that fit the registers of the workgroup (16 per thread) are
+// loaded once and selected there.
+constexpr int TAIL_E = 16;
+
+template <int KT, int RT>
+__device__ void select_sort_write_regs(const TailArgs1& a, uint32_t C, typename Key<KT>::U base,
+                                       LdsTile<KT, RT>& t, SelScratch& sc) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr int NT = TAIL_NT, E = TAIL_E;
+  constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
+  const U dmask = (U)a.dmask;
+  const U* sk = static_cast<const U*>(a.sk);
+  const R* sf = static_cast<const R*>(a.sf);
+  U k[E];
+  R f[E];
+  int nv = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t j = (uint32_t)e * NT + threadIdx.x;
+    if (j < C) {
+      k[e] = sk[j];
+      f[e] = sf[j];
+      nv = e + 1;
+    } else {
+      k[e] = 0;
+      f[e] = 0;
+    }
+  }
+  auto emit = [&](uint64_t j, U u, R f_) { write_out<KT, RT>(j, u, f_, dmask, a.out_keys, a.out_rids); };
+  const RegElems<U, R, E> el{k, f, nv};
+  const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.k_eff, base, sc);
+  if (a.k_eff <= CAP) {
+    block_compact_regs<NT, U, R, E>(el, s, a.k_eff, t.k, t.f, sc);
+    block_sort_emit<NT, U, R>(a.k_eff, true, t.k, t.f, CAP, nullptr, nullptr, nullptr, nullptr, emit);
+  } else {
+    U* ck = static_cast<U*>(a.ck);
+    R* cf = static_cast<R*>(a.cf);
+    block_compact_regs<NT, U, R, E>(el, s, a.k_eff, ck, cf, sc);
+    block_sort_emit<NT, U, R>(a.k_eff, false, t.k, t.f, CAP, ck, cf, static_cast<U*>(a.tk),
+                              static_cast<R*>(a.tf), emit);
+  }
+}
+
 template <int KT, int RT>
 __device__ void tail_body(const TailArgs1& a, LdsTile<KT, RT>& t, SelScratch& sc) {
   using U = typename Key<KT>::U;
@@ -264,7 +321,9 @@ __device__ void tail_body(const TailArgs1& a, LdsTile<KT, RT>& t, SelScratch& sc
   Header* h = a.h;
   const uint64_t C = h->surv_count;
   const bool ok = C >= a.k_eff && C <= a.cap;
-  if (ok) {
+  if (ok && C <= (uint64_t)TAIL_NT * TAIL_E) {
+    select_sort_write_regs<KT, RT>(a, (uint32_t)C, (U)h->thr_k, t, sc);
+  } else if (ok) {
     const BufSrc<U, R> src{static_cast<const U*>(a.sk), static_cast<const R*>(a.sf)};
     select_sort_write<KT, RT>(a, src, C, (U)h->thr_k, t, sc);
   } else {

@@ -161,14 +161,27 @@ struct RegElems {
   }
 };
 
-// A global array seen through a source (key image and flipped row-id by index).
+// A global array seen through a source (key image and flipped row-id by
+// index).  Keys are read four at a time so that each thread has several loads
+// in flight.
 template <int NT, typename Src>
 struct GlobElems {
   const Src& src;
   uint64_t n;
   template <typename Fn>
   __device__ __forceinline__ void each(Fn&& fn) const {
-    for (uint64_t i = threadIdx.x; i < n; i += NT) fn(src.key(i), [&]() { return src.flip(i); });
+    using U = decltype(src.key(0));
+    uint64_t i = threadIdx.x;
+    for (; i + 3 * NT < n; i += 4 * NT) {
+      const U k0 = src.key(i), k1 = src.key(i + NT), k2 = src.key(i + 2 * NT),
+              k3 = src.key(i + 3 * NT);
+      const uint64_t i0 = i;
+      fn(k0, [&]() { return src.flip(i0); });
+      fn(k1, [&]() { return src.flip(i0 + NT); });
+      fn(k2, [&]() { return src.flip(i0 + 2 * NT); });
+      fn(k3, [&]() { return src.flip(i0 + 3 * NT); });
+    }
+    for (; i < n; i += NT) fn(src.key(i), [&]() { return src.flip(i); });
   }
 };
 

@@ -1,0 +1,565 @@
+// Served form: continuous batching of Top-K requests over device-resident key
+// columns, with the cost-accounted gate of the paper (sec. II-B, the "Risky
+// Gate"): a request goes to the GPU only when the estimated CPU cost exceeds
+// the estimated offload cost by more than a margin; otherwise it runs on the
+// host with the multithreaded CPU path.  Host code only.
+//
+// Threads: the caller submits; a batcher thread forms micro-batches of one key
+// type whenever a slot (stream + device arena + pinned staging) is free,
+// admitting requests while the slot's arena has room, and enqueues the batch
+// engine on that slot's stream followed by an asynchronous copy of the
+// results to pinned host memory and an event; a completion thread waits on
+// the slots' events in launch order and publishes the results; CPU workers run
+// the gated-off requests.  With two or more slots, micro-batches overlap on
+// the device, and requests that arrive while others run join the next batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "mitopk.h"
+#include "tk_engine.hpp"
+#include "tk_internal.hpp"
+#include "tk_plan.hpp"
+
+using namespace tk;
+
+namespace {
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Column {
+  const void* d_keys;
+  const void* h_keys;
+  uint64_t n;
+  int key_type;
+};
+
+struct Req {
+  uint64_t id;
+  uint32_t col;
+  uint64_t offset, n;
+  uint32_t k;
+  int order;
+  int route;  // 0 GPU, 1 CPU
+  std::atomic<int> state{0};  // 0 queued, 1 running, 2 done, 3 taken
+  int status = 0;
+  uint64_t t_submit = 0, t_start = 0, t_done = 0;
+  std::vector<uint8_t> out_keys;
+  std::vector<uint64_t> out_rids;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  char* arena = nullptr;      // device
+  size_t arena_bytes = 0;
+  char* h_stage = nullptr;    // pinned: descriptors, queue, sample map
+  char* h_out = nullptr;      // pinned: results
+  size_t stage_bytes = 0, out_bytes = 0;
+  std::vector<uint64_t> reqs;
+  std::vector<uint64_t> out_off;
+  uint64_t out_rid_base = 0;   // where row-ids start in h_out
+  int key_type = 0;
+  bool busy = false;
+};
+
+}  // namespace
+
+struct tk_server {
+  tk_server_cfg cfg{};
+  std::vector<Column> cols;
+  std::deque<Req> reqs;  // stable addresses; index = request id
+  std::mutex mu;
+  std::condition_variable cv_batch, cv_cpu, cv_done, cv_slot;
+  std::deque<uint64_t> gpu_q[3];  // per key type
+  std::deque<uint64_t> cpu_q;
+  std::vector<Slot> slots;
+  std::deque<int> inflight;  // slot indices in launch order
+  std::vector<std::thread> workers;
+  std::thread batcher, completer;
+  bool stop = false;
+  uint64_t submitted = 0, completed = 0, n_gpu = 0, n_cpu = 0, n_batches = 0, n_batched = 0;
+  int dev = 0;
+};
+
+namespace {
+
+double cpu_cost(const tk_server_cfg& c, uint64_t n, uint32_t k) {
+  return c.cpu_a * (double)n + c.cpu_b * (double)k * std::log2((double)k + 1.0) + c.cpu_c;
+}
+double gpu_cost(const tk_server_cfg& c, uint64_t n, uint32_t k) {
+  return c.gpu_a * (double)n + c.gpu_b * (double)k + c.gpu_c;
+}
+
+void finish(tk_server* s, uint64_t id) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->reqs[id].t_done = now_ns();
+    s->reqs[id].state.store(2);
+    ++s->completed;
+  }
+  s->cv_done.notify_all();
+}
+
+void cpu_worker(tk_server* s) {
+  for (;;) {
+    uint64_t id;
+    Req* rp;
+    Column c;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_cpu.wait(lk, [&] { return s->stop || !s->cpu_q.empty(); });
+      if (s->stop && s->cpu_q.empty()) return;
+      id = s->cpu_q.front();
+      s->cpu_q.pop_front();
+      rp = &s->reqs[id];
+      c = s->cols[rp->col];
+    }
+    Req& r = *rp;
+    r.t_start = now_ns();
+    const uint32_t kb = c.key_type == TK_KEY_I64 ? 8 : 4;
+    const uint64_t ke = std::min<uint64_t>(r.k, r.n);
+    r.out_keys.resize(ke * kb);
+    r.out_rids.resize(ke);
+    uint64_t cnt = 0;
+    r.status = tk_cpu_topk(static_cast<const char*>(c.h_keys) + r.offset * kb, nullptr, r.n, r.k,
+                           c.key_type, TK_RID_U64, r.order, r.out_keys.data(), r.out_rids.data(),
+                           &cnt, 1);
+    for (auto& x : r.out_rids) x += r.offset;
+    finish(s, id);
+  }
+}
+
+// Lays out a micro-batch in a slot; returns false if it does not fit.
+struct BatchBuild {
+  std::vector<QDesc> qd;
+  std::vector<Item> items;
+  std::vector<uint2> prep;
+  std::vector<uint64_t> out_off;
+  size_t off_qs, off_qd, off_items, off_prep, off_out_k, off_out_r, end;
+};
+
+struct Taken {
+  Req* r;
+  const void* d_keys;
+  uint64_t offset, n;
+  uint32_t k;
+  int order;
+};
+
+bool build_batch(const std::vector<Taken>& ids, int key_type, size_t arena_bytes, BatchBuild& b,
+                 size_t* needed) {
+  const uint32_t kb = key_type == TK_KEY_I64 ? 8 : 4, rb = 8;
+  const uint32_t q = (uint32_t)ids.size();
+  Tuning t = current_tuning();
+  t.force_exact = 0;
+  t.force_cap = 0;
+  t.min_sample_log2 = 12;
+  b.qd.assign(q, QDesc{});
+  b.items.clear();
+  b.prep.clear();
+  b.out_off.assign(q + 1, 0);
+  for (uint32_t i = 0; i < q; ++i)
+    b.out_off[i + 1] = b.out_off[i] + std::min<uint64_t>(ids[i].k, ids[i].n);
+  size_t off = sizeof(EngineCtl);
+  b.off_qs = off;
+  off = align_up(off + q * sizeof(QState), 256);
+  b.off_qd = off;
+  off = align_up(off + q * sizeof(QDesc), 256);
+  std::vector<SamplePlan> sp(q);
+  for (uint32_t i = 0; i < q; ++i) {
+    const Taken& r = ids[i];
+    QDesc& d = b.qd[i];
+    d.n = r.n;
+    d.k_eff = (uint32_t)std::min<uint64_t>(r.k, r.n);
+    d.order = (uint8_t)r.order;
+    d.key_type = (uint8_t)key_type;
+    d.keys = (uint64_t)(uintptr_t)(static_cast<const char*>(r.d_keys) + r.offset * kb);
+    d.has_rids = 0;
+    d.rid_base = r.offset;
+    d.has_out_keys = 1;
+    d.has_out_rids = 1;
+    if (d.k_eff == 0) {
+      d.cls = CLS_EMPTY;
+      continue;
+    }
+    sp[i] = plan_sample(d.n, d.k_eff, t);
+    if (sp[i].fast) {
+      d.cls = CLS_SAMPLED;
+      d.r1 = sp[i].r1;
+      d.S = sp[i].S;
+      d.samp_blocks = sp[i].blocks;
+      d.cap = sp[i].cap;
+      d.tile_len = tile_len_for(kb);
+      d.ntiles = (uint32_t)((d.n + d.tile_len - 1) / d.tile_len);
+    } else {
+      d.cls = CLS_EXACT;
+    }
+  }
+  for (uint32_t i = 0; i < q; ++i) {
+    const QDesc& d = b.qd[i];
+    if (d.cls == CLS_SAMPLED) {
+      for (uint32_t tt = 0; tt < d.ntiles; ++tt) b.items.push_back(Item{ITEM_TILE, i, tt, 0});
+      for (uint32_t bb = 0; bb < d.samp_blocks; ++bb) b.prep.push_back(make_uint2(i, bb));
+    }
+  }
+  for (uint32_t i = 0; i < q; ++i)
+    if (b.qd[i].cls == CLS_EXACT) b.items.push_back(Item{ITEM_EXACT, i, 0, 0});
+  b.off_items = off;
+  off = align_up(off + b.items.size() * sizeof(Item), 256);
+  b.off_prep = off;
+  off = align_up(off + b.prep.size() * sizeof(uint2), 256);
+  b.off_out_k = off;
+  off = align_up(off + b.out_off[q] * kb, 256);
+  b.off_out_r = off;
+  off = align_up(off + b.out_off[q] * rb, 256);
+  for (uint32_t i = 0; i < q; ++i) {
+    QDesc& d = b.qd[i];
+    d.out_keys = b.off_out_k + b.out_off[i] * kb;  // relative to the arena (base added at launch)
+    d.out_rids = b.off_out_r + b.out_off[i] * rb;
+    if (d.cls != CLS_EMPTY) off += layout_query(d, off, kb, rb, sp[i]);
+  }
+  b.end = off;
+  if (needed) *needed = off;
+  return off <= arena_bytes;
+}
+
+void batcher_loop(tk_server* s) {
+  hipSetDevice(s->dev);
+  const double window_ns = s->cfg.window_us * 1e3;
+  for (;;) {
+    int slot = -1;
+    std::vector<Taken> take;
+    int kt = 0;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_batch.wait(lk, [&] {
+        if (s->stop) return true;
+        bool any = !s->gpu_q[0].empty() || !s->gpu_q[1].empty() || !s->gpu_q[2].empty();
+        if (!any) return false;
+        for (auto& sl : s->slots)
+          if (!sl.busy) return true;
+        return false;
+      });
+      if (s->stop) return;
+      // the key type whose oldest request waited longest
+      uint64_t best = UINT64_MAX;
+      for (int t = 0; t < 3; ++t)
+        if (!s->gpu_q[t].empty() && s->reqs[s->gpu_q[t].front()].t_submit < best) {
+          best = s->reqs[s->gpu_q[t].front()].t_submit;
+          kt = t;
+        }
+      // a short window lets a batch fill when it would otherwise be tiny
+      if (window_ns > 0 && s->gpu_q[kt].size() < s->cfg.max_batch) {
+        const uint64_t deadline = best + (uint64_t)window_ns;
+        const uint64_t tn = now_ns();
+        if (tn < deadline) {
+          lk.unlock();
+          std::this_thread::sleep_for(std::chrono::nanoseconds(std::min<uint64_t>(deadline - tn, 200000)));
+          lk.lock();
+          if (s->stop) return;
+        }
+      }
+      for (size_t i = 0; i < s->slots.size(); ++i)
+        if (!s->slots[i].busy) {
+          slot = (int)i;
+          break;
+        }
+      if (slot < 0) continue;
+      auto& q = s->gpu_q[kt];
+      while (!q.empty() && take.size() < s->cfg.max_batch) {
+        Req& r = s->reqs[q.front()];
+        take.push_back(Taken{&r, s->cols[r.col].d_keys, r.offset, r.n, r.k, r.order});
+        q.pop_front();
+      }
+      s->slots[slot].busy = true;
+    }
+    Slot& sl = s->slots[slot];
+    // admission by memory: shrink the batch until it fits the slot's arena
+    BatchBuild b;
+    size_t need = 0;
+    auto id_of = [&](const Taken& t) { return (uint64_t)(t.r - &s->reqs[0]); };
+    while (!take.empty() && !build_batch(take, kt, sl.arena_bytes, b, &need)) {
+      if (take.size() == 1) break;
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->gpu_q[kt].push_front(take.back().r->id);
+      take.pop_back();
+    }
+    (void)id_of;
+    const uint32_t kb = kt == TK_KEY_I64 ? 8 : 4;
+    const size_t stage = b.off_prep + b.prep.size() * sizeof(uint2);
+    const size_t outb = (b.off_out_r + b.out_off.back() * 8) - b.off_out_k;
+    if (take.empty() || need > sl.arena_bytes || stage > sl.stage_bytes || outb > sl.out_bytes) {
+      // a single request larger than a slot: it goes to the CPU path instead
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (const Taken& t : take) {
+        t.r->route = 1;
+        s->cpu_q.push_back(t.r->id);
+      }
+      sl.busy = false;
+      s->cv_cpu.notify_all();
+      continue;
+    }
+    const uint64_t t0 = now_ns();
+    std::memset(sl.h_stage, 0, stage);
+    std::memcpy(sl.h_stage + b.off_qd, b.qd.data(), b.qd.size() * sizeof(QDesc));
+    std::memcpy(sl.h_stage + b.off_items, b.items.data(), b.items.size() * sizeof(Item));
+    std::memcpy(sl.h_stage + b.off_prep, b.prep.data(), b.prep.size() * sizeof(uint2));
+    EngineArgs a{};
+    a.qd = reinterpret_cast<const QDesc*>(sl.arena + b.off_qd);
+    a.qs = reinterpret_cast<QState*>(sl.arena + b.off_qs);
+    a.ctl = reinterpret_cast<EngineCtl*>(sl.arena);
+    a.items = reinterpret_cast<const Item*>(sl.arena + b.off_items);
+    a.prep = reinterpret_cast<const uint2*>(sl.arena + b.off_prep);
+    a.scratch = sl.arena;
+    a.nitems = (uint32_t)b.items.size();
+    a.nq = (uint32_t)take.size();
+    a.nprep = (uint32_t)b.prep.size();
+    a.keys_base = 0;
+    a.rids_base = 0;
+    a.out_keys_base = (uint64_t)(uintptr_t)sl.arena;
+    a.out_rids_base = (uint64_t)(uintptr_t)sl.arena;
+    int rc = hipMemcpyAsync(sl.arena, sl.h_stage, stage, hipMemcpyHostToDevice, sl.stream) == hipSuccess
+                 ? TK_OK : TK_EHIP;
+    if (rc == TK_OK && a.nitems) rc = engine_launch(a, RID_U64, kt, 0, sl.stream);
+    if (rc == TK_OK)
+      rc = hipMemcpyAsync(sl.h_out, sl.arena + b.off_out_k, outb, hipMemcpyDeviceToHost, sl.stream) ==
+                   hipSuccess ? TK_OK : TK_EHIP;
+    if (rc == TK_OK) rc = hipEventRecord(sl.done, sl.stream) == hipSuccess ? TK_OK : TK_EHIP;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      sl.reqs.clear();
+      for (const Taken& t : take) sl.reqs.push_back(t.r->id);
+      sl.out_off = b.out_off;
+      sl.out_rid_base = b.off_out_r - b.off_out_k;
+      sl.key_type = kt;
+      for (const Taken& t : take) {
+        t.r->t_start = t0;
+        t.r->status = rc;
+        t.r->state.store(1);
+      }
+      s->inflight.push_back(slot);
+      ++s->n_batches;
+      s->n_batched += take.size();
+      (void)kb;
+    }
+    s->cv_slot.notify_all();
+  }
+}
+
+void completer_loop(tk_server* s) {
+  hipSetDevice(s->dev);
+  for (;;) {
+    int slot;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_slot.wait(lk, [&] { return s->stop || !s->inflight.empty(); });
+      if (s->inflight.empty()) return;
+      slot = s->inflight.front();
+      s->inflight.pop_front();
+    }
+    Slot& sl = s->slots[slot];
+    const hipError_t e = hipEventSynchronize(sl.done);
+    const uint32_t kb = sl.key_type == TK_KEY_I64 ? 8 : 4;
+    const uint64_t tdone = now_ns();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (size_t i = 0; i < sl.reqs.size(); ++i) {
+        Req& r = s->reqs[sl.reqs[i]];
+        const uint64_t a = sl.out_off[i], c = sl.out_off[i + 1] - a;
+        r.out_keys.assign(sl.h_out + a * kb, sl.h_out + (a + c) * kb);
+        r.out_rids.resize(c);
+        std::memcpy(r.out_rids.data(), sl.h_out + sl.out_rid_base + a * 8, c * 8);
+        if (e != hipSuccess) r.status = TK_EHIP;
+        r.t_done = tdone;
+        r.state.store(2);
+        ++s->completed;
+      }
+      sl.reqs.clear();
+      sl.busy = false;
+    }
+    s->cv_done.notify_all();
+    s->cv_batch.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" int tk_server_create(const tk_server_cfg* cfg, void* arena, size_t arena_bytes,
+                                tk_server** out) {
+  if (!cfg || !out || !arena || ((uintptr_t)arena & 255u)) return TK_EINVAL;
+  tk_server* s = new (std::nothrow) tk_server;
+  if (!s) return TK_ENOMEM;
+  s->cfg = *cfg;
+  if (s->cfg.max_batch == 0) s->cfg.max_batch = 256;
+  if (s->cfg.slots == 0) s->cfg.slots = 2;
+  if (s->cfg.cpu_threads <= 0) s->cfg.cpu_threads = 4;
+  if (hipGetDevice(&s->dev) != hipSuccess) {
+    delete s;
+    return TK_EHIP;
+  }
+  const size_t per = (arena_bytes / s->cfg.slots) & ~(size_t)255;
+  s->slots.resize(s->cfg.slots);
+  for (uint32_t i = 0; i < s->cfg.slots; ++i) {
+    Slot& sl = s->slots[i];
+    sl.arena = static_cast<char*>(arena) + i * per;
+    sl.arena_bytes = per;
+    sl.stage_bytes = std::min<size_t>(per, (size_t)64 << 20);
+    sl.out_bytes = std::min<size_t>(per, (size_t)64 << 20);
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&sl.h_stage, sl.stage_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sl.h_out, sl.out_bytes, hipHostMallocDefault) != hipSuccess) {
+      tk_server_destroy(s);
+      return TK_EHIP;
+    }
+  }
+  s->batcher = std::thread(batcher_loop, s);
+  s->completer = std::thread(completer_loop, s);
+  for (int i = 0; i < s->cfg.cpu_threads; ++i) s->workers.emplace_back(cpu_worker, s);
+  *out = s;
+  return TK_OK;
+}
+
+extern "C" int tk_server_add_column(tk_server* s, const void* d_keys, const void* h_keys,
+                                    uint64_t n, int key_type, uint32_t* col) {
+  if (!s || !col || key_type < 0 || key_type > 2 || (n && !d_keys)) return TK_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->cols.push_back(Column{d_keys, h_keys, n, key_type});
+  *col = (uint32_t)(s->cols.size() - 1);
+  return TK_OK;
+}
+
+extern "C" int tk_server_submit(tk_server* s, uint32_t col, uint64_t offset, uint64_t n,
+                                uint32_t k, int order, uint64_t* req_id) {
+  if (!s || !req_id || order < 0 || order > 1) return TK_EINVAL;
+  const uint64_t t = now_ns();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (col >= s->cols.size() || offset + n > s->cols[col].n) return TK_EINVAL;
+  const Column& c = s->cols[col];
+  s->reqs.emplace_back();
+  const uint64_t id = s->reqs.size() - 1;
+  Req& r = s->reqs.back();
+  r.id = id;
+  r.col = col;
+  r.offset = offset;
+  r.n = n;
+  r.k = k;
+  r.order = order;
+  r.t_submit = t;
+  // the gate: CPU unless offloading saves more than the margin
+  int route = 0;
+  if (s->cfg.gate == 2) route = 1;
+  else if (s->cfg.gate == 1 && c.h_keys) {
+    const double saving = cpu_cost(s->cfg, n, k) - gpu_cost(s->cfg, n, k);
+    route = saving > s->cfg.margin_ms * 1e-3 ? 0 : 1;
+  }
+  if (route == 1 && !c.h_keys) route = 0;
+  r.route = route;
+  ++s->submitted;
+  if (route == 1) {
+    ++s->n_cpu;
+    s->cpu_q.push_back(id);
+    s->cv_cpu.notify_one();
+  } else {
+    ++s->n_gpu;
+    s->gpu_q[c.key_type].push_back(id);
+    s->cv_batch.notify_one();
+  }
+  *req_id = id;
+  return TK_OK;
+}
+
+extern "C" int tk_server_result(tk_server* s, uint64_t id, void* h_keys, uint64_t* h_rowids,
+                                tk_req_info* info) {
+  if (!s) return TK_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (id >= s->reqs.size()) return TK_EINVAL;
+  Req& r = s->reqs[id];
+  if (r.state.load() < 2) return TK_EAGAIN;
+  if (h_keys) std::memcpy(h_keys, r.out_keys.data(), r.out_keys.size());
+  if (h_rowids) std::memcpy(h_rowids, r.out_rids.data(), r.out_rids.size() * 8);
+  if (info) {
+    info->t_submit_ns = r.t_submit;
+    info->t_start_ns = r.t_start;
+    info->t_done_ns = r.t_done;
+    info->route = r.route;
+    info->status = r.status;
+    info->count = r.out_rids.size();
+  }
+  return r.status;
+}
+
+extern "C" int tk_server_drain(tk_server* s) {
+  if (!s) return TK_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->completed >= s->submitted; });
+  return TK_OK;
+}
+
+extern "C" int tk_server_stats(tk_server* s, tk_server_counters* st) {
+  if (!s || !st) return TK_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  st->submitted = s->submitted;
+  st->completed = s->completed;
+  st->routed_gpu = s->n_gpu;
+  st->routed_cpu = s->n_cpu;
+  st->batches = s->n_batches;
+  st->batched_requests = s->n_batched;
+  return TK_OK;
+}
+
+extern "C" int tk_server_replay(tk_server* s, uint64_t count, const double* t_arrival_s,
+                                const uint32_t* cols, const uint64_t* offsets, const uint64_t* ns,
+                                const uint32_t* ks, const uint8_t* orders, uint64_t* req_ids) {
+  if (!s || !t_arrival_s || !cols || !offsets || !ns || !ks || !orders || !req_ids) return TK_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint64_t i = 0; i < count; ++i) {
+    const auto due = t0 + std::chrono::nanoseconds((int64_t)(t_arrival_s[i] * 1e9));
+    while (std::chrono::steady_clock::now() < due) {
+      const auto left = due - std::chrono::steady_clock::now();
+      if (left > std::chrono::microseconds(200)) std::this_thread::sleep_for(left - std::chrono::microseconds(100));
+    }
+    const int rc = tk_server_submit(s, cols[i], offsets[i], ns[i], ks[i], orders[i], &req_ids[i]);
+    if (rc != TK_OK) return rc;
+  }
+  return TK_OK;
+}
+
+extern "C" void tk_server_destroy(tk_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_batch.notify_all();
+  s->cv_cpu.notify_all();
+  s->cv_slot.notify_all();
+  if (s->batcher.joinable()) s->batcher.join();
+  if (s->completer.joinable()) s->completer.join();
+  for (auto& w : s->workers)
+    if (w.joinable()) w.join();
+  for (auto& sl : s->slots) {
+    if (sl.stream) {
+      hipStreamSynchronize(sl.stream);
+      hipStreamDestroy(sl.stream);
+    }
+    if (sl.done) hipEventDestroy(sl.done);
+    if (sl.h_stage) hipHostFree(sl.h_stage);
+    if (sl.h_out) hipHostFree(sl.h_out);
+  }
+  delete s;
+}

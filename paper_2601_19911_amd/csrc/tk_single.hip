@@ -400,13 +400,13 @@ void profile_mark(hipStream_t st, bool begin) {
   if (begin && g_prof.used + 2 > g_prof.ev.size()) return;
   const uint32_t slot = begin ? g_prof.used : g_prof.used + 1;
   if (!begin && slot >= g_prof.ev.size()) return;
-  hipEventRecord(g_prof.ev[slot], st);
+  (void)hipEventRecord(g_prof.ev[slot], st);
   if (!begin) g_prof.used += 2;
 }
 
 int profile_begin(uint32_t max_launches) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
-  for (auto e : g_prof.ev) hipEventDestroy(e);
+  for (auto e : g_prof.ev) (void)hipEventDestroy(e);
   g_prof.ev.assign(2 * (size_t)max_launches, nullptr);
   for (auto& e : g_prof.ev)
     if (hipEventCreate(&e) != hipSuccess) return TK_EHIP;

@@ -1,0 +1,98 @@
+"""Served form: every request's result equals the oracle (and tk_topk) on the
+same rows, alone or in the mix, through either route of the gate."""
+import numpy as np
+import pytest
+
+import inputgen
+import oracle
+from tests.gpu_util import assert_same, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+import paper_2601_19911_amd as tk
+from paper_2601_19911_amd.serve import GATE_COST, GATE_CPU, GATE_GPU, Server
+
+
+def _columns(n):
+    cols = []
+    for kind, seed in ((inputgen.KIND_U_I32, 1), (inputgen.KIND_U_I64, 2), (inputgen.KIND_U_F32, 3)):
+        h = inputgen.generate(kind, seed, n)
+        cols.append((to_dev(h), h))
+    return cols
+
+
+def _requests(rng, count, n_col):
+    reqs = []
+    for _ in range(count):
+        col = int(rng.integers(0, 3))
+        n = int(2 ** rng.uniform(10, 20))
+        off = int(rng.integers(0, n_col - n))
+        k = int(rng.choice([1, 10, 100, 1000, 10000]))
+        reqs.append((col, off, n, k, int(rng.integers(0, 2))))
+    return reqs
+
+
+def _expect(host_cols, col, off, n, k, order):
+    keys = host_cols[col][off:off + n]
+    ek, er = oracle.topk(keys, None, k, order, rid_dtype=np.uint64)
+    return ek, er + np.uint64(off)
+
+
+@pytest.mark.parametrize("gate", [GATE_GPU, GATE_COST, GATE_CPU])
+def test_served_results_match_oracle(gate):
+    import torch
+    ncol = 1 << 21
+    cols = _columns(ncol)
+    host = [h for _, h in cols]
+    cost = {"cpu_a": 2e-9, "cpu_b": 5e-9, "cpu_c": 5e-6, "gpu_a": 2e-10, "gpu_b": 1e-9,
+            "gpu_c": 60e-6}
+    srv = Server(arena_bytes=512 << 20, max_batch=64, slots=2, gate=gate, cost=cost)
+    ids = [srv.add_column(d, h) for d, h in cols]
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(gate + 7)
+    reqs = _requests(rng, 120, ncol)
+    say(f"serving {len(reqs)} requests, gate={gate}")
+    rid = [srv.submit(ids[c], off, n, k, o) for (c, off, n, k, o) in reqs]
+    srv.drain()
+    st = srv.stats()
+    say(f"stats {st}")
+    assert st["completed"] == len(reqs)
+    routes = []
+    for (c, off, n, k, o), r in zip(reqs, rid):
+        got = srv.result(r, c, min(k, n))
+        assert got is not None
+        ok, orr, info = got
+        routes.append(info.route)
+        ek, er = _expect(host, c, off, n, k, o)
+        assert_same(ok, orr, ek, er, what=f"served col={c} off={off} n={n} k={k} o={o} route={info.route}")
+    if gate == GATE_CPU:
+        assert all(r == 1 for r in routes)
+    if gate == GATE_GPU:
+        assert all(r == 0 for r in routes)
+    srv.close()
+
+
+def test_served_same_alone_and_in_mix():
+    """A request gives the same result submitted alone and inside a busy mix."""
+    import torch
+    ncol = 1 << 22
+    cols = _columns(ncol)
+    host = [h for _, h in cols]
+    srv = Server(arena_bytes=512 << 20, max_batch=32, slots=3, gate=GATE_GPU)
+    ids = [srv.add_column(d, h) for d, h in cols]
+    probe = (1, 12345, 1 << 21, 1000, 0)
+    alone = srv.submit(ids[probe[0]], *probe[1:])
+    srv.drain()
+    a = srv.result(alone, probe[0], 1000)
+    rng = np.random.default_rng(3)
+    mix = _requests(rng, 200, ncol)
+    rids = [srv.submit(ids[c], off, n, k, o) for (c, off, n, k, o) in mix[:100]]
+    inmix = srv.submit(ids[probe[0]], *probe[1:])
+    rids += [srv.submit(ids[c], off, n, k, o) for (c, off, n, k, o) in mix[100:]]
+    srv.drain()
+    b = srv.result(inmix, probe[0], 1000)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    ek, er = _expect(host, *probe)
+    assert_same(a[0], a[1], ek, er, what="alone")
+    assert srv.stats()["batches"] >= 2
+    srv.close()

@@ -147,8 +147,7 @@ def test_paths_are_taken_and_exact():
     exp = oracle.topk(keys, None, 1000, oracle.DESC)
 
     def go(expect_path):
-        ws = torch.empty(tk.workspace_size(n, 1000, tk.TK_KEY_F32, tk.TK_RID_U32), dtype=torch.uint8,
-                         device="cuda")
+        ws = tk.new_workspace(n, 1000, tk.TK_KEY_F32, tk.TK_RID_U32)
         ok, orr = tk.topk(kd, 1000, workspace=ws)
         torch.cuda.synchronize()
         info = tk.query_info(ws)
@@ -168,9 +167,29 @@ def test_paths_are_taken_and_exact():
     go(2)
 
 
+def test_garbage_workspace_is_still_exact():
+    """A workspace that was never zeroed: the first query may take the exact
+    path, every result is exact, and the second query is back on the fast path."""
+    import torch
+    n = 1 << 20
+    keys = inputgen.generate(inputgen.KIND_U_I32, 31, n)
+    exp = oracle.topk(keys, None, 500, oracle.DESC)
+    kd = to_dev(keys)
+    ws = torch.full((tk.workspace_size(n, 500, tk.TK_KEY_I32, tk.TK_RID_U32),), 0xA5,
+                    dtype=torch.uint8, device="cuda")
+    for i in range(2):
+        ok, orr = tk.topk(kd, 500, workspace=ws)
+        torch.cuda.synchronize()
+        assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"garbage workspace call {i}")
+        info = tk.query_info(ws)
+        say(f"call {i}: {info}")
+        if i == 1:
+            assert info["path"] == 2
+
+
 def test_workspace_reuse_across_queries():
     import torch
-    ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    ws = torch.zeros(64 << 20, dtype=torch.uint8, device="cuda")
     rng = np.random.default_rng(5)
     for i in range(6):
         n = int(rng.integers(1 << 18, 1 << 21))
