@@ -440,37 +440,56 @@ int engine_grid(int dev) {
 }
 
 template <int RT, int KTF>
-void launch_engine(const EngineArgs& a, uint32_t grid_override, int dev, hipStream_t st) {
-  int grid = engine_grid<RT, KTF>(dev);
-  if (grid_override) grid = (int)grid_override;
-  if ((uint32_t)grid > a.nitems) grid = (int)a.nitems;
+void launch_engine(const EngineArgs& a, uint32_t grid, hipStream_t st) {
+  if (grid > a.nitems) grid = a.nitems;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((k_engine<RT, KTF>), dim3(grid), dim3(ENG_NT), 0, st, a);
 }
 
 template <int RT>
-void launch_all(const EngineArgs& a, int key_type, uint32_t grid_override, int dev, hipStream_t st) {
+uint32_t grid_for(int key_type, int dev) {
+  switch (key_type) {
+    case KEY_I32: return (uint32_t)engine_grid<RT, KEY_I32>(dev);
+    case KEY_F32: return (uint32_t)engine_grid<RT, KEY_F32>(dev);
+    case KEY_I64: return (uint32_t)engine_grid<RT, KEY_I64>(dev);
+    default: return (uint32_t)engine_grid<RT, -1>(dev);
+  }
+}
+
+template <int RT>
+void launch_all(const EngineArgs& a, int key_type, uint32_t grid, hipStream_t st) {
   const uint32_t rgrid = std::max<uint32_t>(1, std::min<uint32_t>(1024, (a.nq * 16 + 255) / 256));
   hipLaunchKernelGGL(k_reset, dim3(rgrid), dim3(256), 0, st, a);
   if (a.nprep) hipLaunchKernelGGL(k_bprep<RT>, dim3(a.nprep), dim3(PREP_NT), 0, st, a);
   profile_mark(st, true);
   switch (key_type) {
-    case KEY_I32: launch_engine<RT, KEY_I32>(a, grid_override, dev, st); break;
-    case KEY_F32: launch_engine<RT, KEY_F32>(a, grid_override, dev, st); break;
-    case KEY_I64: launch_engine<RT, KEY_I64>(a, grid_override, dev, st); break;
-    default: launch_engine<RT, -1>(a, grid_override, dev, st); break;
+    case KEY_I32: launch_engine<RT, KEY_I32>(a, grid, st); break;
+    case KEY_F32: launch_engine<RT, KEY_F32>(a, grid, st); break;
+    case KEY_I64: launch_engine<RT, KEY_I64>(a, grid, st); break;
+    default: launch_engine<RT, -1>(a, grid, st); break;
   }
   profile_mark(st, false);
 }
 
 }  // namespace
 
+uint32_t engine_grid_size(uint32_t rid_type, int key_type) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  return rid_type == RID_U64 ? grid_for<RID_U64>(key_type, dev) : grid_for<RID_U32>(key_type, dev);
+}
+
+void engine_enqueue(const EngineArgs& a, uint32_t rid_type, int key_type, uint32_t grid,
+                    hipStream_t st) {
+  if (rid_type == RID_U64) launch_all<RID_U64>(a, key_type, grid, st);
+  else launch_all<RID_U32>(a, key_type, grid, st);
+}
+
 int engine_launch(const EngineArgs& a, uint32_t rid_type, int key_type, uint32_t grid_override,
                   hipStream_t st) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return TK_EHIP;
-  if (rid_type == RID_U64) launch_all<RID_U64>(a, key_type, grid_override, dev, st);
-  else launch_all<RID_U32>(a, key_type, grid_override, dev, st);
+  const uint32_t grid = grid_override ? grid_override : engine_grid_size(rid_type, key_type);
+  if (grid == 0) return TK_EHIP;
+  engine_enqueue(a, rid_type, key_type, grid, st);
   return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
 }
 #endif  // TK_EMU

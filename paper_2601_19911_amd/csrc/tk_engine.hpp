@@ -73,9 +73,16 @@ struct EngineArgs {
 // scratch bytes of one query's regions, placed at `off`
 uint64_t layout_query(QDesc& d, uint64_t off, uint32_t kb, uint32_t rb, const SamplePlan& p);
 // Enqueues k_reset, k_bprep and k_engine.  key_type: the type of every query,
-// or -1 for a launch that mixes key types.
+// or -1 for a launch that mixes key types.  grid_override 0: the occupancy grid.
 int engine_launch(const EngineArgs& a, uint32_t rid_type, int key_type, uint32_t grid_override,
                   hipStream_t st);
+// The occupancy grid of k_engine on the current device (0 on a HIP error).
+// Queries the runtime, so it is called before a stream capture begins.
+uint32_t engine_grid_size(uint32_t rid_type, int key_type);
+// engine_launch with a given grid and no runtime queries: safe inside a stream
+// capture (launch errors surface when the capture ends).
+void engine_enqueue(const EngineArgs& a, uint32_t rid_type, int key_type, uint32_t grid,
+                    hipStream_t st);
 
 // keys per streaming tile (256 KiB of keys)
 inline uint32_t tile_len_for(uint32_t kb) { return kb == 8 ? (1u << 15) : (1u << 16); }
