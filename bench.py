@@ -20,7 +20,7 @@ import time
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -34,7 +34,7 @@ def parse():
                     help="CPU budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the result")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def traffic_from_profiles(kernel: str):
@@ -48,13 +48,8 @@ def traffic_from_profiles(kernel: str):
         return None
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-
+def measure(args) -> dict:
+    """Times `args.steps` whole queries of one configuration; returns the JSON record."""
     import numpy as np
     import torch
 
@@ -116,6 +111,16 @@ def main():
     wall = time.perf_counter() - wall0
     ms_total = t0.elapsed_time(t1)
     ms_step = ms_total / args.steps
+
+    # per-query latency distribution (each query bracketed by its own events)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in evs:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    per_q = np.array([a.elapsed_time(b) for a, b in evs])
 
     # dominant kernel (the streaming filter), timed with event pairs on its stream
     tk.profile_begin(args.steps)
@@ -184,10 +189,21 @@ def main():
         "whole_query_frac_of_peak": alg_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "path": info["path"], "survivors": info["survivors"],
         "oracle_match": check,
+        "query_ms_median": float(np.median(per_q)),
+        "query_ms_p95": float(np.percentile(per_q, 95)),
         "wall_s_timed": wall,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(result), flush=True)
+    return result
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    print(json.dumps(measure(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -1,0 +1,501 @@
+#!/usr/bin/env python3
+"""Measurement suites beside the headline line of bench.py.
+
+    python bench_suites.py c2 [--quick]      single-query variants (dtype, distribution, K, order)
+    python bench_suites.py c3 [--q 4096]     batched plan vs per-query launches (1 and 4 streams)
+    python bench_suites.py c4                key-only vs full-row transfer with late materialization
+    python bench_suites.py c5                served form: Poisson arrivals, gate on vs always-GPU
+    python bench_suites.py crossover         CPU vs GPU time over N (host- and device-resident keys)
+    python bench_suites.py e2e               headline query with pinned H2D and D2H included
+
+Each suite prints one JSON object per measurement on stdout.  Every input is
+synthetic and seeded (inputgen); every GPU result that a suite reports is
+checked against the CPU oracle on the same rows (all of them, or a stated
+sample of queries).
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def emit(d):
+    print(json.dumps(d), flush=True)
+
+
+def pct(a, p):
+    return float(np.percentile(np.asarray(a, dtype=np.float64), p)) if len(a) else None
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def key_dtype_np(kc):
+    import paper_2601_19911_amd as tk
+    return {tk.TK_KEY_I32: np.int32, tk.TK_KEY_I64: np.int64, tk.TK_KEY_F32: np.float32}[kc]
+
+
+def dev_view_np(t):
+    """Host numpy copy of a device tensor, unsigned types included."""
+    torch = _torch()
+    if t.dtype == torch.uint32:
+        return t.view(torch.int32).cpu().numpy().view(np.uint32)
+    if t.dtype == torch.uint64:
+        return t.view(torch.int64).cpu().numpy().view(np.uint64)
+    return t.cpu().numpy()
+
+
+def same(gk, gr, ek, er):
+    bits = (lambda a: a.view(np.uint32 if a.dtype.itemsize == 4 else np.uint64))
+    return (gk.shape == ek.shape and np.array_equal(bits(gk), bits(ek)) and
+            np.array_equal(gr.astype(np.uint64), er.astype(np.uint64)))
+
+
+# ---- C2: single-query variants -------------------------------------------------------------------
+
+def suite_c2(a):
+    import bench
+    variants = []
+    for dt in ("float32", "int64"):
+        for dist in ("uniform", "zipf", "sorted"):
+            for k in ((1000,) if a.quick else (10, 1000, 100000)):
+                variants.append((dt, dist, k, "desc"))
+            if dist == "zipf":
+                variants.append((dt, dist, 1000, "asc"))
+    for dt, dist, k, order in variants:
+        args = bench.parse([f"--dtype={dt}", f"--dist={dist}", f"--k={k}", f"--order={order}",
+                            "--steps=31", "--warmup=5", "--no-cpu"])
+        r = bench.measure(args)
+        r["suite"] = "c2"
+        emit(r)
+
+
+# ---- C3: batched vs per-query --------------------------------------------------------------------
+
+def suite_c3(a):
+    torch = _torch()
+    import inputgen
+    import oracle
+    import paper_2601_19911_amd as tk
+    from inputgen import native as gen
+    from paper_2601_19911_amd.batched import Plan
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    off, ks, orders = inputgen.batched_queries(a.q, seed=inputgen.config_seed(3),
+                                               n_lo_log2=10, n_hi_log2=a.n_hi_log2, k_max=4096)
+    Q = len(ks)
+    total = int(off[-1])
+    ns = np.diff(off).astype(np.int64)
+    kef = np.minimum(ks.astype(np.int64), ns)
+    oo = np.zeros(Q + 1, dtype=np.uint64)
+    oo[1:] = np.cumsum(kef)
+    print(f"c3: Q={Q} sum N={total} ({total * 8 / 1e9:.2f} GB int64) sum K={int(oo[-1])}",
+          file=sys.stderr, flush=True)
+    keys = torch.empty(total, dtype=torch.int64, device=dev)
+    gen.device_fill(inputgen.KIND_U_I64, inputgen.config_seed(3), total, keys.data_ptr(),
+                    stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    kp = keys.data_ptr()
+    L = tk.lib()
+    reps = a.reps
+
+    # (i)/(ii) per-query tk_topk launches on S streams, all queries released at t0
+    def per_query(nstreams):
+        streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        wsb = max(tk.workspace_size(int(n), int(k), tk.TK_KEY_I64, tk.TK_RID_U32)
+                  for n, k in zip(ns, kef))
+        wss = [torch.zeros(wsb, dtype=torch.uint8, device=dev) for _ in range(nstreams)]
+        ok = torch.empty(int(oo[-1]), dtype=torch.int64, device=dev)
+        orr = torch.empty(int(oo[-1]), dtype=torch.uint32, device=dev)
+        cnt = ctypes.c_uint64()
+        best = None
+        for rep in range(reps + 1):
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(Q)]
+            t0 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0.record(torch.cuda.current_stream())
+            for s in streams:
+                s.wait_event(t0)
+            w0 = time.perf_counter()
+            for q in range(Q):
+                s = streams[q % nstreams]
+                rc = L.tk_topk(kp + int(off[q]) * 8, None, int(ns[q]), int(ks[q]), tk.TK_KEY_I64,
+                               tk.TK_RID_U32, int(orders[q]), ok.data_ptr() + int(oo[q]) * 8,
+                               orr.data_ptr() + int(oo[q]) * 4, ctypes.byref(cnt),
+                               wss[q % nstreams].data_ptr(), wsb, s.cuda_stream)
+                tk.check(rc, "tk_topk")
+                evs[q].record(s)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - w0
+            lat = np.array([t0.elapsed_time(e) for e in evs]) * 1e-3
+            total_s = float(lat.max())
+            if rep and (best is None or total_s < best[0]):
+                best = (total_s, lat, wall)
+        return best, ok, orr
+
+    def plan_run():
+        s = torch.cuda.Stream()
+        plan = Plan(off, ks, orders, key_dtype=torch.int64, rid_dtype=torch.uint32, stream=s)
+        ok, orr = plan.alloc_outputs()
+        torch.cuda.synchronize()
+        plan.launch(keys, ok, orr, stream=s)  # eager first launch
+        plan.launch(keys, ok, orr, stream=s)  # captured
+        torch.cuda.synchronize()
+        best = None
+        for rep in range(reps):
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0.record(s)
+            plan.launch(keys, ok, orr, stream=s)
+            t1.record(s)
+            torch.cuda.synchronize()
+            total_s = t0.elapsed_time(t1) * 1e-3
+            lat = plan.query_times()
+            st = plan.stats()
+            if best is None or total_s < best[0]:
+                best = (total_s, lat, st)
+        info = plan.info()
+        return best, ok, orr, info, plan
+
+    def report(mode, total_s, lat, extra):
+        bytes_alg = total * 8
+        emit({"suite": "c3", "mode": mode, "queries": Q, "sum_n": total, "sum_k": int(oo[-1]),
+              "seconds": total_s, "keys_per_s": total / total_s, "qps": Q / total_s,
+              "gbs": bytes_alg / total_s / 1e9, "frac_of_peak": bytes_alg / total_s / 1e9 / HBM_PEAK_GBS,
+              "lat_p50_ms": pct(lat, 50) * 1e3, "lat_p95_ms": pct(lat, 95) * 1e3,
+              "lat_p99_ms": pct(lat, 99) * 1e3, "lat_max_ms": float(np.max(lat)) * 1e3, **extra})
+
+    (pb, pok, porr, pinfo, plan) = plan_run()
+    report("batched_plan", pb[0], pb[1], {"plan": pinfo, "stats": pb[2], "reps": reps})
+    pk, pr = dev_view_np(pok), dev_view_np(porr)
+    results = {}
+    for S in (1, 4):
+        (b, ok, orr) = per_query(S)
+        report(f"per_query_{S}_stream", b[0], b[1], {"host_submit_s": b[2], "reps": reps})
+        results[S] = (dev_view_np(ok), dev_view_np(orr))
+    # parity: per-query == batched everywhere; a sample of queries == oracle
+    agree = all(np.array_equal(results[S][0], pk) and np.array_equal(results[S][1], pr)
+                for S in results)
+    order_idx = np.argsort(ns)
+    pick = sorted(set(list(order_idx[:: max(1, Q // a.check_queries)]) + [int(order_idx[-1])]))
+    bad = 0
+    for q in pick:
+        lo, hi = int(off[q]), int(off[q + 1])
+        host = dev_view_np(keys[lo:hi])
+        ek, er = oracle.topk(host, None, int(ks[q]), int(orders[q]), rid_dtype=np.uint32)
+        a0, a1 = int(oo[q]), int(oo[q + 1])
+        bad += not same(pk[a0:a1], pr[a0:a1], ek, er)
+    emit({"suite": "c3", "check": "parity", "batched_equals_per_query": bool(agree),
+          "oracle_checked_queries": len(pick), "oracle_mismatches": bad})
+    plan.close()
+
+
+# ---- E2E: pinned host keys, H2D + query + D2H ------------------------------------------------------
+
+def _pinned_copy(np_arr):
+    torch = _torch()
+    t = torch.from_numpy(np_arr.view(np.int32) if np_arr.dtype == np.uint32 else np_arr)
+    p = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+    p.copy_(t)
+    return p
+
+
+def suite_e2e(a):
+    torch = _torch()
+    import inputgen
+    import oracle
+    import paper_2601_19911_amd as tk
+    from inputgen import native as gen
+
+    dev = torch.device("cuda:0")
+    n, k = 1 << a.log2n, 1000
+    seed = inputgen.config_seed(2)
+    hk = gen.host_fill(inputgen.KIND_U_F32, seed, n)
+    hr = np.arange(n, dtype=np.uint32)
+    pk, pr = _pinned_copy(hk), _pinned_copy(hr)
+    dk = torch.empty(n, dtype=torch.float32, device=dev)
+    dr = torch.empty(n, dtype=torch.int32, device=dev)
+    ok = torch.empty(k, dtype=torch.float32, device=dev)
+    orr = torch.empty(k, dtype=torch.int32, device=dev)
+    hok = torch.empty(k, dtype=torch.float32, pin_memory=True)
+    hor = torch.empty(k, dtype=torch.int32, pin_memory=True)
+    ws = tk.new_workspace(n, k, tk.TK_KEY_F32, tk.TK_RID_U32, device=dev)
+    s = torch.cuda.current_stream()
+
+    def one():
+        dk.copy_(pk, non_blocking=True)
+        dr.copy_(pr, non_blocking=True)
+        tk.topk(dk, k, rowids=dr.view(torch.uint32), out_keys=ok, out_rowids=orr.view(torch.uint32),
+                workspace=ws, stream=s)
+        hok.copy_(ok, non_blocking=True)
+        hor.copy_(orr, non_blocking=True)
+
+    for _ in range(2):
+        one()
+    torch.cuda.synchronize()
+    times, h2d = [], []
+    for _ in range(a.reps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(s)
+        dk.copy_(pk, non_blocking=True)
+        dr.copy_(pr, non_blocking=True)
+        e1.record(s)
+        tk.topk(dk, k, rowids=dr.view(torch.uint32), out_keys=ok, out_rowids=orr.view(torch.uint32),
+                workspace=ws, stream=s)
+        hok.copy_(ok, non_blocking=True)
+        hor.copy_(orr, non_blocking=True)
+        e2.record(s)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e2) * 1e-3)
+        h2d.append(e0.elapsed_time(e1) * 1e-3)
+    ek, er = oracle.topk(hk, hr, k, oracle.DESC)
+    match = same(hok.numpy(), hor.numpy().view(np.uint32), ek, er)
+    t = float(np.median(times))
+    emit({"suite": "e2e", "workload": f"N=2^{a.log2n} float32 + uint32 row-ids in pinned host "
+          "memory, K=1000 desc: H2D of keys and row-ids, Top-K, D2H of the results",
+          "median_s": t, "p95_s": pct(times, 95), "keys_per_s": n / t,
+          "h2d_median_s": float(np.median(h2d)), "h2d_gbs": n * 8 / float(np.median(h2d)) / 1e9,
+          "reps": a.reps, "oracle_match": bool(match)})
+
+
+# ---- C4: key-only vs full-row with late materialization ----------------------------------------
+
+def suite_c4(a):
+    torch = _torch()
+    import inputgen
+    import oracle
+    import paper_2601_19911_amd as tk
+    from inputgen import native as gen
+
+    dev = torch.device("cuda:0")
+    n, k, ncols = 1 << a.log2n, 1000, 8
+    seed = inputgen.config_seed(4)
+    cdf = inputgen.zipf_cdf(1.05, 10 ** 6)
+    hk = gen.host_fill(inputgen.KIND_ZIPF_I64, seed, n, cdf=cdf)
+    payload = np.empty((ncols, n), dtype=np.float64)
+    for c in range(ncols):
+        payload[c] = gen.host_fill(inputgen.KIND_PAYLOAD_F64, seed + 1 + c, n)
+    hr = np.arange(n, dtype=np.uint32)
+    pk, pr = _pinned_copy(hk), _pinned_copy(hr)
+    ppay = _pinned_copy(payload)
+    s = torch.cuda.current_stream()
+    dk = torch.empty(n, dtype=torch.int64, device=dev)
+    dr = torch.empty(n, dtype=torch.int32, device=dev)
+    dpay = torch.empty((ncols, n), dtype=torch.float64, device=dev)
+    ok = torch.empty(k, dtype=torch.int64, device=dev)
+    orr = torch.empty(k, dtype=torch.int32, device=dev)
+    hok = torch.empty(k, dtype=torch.int64, pin_memory=True)
+    hor = torch.empty(k, dtype=torch.int32, pin_memory=True)
+    rows_dev = torch.empty((ncols, k), dtype=torch.float64, device=dev)
+    hrows = torch.empty((ncols, k), dtype=torch.float64, pin_memory=True)
+    ws = tk.new_workspace(n, k, tk.TK_KEY_I64, tk.TK_RID_U32, device=dev)
+    L = tk.lib()
+
+    def key_only():
+        dk.copy_(pk, non_blocking=True)
+        dr.copy_(pr, non_blocking=True)
+        tk.topk(dk, k, rowids=dr.view(torch.uint32), out_keys=ok, out_rowids=orr.view(torch.uint32),
+                workspace=ws, stream=s)
+        hok.copy_(ok, non_blocking=True)
+        hor.copy_(orr, non_blocking=True)
+        torch.cuda.synchronize()
+        # late materialization on the host: gather the payload rows at the row-ids
+        return tk.gather_rows_host(payload, hor.numpy().view(np.uint32))
+
+    def full_row():
+        dk.copy_(pk, non_blocking=True)
+        dr.copy_(pr, non_blocking=True)
+        dpay.copy_(ppay, non_blocking=True)
+        tk.topk(dk, k, rowids=dr.view(torch.uint32), out_keys=ok, out_rowids=orr.view(torch.uint32),
+                workspace=ws, stream=s)
+        tk.gather_rows_device(dpay, orr.view(torch.uint32), rows_dev, stream=s)
+        hrows.copy_(rows_dev, non_blocking=True)
+        hok.copy_(ok, non_blocking=True)
+        hor.copy_(orr, non_blocking=True)
+        torch.cuda.synchronize()
+        return hrows.numpy().copy()
+
+    ek, er = oracle.topk(hk, hr, k, oracle.DESC)
+    expect_rows = payload[:, er.astype(np.int64)]
+    for name, fn in (("key_only", key_only), ("full_row", full_row)):
+        fn()
+        ts = []
+        for _ in range(a.reps):
+            t0 = time.perf_counter()
+            rows = fn()
+            ts.append(time.perf_counter() - t0)
+        ok_match = same(hok.numpy(), hor.numpy().view(np.uint32), ek, er)
+        rows_match = bool(np.array_equal(rows.view(np.uint64), expect_rows.view(np.uint64)))
+        h2d_bytes = n * (8 + 4) + (n * ncols * 8 if name == "full_row" else 0)
+        emit({"suite": "c4", "mode": name, "n": n, "k": k, "payload_cols": ncols,
+              "h2d_bytes": h2d_bytes, "median_s": float(np.median(ts)), "p95_s": pct(ts, 95),
+              "reps": a.reps, "oracle_match": bool(ok_match), "rows_match": rows_match})
+
+
+# ---- C5: served form ----------------------------------------------------------------------------
+
+def suite_c5(a):
+    torch = _torch()
+    import inputgen
+    import oracle
+    import paper_2601_19911_amd as tk
+    from inputgen import native as gen
+    from paper_2601_19911_amd.serve import GATE_COST, GATE_GPU, Server
+
+    dev = torch.device("cuda:0")
+    col_len = 1 << a.col_log2
+    kinds = [(inputgen.KIND_U_I32, torch.int32), (inputgen.KIND_U_I64, torch.int64),
+             (inputgen.KIND_U_F32, torch.float32)]
+    cols = []
+    for c in range(a.columns):
+        kind, dt = kinds[c % 3]
+        seed = inputgen.config_seed(5) + 10 + c
+        d = torch.empty(col_len, dtype=dt, device=dev)
+        gen.device_fill(kind, seed, col_len, d.data_ptr(), stream=torch.cuda.current_stream().cuda_stream)
+        h = gen.host_fill(kind, seed, col_len)
+        cols.append((d, h))
+    torch.cuda.synchronize()
+    req = inputgen.serving_requests(a.requests, col_len=col_len)
+    cnt = a.requests
+    col_of = np.minimum((req["u_col"] * a.columns).astype(np.int64), a.columns - 1)
+    n, k, off = req["n"], req["k"], req["offset"]
+    cost = json.loads(a.cost) if a.cost else None
+
+    def run(gate, rate):
+        srv = Server(arena_bytes=a.arena_mb << 20, max_batch=a.max_batch, slots=a.slots,
+                     window_us=a.window_us, gate=gate, margin_ms=0.0, cpu_threads=a.cpu_threads,
+                     cost=cost)
+        ids = [srv.add_column(d, h) for d, h in cols]
+        # Poisson arrivals: exponential gaps from the recipe's uniforms
+        gaps = -np.log1p(-req["u_arr"]) / rate
+        t_arr = np.cumsum(gaps) - gaps[0]
+        rids = srv.replay(t_arr, np.array(ids)[col_of], off, n, k, np.zeros(cnt, dtype=np.uint8))
+        srv.drain()
+        lat, routes, sub = [], [], []
+        bad = 0
+        for i in range(cnt):
+            res = srv.result(int(rids[i]), int(col_of[i]), int(min(k[i], n[i])))
+            gk, gr, info = res
+            lat.append((info.t_done_ns - info.t_submit_ns) * 1e-9)
+            sub.append(info.t_submit_ns)
+            routes.append(info.route)
+            if i % a.check_every == 0:
+                h = cols[int(col_of[i])][1][int(off[i]):int(off[i] + n[i])]
+                ek, er = oracle.topk(h, None, int(k[i]), oracle.DESC, rid_dtype=np.uint64)
+                bad += not same(gk, gr, ek, er + np.uint64(off[i]))
+        st = srv.stats()
+        srv.close()
+        return np.array(lat), np.array(routes), st, bad
+
+    results = {}
+    for gate, name in ((GATE_GPU, "always_gpu"), (GATE_COST, "cost_gate")):
+        for lam in a.rates:
+            lat, routes, st, bad = run(gate, lam)
+            emit({"suite": "c5", "gate": name, "rate_qps": lam, "requests": cnt,
+                  "lat_p50_ms": pct(lat, 50) * 1e3, "lat_p95_ms": pct(lat, 95) * 1e3,
+                  "lat_p99_ms": pct(lat, 99) * 1e3, "cpu_routed": float(np.mean(routes == 1)),
+                  "stats": st, "oracle_checked": (cnt + a.check_every - 1) // a.check_every,
+                  "oracle_mismatches": bad})
+
+
+# ---- crossover ---------------------------------------------------------------------------------
+
+def suite_crossover(a):
+    torch = _torch()
+    import inputgen
+    import paper_2601_19911_amd as tk
+    from inputgen import native as gen
+
+    dev = torch.device("cuda:0")
+    cores = len(os.sched_getaffinity(0))
+    kinds = {"int32": (inputgen.KIND_U_I32, torch.int32), "int64": (inputgen.KIND_U_I64, torch.int64),
+             "float32": (inputgen.KIND_U_F32, torch.float32)}
+    s = torch.cuda.current_stream()
+    for dt in a.dtypes:
+        kind, tdt = kinds[dt]
+        nmax = 1 << a.max_log2
+        hk = gen.host_fill(kind, inputgen.config_seed(6), nmax)
+        pk = _pinned_copy(hk)
+        dk = torch.empty(nmax, dtype=tdt, device=dev)
+        dk.copy_(pk)
+        for K in a.ks:
+            ws = tk.new_workspace(nmax, K, tk.key_code(tdt), tk.TK_RID_U32, device=dev)
+            ok = torch.empty(K, dtype=tdt, device=dev)
+            orr = torch.empty(K, dtype=torch.uint32, device=dev)
+            hok = torch.empty(K, dtype=tdt, pin_memory=True)
+            hor = torch.empty(K, dtype=torch.int32, pin_memory=True)
+            for lg in range(a.min_log2, a.max_log2 + 1):
+                N = 1 << lg
+                reps = 31 if N <= (1 << 22) else 5
+
+                def gpu(resident):
+                    ts = []
+                    for r in range(reps + 2):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        if not resident:
+                            dk[:N].copy_(pk[:N], non_blocking=True)
+                        tk.topk(dk[:N], K, out_keys=ok[:min(K, N)], out_rowids=orr[:min(K, N)],
+                                workspace=ws, stream=s)
+                        hok[:min(K, N)].copy_(ok[:min(K, N)], non_blocking=True)
+                        hor[:min(K, N)].copy_(orr[:min(K, N)].view(torch.int32), non_blocking=True)
+                        torch.cuda.synchronize()
+                        if r >= 2:
+                            ts.append(time.perf_counter() - t0)
+                    return float(np.median(ts))
+
+                cts = []
+                for r in range(reps + 1):
+                    t0 = time.perf_counter()
+                    tk.cpu_topk(hk[:N], K, nthreads=cores)
+                    if r:
+                        cts.append(time.perf_counter() - t0)
+                emit({"suite": "crossover", "dtype": dt, "k": K, "n": N,
+                      "gpu_resident_s": gpu(True), "gpu_host_keys_s": gpu(False),
+                      "cpu_all_cores_s": float(np.median(cts)), "cpu_threads": cores, "reps": reps})
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("suite", choices=["c2", "c3", "c4", "c5", "crossover", "e2e"])
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--q", type=int, default=4096)
+    ap.add_argument("--n-hi-log2", type=float, default=24.0)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--check-queries", type=int, default=24)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--columns", type=int, default=6)
+    ap.add_argument("--col-log2", type=int, default=28)
+    ap.add_argument("--requests", type=int, default=4000)
+    ap.add_argument("--rates", type=float, nargs="+", default=[2000.0])
+    ap.add_argument("--arena-mb", type=int, default=4096)
+    ap.add_argument("--max-batch", type=int, default=256)
+    ap.add_argument("--slots", type=int, default=2)
+    ap.add_argument("--window-us", type=float, default=50.0)
+    ap.add_argument("--cpu-threads", type=int, default=8)
+    ap.add_argument("--cost", type=str, default="")
+    ap.add_argument("--check-every", type=int, default=20)
+    ap.add_argument("--dtypes", nargs="+", default=["int32", "int64", "float32"])
+    ap.add_argument("--ks", type=int, nargs="+", default=[10, 100, 1000])
+    ap.add_argument("--min-log2", type=int, default=8)
+    ap.add_argument("--max-log2", type=int, default=26)
+    a = ap.parse_args()
+    {"c2": suite_c2, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5, "crossover": suite_crossover,
+     "e2e": suite_e2e}[a.suite](a)
+
+
+if __name__ == "__main__":
+    main()

@@ -224,6 +224,21 @@ int tk_cpu_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, in
                 int rid_type, int order, void* out_keys, void* out_rowids, uint64_t* out_count,
                 int nthreads);
 
+/* Late materialization (paper sec. II-C): the caller fetches payload rows at
+ * the returned row-ids.  `cols` is a row-major [ncols][n] array of float64
+ * payload columns, `rowids` k row-ids (uint32 or uint64 per rid_type), `out`
+ * a [ncols][k] array: out[c][j] = cols[c][rowids[j]].
+ *   tk_gather_f64_host    host arrays, synchronous, nthreads host threads;
+ *                         a row-id >= n returns TK_EINVAL before any write.
+ *   tk_gather_f64_device  device arrays, stream-ordered and asynchronous (the
+ *                         full-row comparison, whose payload already sits in
+ *                         HBM); a row-id >= n yields 0.0 in its output slots.
+ * k = 0 or ncols = 0 is a no-op returning TK_OK. */
+int tk_gather_f64_host(const double* cols, uint32_t ncols, uint64_t n, const void* rowids,
+                       int rid_type, uint64_t k, double* out, int nthreads);
+int tk_gather_f64_device(const double* cols, uint32_t ncols, uint64_t n, const void* rowids,
+                         int rid_type, uint64_t k, double* out, void* stream);
+
 /* Kernel timing for roofline reports.  Between tk_profile_begin and
  * tk_profile_end, every streaming pass over the keys (the dominant kernel:
  * the filter of tk_topk, the persistent kernel of tk_plan_launch) is

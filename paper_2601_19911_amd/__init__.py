@@ -57,6 +57,10 @@ def lib():
         L.tk_set_tuning.restype = i32
         L.tk_cpu_topk.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, ctypes.POINTER(u64), i32]
         L.tk_cpu_topk.restype = i32
+        L.tk_gather_f64_host.argtypes = [vp, ctypes.c_uint32, u64, vp, i32, u64, vp, i32]
+        L.tk_gather_f64_host.restype = i32
+        L.tk_gather_f64_device.argtypes = [vp, ctypes.c_uint32, u64, vp, i32, u64, vp, vp]
+        L.tk_gather_f64_device.restype = i32
         L.tk_profile_begin.argtypes = [ctypes.c_uint32]
         L.tk_profile_begin.restype = i32
         L.tk_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]
@@ -213,3 +217,31 @@ def cpu_topk(keys: np.ndarray, k: int, rowids: np.ndarray | None = None, order="
                            ctypes.byref(cnt), int(nthreads))
     check(rc, "tk_cpu_topk")
     return ok, orr
+
+
+# ---- late materialization ---------------------------------------------------------------------
+
+def gather_rows_host(payload: np.ndarray, rowids: np.ndarray, nthreads: int = 8) -> np.ndarray:
+    """payload[:, rowids] for a [ncols, n] float64 host array (C threads)."""
+    payload = np.ascontiguousarray(payload, dtype=np.float64)
+    rowids = np.ascontiguousarray(rowids)
+    if payload.ndim != 2:
+        raise ValueError("payload must be [ncols, n]")
+    ncols, n = payload.shape
+    out = np.empty((ncols, len(rowids)), dtype=np.float64)
+    check(lib().tk_gather_f64_host(payload.ctypes.data, ncols, n, rowids.ctypes.data,
+                                   rid_code(rowids.dtype), len(rowids), out.ctypes.data, nthreads),
+          "tk_gather_f64_host")
+    return out
+
+
+def gather_rows_device(payload, rowids, out, stream=None):
+    """out[:, j] = payload[:, rowids[j]] on the device (stream-ordered)."""
+    if payload.dim() != 2 or out.dim() != 2 or out.shape[0] != payload.shape[0]:
+        raise ValueError("payload [ncols, n] and out [ncols, k] required")
+    if out.shape[1] != rowids.shape[0]:
+        raise ValueError("out must have one column per row-id")
+    check(lib().tk_gather_f64_device(payload.data_ptr(), payload.shape[0], payload.shape[1],
+                                     rowids.data_ptr(), rid_code(rowids.dtype), rowids.shape[0],
+                                     out.data_ptr(), _stream_handle(stream)),
+          "tk_gather_f64_device")

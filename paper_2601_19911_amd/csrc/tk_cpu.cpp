@@ -127,3 +127,47 @@ extern "C" int tk_cpu_topk(const void* keys, const void* rowids, uint64_t n, uin
     return TK_ENOMEM;
   }
 }
+
+namespace {
+
+template <typename R>
+int gather_host(const double* cols, uint32_t ncols, uint64_t n, const R* rids, uint64_t k,
+                double* out, int nthreads) {
+  for (uint64_t j = 0; j < k; ++j)
+    if ((uint64_t)rids[j] >= n) return TK_EINVAL;
+  auto work = [&](uint32_t c0, uint32_t c1) {
+    for (uint32_t c = c0; c < c1; ++c) {
+      const double* col = cols + (uint64_t)c * n;
+      double* o = out + (uint64_t)c * k;
+      for (uint64_t j = 0; j < k; ++j) o[j] = col[rids[j]];
+    }
+  };
+  const uint32_t t = (uint32_t)std::max(1, std::min<int>(nthreads, (int)ncols));
+  if (t == 1 || (uint64_t)ncols * k < 65536) {
+    work(0, ncols);
+    return TK_OK;
+  }
+  std::vector<std::thread> th;
+  for (uint32_t i = 0; i < t; ++i)
+    th.emplace_back(work, (uint32_t)((uint64_t)ncols * i / t), (uint32_t)((uint64_t)ncols * (i + 1) / t));
+  for (auto& x : th) x.join();
+  return TK_OK;
+}
+
+}  // namespace
+
+extern "C" int tk_gather_f64_host(const double* cols, uint32_t ncols, uint64_t n,
+                                  const void* rowids, int rid_type, uint64_t k, double* out,
+                                  int nthreads) {
+  if (rid_type != TK_RID_U32 && rid_type != TK_RID_U64) return TK_EINVAL;
+  if (k == 0 || ncols == 0) return TK_OK;
+  if (!cols || !rowids || !out) return TK_EINVAL;
+  if (nthreads <= 0) nthreads = 1;
+  try {
+    if (rid_type == TK_RID_U32)
+      return gather_host(cols, ncols, n, static_cast<const uint32_t*>(rowids), k, out, nthreads);
+    return gather_host(cols, ncols, n, static_cast<const uint64_t*>(rowids), k, out, nthreads);
+  } catch (...) {
+    return TK_ENOMEM;
+  }
+}

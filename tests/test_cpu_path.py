@@ -34,3 +34,17 @@ def test_cpu_u64_rowids_and_specials():
     rids = np.arange(len(keys), dtype=np.uint64)[::-1].copy()
     for order, o in (("desc", oracle.DESC), ("asc", oracle.ASC)):
         _same(tk.cpu_topk(keys, 12345, rowids=rids, order=order), oracle.topk(keys, rids, 12345, o))
+
+
+def test_gather_rows_host_is_numpy_take():
+    """Late materialization: gathered rows equal numpy's take on the payload."""
+    import paper_2601_19911_amd as tk
+    rng = np.random.default_rng(5)
+    pay = rng.random((8, 50000))
+    for dt in (np.uint32, np.uint64):
+        r = rng.integers(0, 50000, 3000).astype(dt)
+        assert np.array_equal(tk.gather_rows_host(pay, r).view(np.uint64),
+                              pay[:, r.astype(np.int64)].view(np.uint64))
+    assert tk.gather_rows_host(pay, np.zeros(0, dtype=np.uint32)).shape == (8, 0)
+    with pytest.raises(tk.TopKError):
+        tk.gather_rows_host(pay, np.array([50000], dtype=np.uint32))

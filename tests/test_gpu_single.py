@@ -206,3 +206,16 @@ def test_repeatable():
     for _ in range(3):
         b = run(keys, None, 777, "desc")
         assert np.array_equal(a[1], b[1])
+
+
+def test_gather_rows_device_matches_take():
+    import torch
+    rng = np.random.default_rng(9)
+    pay = rng.random((8, 70000))
+    r = rng.integers(0, 70000, 1000).astype(np.uint32)
+    dp = torch.from_numpy(pay).cuda()
+    dr = to_dev(r)
+    out = torch.empty((8, 1000), dtype=torch.float64, device="cuda")
+    tk.gather_rows_device(dp, dr, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), pay[:, r].view(np.uint64))
