@@ -413,9 +413,37 @@ def suite_c5(a):
 
 # ---- crossover ---------------------------------------------------------------------------------
 
+def fit_costs(rows):
+    """Least-squares cost models of the gate (reading: C_cpu = a N + b K log2(K+1) + c,
+    C_gpu = a N + b K + c), from crossover rows of one dtype."""
+    N = np.array([r["n"] for r in rows], dtype=np.float64)
+    K = np.array([min(r["k"], r["n"]) for r in rows], dtype=np.float64)
+    cpu = np.array([r["cpu_all_cores_s"] for r in rows])
+    gpu = np.array([r["gpu_resident_s"] for r in rows])
+    A = np.stack([N, K * np.log2(K + 1), np.ones_like(N)], 1)
+    ca = np.linalg.lstsq(A, cpu, rcond=None)[0]
+    B = np.stack([N, K, np.ones_like(N)], 1)
+    ga = np.linalg.lstsq(B, gpu, rcond=None)[0]
+    return {"cpu_a": float(ca[0]), "cpu_b": float(ca[1]), "cpu_c": float(ca[2]),
+            "gpu_a": float(ga[0]), "gpu_b": float(ga[1]), "gpu_c": float(ga[2])}
+
+
+def crossover_n(rows, key):
+    """Smallest N from which the GPU time stays below the CPU time."""
+    rows = sorted(rows, key=lambda r: r["n"])
+    best = None
+    for r in reversed(rows):
+        if r[key] < r["cpu_all_cores_s"]:
+            best = r["n"]
+        else:
+            break
+    return best
+
+
 def suite_crossover(a):
     torch = _torch()
     import inputgen
+    import oracle
     import paper_2601_19911_amd as tk
     from inputgen import native as gen
 
@@ -431,6 +459,7 @@ def suite_crossover(a):
         pk = _pinned_copy(hk)
         dk = torch.empty(nmax, dtype=tdt, device=dev)
         dk.copy_(pk)
+        rows = []
         for K in a.ks:
             ws = tk.new_workspace(nmax, K, tk.key_code(tdt), tk.TK_RID_U32, device=dev)
             ok = torch.empty(K, dtype=tdt, device=dev)
@@ -439,6 +468,7 @@ def suite_crossover(a):
             hor = torch.empty(K, dtype=torch.int32, pin_memory=True)
             for lg in range(a.min_log2, a.max_log2 + 1):
                 N = 1 << lg
+                ke = min(K, N)
                 reps = 31 if N <= (1 << 22) else 5
 
                 def gpu(resident):
@@ -448,24 +478,36 @@ def suite_crossover(a):
                         t0 = time.perf_counter()
                         if not resident:
                             dk[:N].copy_(pk[:N], non_blocking=True)
-                        tk.topk(dk[:N], K, out_keys=ok[:min(K, N)], out_rowids=orr[:min(K, N)],
-                                workspace=ws, stream=s)
-                        hok[:min(K, N)].copy_(ok[:min(K, N)], non_blocking=True)
-                        hor[:min(K, N)].copy_(orr[:min(K, N)].view(torch.int32), non_blocking=True)
+                        tk.topk(dk[:N], K, out_keys=ok[:ke], out_rowids=orr[:ke], workspace=ws,
+                                stream=s)
+                        hok[:ke].copy_(ok[:ke], non_blocking=True)
+                        hor[:ke].copy_(orr[:ke].view(torch.int32), non_blocking=True)
                         torch.cuda.synchronize()
                         if r >= 2:
                             ts.append(time.perf_counter() - t0)
                     return float(np.median(ts))
 
+                g_res, g_host = gpu(True), gpu(False)
+                ek, er = oracle.topk(hk[:N], None, K, oracle.DESC, rid_dtype=np.uint32)
+                match = same(hok[:ke].numpy(), hor[:ke].numpy().view(np.uint32), ek, er)
                 cts = []
                 for r in range(reps + 1):
                     t0 = time.perf_counter()
-                    tk.cpu_topk(hk[:N], K, nthreads=cores)
+                    ck, cr = tk.cpu_topk(hk[:N], K, nthreads=cores)
                     if r:
                         cts.append(time.perf_counter() - t0)
-                emit({"suite": "crossover", "dtype": dt, "k": K, "n": N,
-                      "gpu_resident_s": gpu(True), "gpu_host_keys_s": gpu(False),
-                      "cpu_all_cores_s": float(np.median(cts)), "cpu_threads": cores, "reps": reps})
+                cpu_match = same(ck, cr, ek, er)
+                row = {"suite": "crossover", "dtype": dt, "k": K, "n": N, "gpu_resident_s": g_res,
+                       "gpu_host_keys_s": g_host, "cpu_all_cores_s": float(np.median(cts)),
+                       "cpu_threads": cores, "reps": reps, "oracle_match": bool(match),
+                       "cpu_match": bool(cpu_match)}
+                rows.append(row)
+                emit(row)
+            ks_rows = [r for r in rows if r["k"] == K]
+            emit({"suite": "crossover", "dtype": dt, "k": K,
+                  "crossover_n_resident": crossover_n(ks_rows, "gpu_resident_s"),
+                  "crossover_n_host_keys": crossover_n(ks_rows, "gpu_host_keys_s")})
+        emit({"suite": "crossover", "dtype": dt, "fit": fit_costs(rows)})
 
 
 def main():

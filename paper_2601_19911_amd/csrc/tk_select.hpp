@@ -363,9 +363,59 @@ __device__ __forceinline__ uint64_t merge_split(const U* ak, const R* af, uint64
 // (lk, lf) of CAP elements and m <= CAP.  Otherwise they are in (ck, cf) in
 // global memory: tiles of CAP are bitonic-sorted in LDS, then merged pairwise
 // through (tk, tf) with merge-path splits.
+// Bitonic sort, best first, of P <= NT composites held one per thread
+// (thread t holds element t; P a power of two).  Strides below the wave
+// width exchange through lane shuffles; wider strides through LDS, ping-
+// ponging between two halves of (bk, bf) (2P slots) so each such stage takes
+// one barrier.  On return thread t holds the element of rank t.
+template <int NT, typename U, typename R>
+__device__ __forceinline__ void bitonic_regs_desc(U& k, R& f, uint32_t P, U* bk, R* bf) {
+  const uint32_t t = threadIdx.x;
+  uint32_t buf = 0;
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      U ok;
+      R of;
+      if (stride >= 64) {
+        U* xk = bk + buf * P;
+        R* xf = bf + buf * P;
+        if (t < P) {
+          xk[t] = k;
+          xf[t] = f;
+        }
+        __syncthreads();
+        ok = t < P ? xk[t ^ stride] : k;
+        of = t < P ? xf[t ^ stride] : f;
+        buf ^= 1u;
+      } else {
+        ok = __shfl_xor(k, (int)stride, 64);
+        of = __shfl_xor(f, (int)stride, 64);
+      }
+      const bool keep_max = ((t & stride) == 0) == ((t & size) == 0);
+      const bool take = keep_max ? cgt(ok, of, k, f) : cgt(k, f, ok, of);
+      if (take) {
+        k = ok;
+        f = of;
+      }
+    }
+  }
+}
+
 template <int NT, typename U, typename R, typename Emit>
 __device__ void block_sort_emit(uint64_t m, bool in_lds, U* lk, R* lf, uint32_t CAP, U* ck, R* cf,
                                 U* tk, R* tf, Emit&& emit) {
+  if (in_lds && m <= NT && 2 * (uint64_t)NT <= CAP) {
+    uint32_t P = 1;
+    while (P < m) P <<= 1;
+    const uint32_t t = threadIdx.x;
+    U k = t < m ? lk[t] : (U)0;
+    R f = t < m ? lf[t] : (R)0;
+    __syncthreads();  // the tile is reused as the exchange buffer
+    bitonic_regs_desc<NT, U, R>(k, f, P, lk, lf);
+    if (t < m) emit((uint64_t)t, k, f);
+    __syncthreads();
+    return;
+  }
   if (in_lds) {
     uint32_t P = 1;
     while (P < m) P <<= 1;
