@@ -275,7 +275,7 @@ __device__ void select_sort_write(const TailArgs1& a, const Src& src, uint64_t n
 constexpr int TAIL_E = 16;
 
 template <int KT, int RT>
-__device__ void select_sort_write_regs(const TailArgs1& a, uint32_t C, typename Key<KT>::U base,
+__device__ __forceinline__ void select_sort_write_regs(const TailArgs1& a, uint32_t C, typename Key<KT>::U base,
                                        LdsTile<KT, RT>& t, SelScratch& sc) {
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;

@@ -195,7 +195,7 @@ __device__ __forceinline__ int bitlen(U x) {
 // Boundary of the best `target` candidates (every candidate has u >= base and
 // there are at least `target` of them).
 template <int NT, typename U, typename R, typename Elems>
-__device__ Sel<U, R> block_radix_select(const Elems& el, uint64_t target, U base, SelScratch& sc) {
+__device__ __forceinline__ Sel<U, R> block_radix_select(const Elems& el, uint64_t target, U base, SelScratch& sc) {
   Sel<U, R> s;
   s.base = base;
   s.P = 0;
@@ -263,7 +263,7 @@ __device__ Sel<U, R> block_radix_select(const Elems& el, uint64_t target, U base
 // after them.  Every thread must call these (their loops are
 // workgroup-uniform).
 template <int NT, typename U, typename R, int E, typename KOut, typename FOut>
-__device__ void block_compact_regs(const RegElems<U, R, E>& el, const Sel<U, R>& s,
+__device__ __forceinline__ void block_compact_regs(const RegElems<U, R, E>& el, const Sel<U, R>& s,
                                    uint64_t target, KOut dk, FOut df, SelScratch& sc) {
   if (threadIdx.x == 0) { sc.cnt[0] = 0; sc.cnt[1] = 0; }
   __syncthreads();
@@ -301,7 +301,7 @@ __device__ void block_compact_regs(const RegElems<U, R, E>& el, const Sel<U, R>&
 }
 
 template <int NT, typename U, typename R, typename Src, typename KOut, typename FOut>
-__device__ void block_compact_glob(const Src& src, uint64_t n, const Sel<U, R>& s, uint64_t target,
+__device__ __forceinline__ void block_compact_glob(const Src& src, uint64_t n, const Sel<U, R>& s, uint64_t target,
                                    KOut dk, FOut df, SelScratch& sc) {
   if (threadIdx.x == 0) { sc.cnt[0] = 0; sc.cnt[1] = 0; }
   __syncthreads();
@@ -401,20 +401,119 @@ __device__ __forceinline__ void bitonic_regs_desc(U& k, R& f, uint32_t P, U* bk,
   }
 }
 
+// Bitonic sort, best first, of P <= NT * E composites held E per thread:
+// element i sits in thread i / E, slot i % E (P a power of two, threads whose
+// slots lie beyond P hold anything and take part in the exchanges).  Strides
+// below E compare registers of one thread; strides up to 32 E exchange with
+// lane shuffles; wider strides go through LDS, ping-ponging between two
+// halves of (bk, bf) (2P slots), one barrier per stage.  On return element i
+// is the composite of rank i.
+template <int NT, int E, typename U, typename R>
+__device__ __forceinline__ void bitonic_regs_desc_e(U (&k)[E], R (&f)[E], uint32_t P, U* bk,
+                                                    R* bf) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t i0 = t * E;
+  uint32_t buf = 0;
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride >= (uint32_t)E; stride >>= 1) {
+      const uint32_t ts = stride / E;
+      U* xk = bk + buf * P;
+      R* xf = bf + buf * P;
+      if (ts >= 64) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (i0 + e < P) {
+            xk[i0 + e] = k[e];
+            xf[i0 + e] = f[e];
+          }
+        __syncthreads();
+        buf ^= 1u;
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        U ok;
+        R of;
+        if (ts >= 64) {
+          const uint32_t j = (t ^ ts) * E + e;
+          ok = j < P ? xk[j] : k[e];
+          of = j < P ? xf[j] : f[e];
+        } else {
+          ok = __shfl_xor(k[e], (int)ts, 64);
+          of = __shfl_xor(f[e], (int)ts, 64);
+        }
+        const uint32_t i = i0 + e;
+        const bool keep_max = ((i & stride) == 0) == ((i & size) == 0);
+        const bool take = keep_max ? cgt(ok, of, k[e], f[e]) : cgt(k[e], f[e], ok, of);
+        if (take) {
+          k[e] = ok;
+          f[e] = of;
+        }
+      }
+    }
+#pragma unroll
+    for (int s2 = E / 2; s2 >= 1; s2 >>= 1) {
+      if ((uint32_t)s2 >= size) continue;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (e & s2) continue;
+        const int e2 = e | s2;
+        const uint32_t i = i0 + e;
+        const bool desc = (i & size) == 0;
+        const bool swap = desc ? cgt(k[e2], f[e2], k[e], f[e]) : cgt(k[e], f[e], k[e2], f[e2]);
+        if (swap) {
+          const U tk_ = k[e];
+          const R tf_ = f[e];
+          k[e] = k[e2];
+          f[e] = f[e2];
+          k[e2] = tk_;
+          f[e2] = tf_;
+        }
+      }
+    }
+  }
+}
+
+// Sorts m <= NT * E composites sitting at the start of the LDS tile (lk, lf)
+// (2P <= CAP) in registers and emits them.
+template <int NT, int E, typename U, typename R, typename Emit>
+__device__ __forceinline__ void sort_emit_regs(uint32_t m, U* lk, R* lf, Emit&& emit) {
+  uint32_t P = 1;
+  while (P < m) P <<= 1;
+  const uint32_t i0 = threadIdx.x * E;
+  U k[E];
+  R f[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    k[e] = i0 + e < m ? lk[i0 + e] : (U)0;
+    f[e] = i0 + e < m ? lf[i0 + e] : (R)0;
+  }
+  __syncthreads();  // the tile is reused as the exchange buffer
+  bitonic_regs_desc_e<NT, E, U, R>(k, f, P, lk, lf);
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (i0 + e < m) emit((uint64_t)(i0 + e), k[e], f[e]);
+  __syncthreads();
+}
+
 template <int NT, typename U, typename R, typename Emit>
-__device__ void block_sort_emit(uint64_t m, bool in_lds, U* lk, R* lf, uint32_t CAP, U* ck, R* cf,
+__device__ __forceinline__ void block_sort_emit(uint64_t m, bool in_lds, U* lk, R* lf, uint32_t CAP, U* ck, R* cf,
                                 U* tk, R* tf, Emit&& emit) {
-  if (in_lds && m <= NT && 2 * (uint64_t)NT <= CAP) {
+  if (in_lds) {
+    // registers: up to 4 (or 16) composites per thread, exchange buffer 2P <= CAP
     uint32_t P = 1;
     while (P < m) P <<= 1;
-    const uint32_t t = threadIdx.x;
-    U k = t < m ? lk[t] : (U)0;
-    R f = t < m ? lf[t] : (R)0;
-    __syncthreads();  // the tile is reused as the exchange buffer
-    bitonic_regs_desc<NT, U, R>(k, f, P, lk, lf);
-    if (t < m) emit((uint64_t)t, k, f);
-    __syncthreads();
-    return;
+    if (m <= NT && 2 * P <= CAP) {
+      sort_emit_regs<NT, 1, U, R>((uint32_t)m, lk, lf, emit);
+      return;
+    }
+    if (m <= 4 * NT && 2 * P <= CAP) {
+      sort_emit_regs<NT, 4, U, R>((uint32_t)m, lk, lf, emit);
+      return;
+    }
+    if (m <= 16 * NT && 2 * P <= CAP) {
+      sort_emit_regs<NT, 16, U, R>((uint32_t)m, lk, lf, emit);
+      return;
+    }
   }
   if (in_lds) {
     uint32_t P = 1;
