@@ -163,7 +163,9 @@ def suite_c3(a):
             t1.record(s)
             torch.cuda.synchronize()
             total_s = t0.elapsed_time(t1) * 1e-3
-            lat = plan.query_times()
+            # every query of a launch completes when the launch does: its
+            # latency from the common release time is the launch time
+            lat = np.full(Q, total_s)
             st = plan.stats()
             if best is None or total_s < best[0]:
                 best = (total_s, lat, st)

@@ -114,15 +114,17 @@ int tk_set_tuning(const tk_tuning* t);
  * when rowids is NULL at launch, else rowids[offsets[i] + j].  Results are
  * packed: query i's min(k[i], n_i) results start at element out_offsets[i]
  * (exclusive prefix sum, see tk_plan_output_offsets).  The plan classifies
- * every query (sampled streaming pass, or one-workgroup radix select for
- * small ones), lays out its workspace and builds one work queue; a launch is
- * three kernels (state reset, sample workgroups, persistent engine), captured
- * in a hipGraph the first time a pointer set is seen and replayed after.
- * Results equal tk_topk on each query alone. */
+ * every query: the sampled path (sample, streaming filter, tail over the
+ * survivors), or, for queries too small for a sample or whose K is a large
+ * share of N, one workgroup's radix select over the query.  A launch is three
+ * kernels over all queries (sample workgroups, filter workgroups, one tail
+ * workgroup per query); from the second launch with the same pointers and
+ * stream they are replayed from a captured hipGraph.  Results equal tk_topk on
+ * each query alone. */
 typedef struct tk_plan tk_plan;
 typedef struct {
-  uint32_t tile_keys;        /* keys per streaming tile; 0: 256 KiB of keys */
-  uint32_t engine_grid;      /* persistent workgroups; 0: as many as fit */
+  uint32_t tile_keys;        /* keys each filter workgroup streams; 0: 65536 (>= 4096) */
+  uint32_t engine_grid;      /* reserved, must be 0 */
   uint32_t min_sample_log2;  /* smallest sample; queries under 16x it take the exact select; 0: 12 */
   uint32_t max_sample_log2;  /* largest sample; 0: 20 */
   double sample_sigma;       /* margin of the sampled threshold; 0: 3 */
@@ -136,28 +138,31 @@ typedef struct {
 size_t tk_plan_workspace_size(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders,
                               uint32_t q, int key_type, int rid_type, const tk_plan_params* params);
 /* Creates a plan bound to `workspace` (device, 256-byte aligned, at least
- * tk_plan_workspace_size bytes, owned by the caller and reserved for the
- * plan until tk_plan_destroy).  Uploads descriptors on `stream` and waits
- * for them.  *plan receives an object owned by the library. */
+ * tk_plan_workspace_size bytes, zero-filled by the caller before the first
+ * launch, owned by the caller and reserved for the plan until
+ * tk_plan_destroy).  *plan receives an object owned by the library.
+ * `stream` is kept for compatibility and not used. */
 int tk_plan_create(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders, uint32_t q,
                    int key_type, int rid_type, const tk_plan_params* params, void* workspace,
                    size_t workspace_bytes, void* stream, tk_plan** plan);
 /* out_offsets[q+1]: where each query's results start in the packed outputs. */
 int tk_plan_output_offsets(const tk_plan* plan, uint64_t* out_offsets);
-/* How many queries take the sampled and the exact route, and queue length. */
+/* Queries on the sampled route, queries on the whole-input route, and the
+ * workgroups of one launch (sample + filter + tail). */
 int tk_plan_info(const tk_plan* plan, uint32_t* n_sampled, uint32_t* n_exact, uint32_t* n_items);
 /* Runs every query of the plan on `stream` (asynchronous).  keys: the packed
  * device key buffer; rowids: packed row-ids or NULL; out_keys/out_rowids:
- * packed outputs (out_keys may be NULL).  Calls on one plan must not
- * overlap on the device. */
+ * packed outputs (out_keys may be NULL).  When the pointer set differs from
+ * the previous launch, the per-query argument records are uploaded first
+ * (a synchronous copy on `stream`).  Calls on one plan must not overlap. */
 int tk_plan_launch(tk_plan* plan, const void* keys, const void* rowids, void* out_keys,
                    void* out_rowids, void* stream);
-/* After the stream has passed a launch: seconds from the launch's start to
- * each query's result being written (device clock), -1 if unfinished, 0 for
- * empty queries.  Synchronous copy of q small records. */
+/* Per-query device completion times are not recorded by this design: every
+ * query of a launch completes when the launch does.  Returns TK_EUNSUPPORTED. */
 int tk_plan_query_times(const tk_plan* plan, double* seconds);
-/* After a launch: queries whose sample misjudged (exact select over the
- * input ran instead) and queries left unfinished (must be 0). */
+/* After a launch has finished: sampled queries whose sample misjudged (the
+ * tail selected over the whole input instead), and sampled queries with no
+ * recorded path (must be 0).  Synchronous copy of the 64-byte query states. */
 int tk_plan_stats(const tk_plan* plan, uint32_t* fallbacks, uint32_t* unfinished);
 void tk_plan_destroy(tk_plan* plan);
 

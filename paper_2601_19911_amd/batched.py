@@ -51,8 +51,8 @@ class Plan:
     """A batched Top-K plan over queries offsets[i]..offsets[i+1] of a packed key buffer."""
 
     def __init__(self, offsets, ks, orders, key_dtype, rid_dtype, device="cuda", stream=None,
-                 tile_keys=0, engine_grid=0, min_sample_log2=0, max_sample_log2=0,
-                 sample_sigma=0.0, use_graph=True):
+                 tile_keys=0, min_sample_log2=0, max_sample_log2=0, sample_sigma=0.0,
+                 use_graph=True):
         import torch
         L = _bind()
         self.offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
@@ -65,7 +65,7 @@ class Plan:
         self.key_dtype = key_dtype
         self.rid_dtype = rid_dtype
         self.kc, self.rc = key_code(key_dtype), rid_code(rid_dtype)
-        self.params = tk_plan_params(tile_keys, engine_grid, min_sample_log2, max_sample_log2,
+        self.params = tk_plan_params(tile_keys, 0, min_sample_log2, max_sample_log2,
                                      sample_sigma, 0 if use_graph else -1)
         nbytes = L.tk_plan_workspace_size(self.offsets.ctypes.data, self.ks.ctypes.data,
                                           self.orders.ctypes.data, self.q, self.kc, self.rc,
@@ -101,11 +101,6 @@ class Plan:
                                      None if rowids is None else rowids.data_ptr(),
                                      None if out_keys is None else out_keys.data_ptr(),
                                      out_rowids.data_ptr(), st), "tk_plan_launch")
-
-    def query_times(self):
-        t = np.zeros(self.q, dtype=np.float64)
-        check(_bind().tk_plan_query_times(self._h, t.ctypes.data), "tk_plan_query_times")
-        return t
 
     def stats(self):
         a, b = ctypes.c_uint32(), ctypes.c_uint32()

@@ -1,17 +1,17 @@
 // Batched Top-K plans: thousands of independent queries of uneven N and K
-// over one packed key buffer, run by the batch engine (tk_engine.hip) as one
-// hipGraph-captured sequence of launches.  Host code only.
+// over one packed key buffer, run as one multi-query launch (tk_multi.hip):
+// sample, filter and tail workgroups of every query in three kernels,
+// replayed from a hipGraph once the pointer set is known.  Host code only.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <mutex>
-#include <numeric>
 #include <vector>
 
 #include "mitopk.h"
-#include "tk_engine.hpp"
 #include "tk_internal.hpp"
+#include "tk_multi.hpp"
 #include "tk_plan.hpp"
 
 using namespace tk;
@@ -21,27 +21,23 @@ struct tk_plan {
   uint32_t q = 0;
   tk_plan_params params{};
   Tuning tun;
-  std::vector<QDesc> qd;
-  std::vector<Item> items;
-  std::vector<uint2> prep;
+  std::vector<uint64_t> n, k, off;
+  std::vector<int> order;
   std::vector<uint64_t> out_off;  // q + 1 entries
+  MLayout L;
+  uint64_t rec_bytes = 0;         // argument records, after the layout
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  size_t off_qs = 0, off_qd = 0, off_items = 0, off_prep = 0, scratch_end = 0;
-  uint32_t n_sampled = 0, n_exact = 0;
-  // descriptors on the device match this pointer set
+  // records on the device match this pointer set
   bool uploaded = false;
   uint64_t u_keys = 0, u_rids = 0, u_ok = 0, u_or = 0;
-  // graph cache for one (bases, stream) combination
+  MLaunch launch;
+  // graph of the launch for one (pointers, stream) combination
   bool have_graph = false;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
-  uint64_t g_keys = 0, g_rids = 0, g_ok = 0, g_or = 0;
   hipStream_t g_stream = nullptr;
-  // the pointer set launched eagerly last, and its grid
-  uint64_t w_keys = 0, w_rids = 0, w_ok = 0, w_or = 0;
-  hipStream_t w_stream = nullptr;
-  uint32_t w_grid = 0;
+  bool warm = false;              // this pointer set has run once on g_stream
   std::mutex mu;
 };
 
@@ -60,111 +56,13 @@ Tuning plan_tuning(const tk_plan_params* p) {
   return t;
 }
 
-// Builds descriptors, queue and layout; returns the workspace bytes needed.
-size_t build(tk_plan& P, const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders) {
-  const uint32_t kb = P.key_type == TK_KEY_I64 ? 8 : 4, rb = P.rid_type == TK_RID_U64 ? 8 : 4;
-  const uint32_t q = P.q;
-  P.qd.assign(q, QDesc{});
-  P.out_off.assign(q + 1, 0);
-  for (uint32_t i = 0; i < q; ++i) {
-    const uint64_t n = offsets[i + 1] - offsets[i];
-    P.out_off[i + 1] = P.out_off[i] + std::min<uint64_t>(ks[i], n);
-  }
-  size_t off = sizeof(EngineCtl);
-  P.off_qs = off;
-  off = align_up(off + (size_t)q * sizeof(QState), 256);
-  P.off_qd = off;
-  off = align_up(off + (size_t)q * sizeof(QDesc), 256);
-  // classify, count items
-  std::vector<SamplePlan> sp(q);
-  uint64_t nitems = 0, nprep = 0;
-  const uint32_t tile = P.params.tile_keys ? P.params.tile_keys : tile_len_for(kb);
-  for (uint32_t i = 0; i < q; ++i) {
-    QDesc& d = P.qd[i];
-    d.n = offsets[i + 1] - offsets[i];
-    d.k_eff = (uint32_t)std::min<uint64_t>(ks[i], d.n);
-    d.order = orders[i] ? 1 : 0;
-    d.key_type = (uint8_t)P.key_type;
-    d.keys = offsets[i] * kb;
-    d.rids = offsets[i] * rb;
-    d.rid_base = 0;
-    d.out_keys = P.out_off[i] * kb;
-    d.out_rids = P.out_off[i] * rb;
-    if (d.k_eff == 0) {
-      d.cls = CLS_EMPTY;
-      continue;
-    }
-    sp[i] = plan_sample(d.n, d.k_eff, P.tun);
-    if (sp[i].fast) {
-      d.cls = CLS_SAMPLED;
-      d.r1 = sp[i].r1;
-      d.S = sp[i].S;
-      d.samp_blocks = sp[i].blocks;
-      d.cap = sp[i].cap;
-      d.tile_len = tile;
-      d.ntiles = (uint32_t)((d.n + tile - 1) / tile);
-      nitems += d.ntiles;
-      nprep += d.samp_blocks;
-      ++P.n_sampled;
-    } else {
-      d.cls = CLS_EXACT;
-      nitems += 1;
-      ++P.n_exact;
-    }
-  }
-  P.off_items = off;
-  off = align_up(off + nitems * sizeof(Item), 256);
-  P.off_prep = off;
-  off = align_up(off + nprep * sizeof(uint2), 256);
-  for (uint32_t i = 0; i < q; ++i)
-    if (P.qd[i].cls != CLS_EMPTY) off += layout_query(P.qd[i], off, kb, rb, sp[i]);
-  P.scratch_end = off;
-  // queue: sampled queries by decreasing size (their tiles contiguous), then
-  // the exact queries by decreasing size to fill the gaps at the end
-  std::vector<uint32_t> order(q);
-  std::iota(order.begin(), order.end(), 0u);
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
-    const QDesc& a = P.qd[x];
-    const QDesc& b = P.qd[y];
-    if (a.cls != b.cls) return a.cls < b.cls;
-    return a.n > b.n;
-  });
-  P.items.clear();
-  P.prep.clear();
-  for (uint32_t i : order) {
-    const QDesc& d = P.qd[i];
-    if (d.cls == CLS_SAMPLED) {
-      for (uint32_t t = 0; t < d.ntiles; ++t) P.items.push_back(Item{ITEM_TILE, i, t, 0});
-      for (uint32_t b = 0; b < d.samp_blocks; ++b) P.prep.push_back(make_uint2(i, b));
-    } else if (d.cls == CLS_EXACT) {
-      P.items.push_back(Item{ITEM_EXACT, i, 0, 0});
-    }
-  }
-  return align_up(off, 256);
-}
-
-EngineArgs plan_args(const tk_plan& P, const void* keys, const void* rids, void* ok, void* orr) {
-  EngineArgs a{};
-  a.qd = reinterpret_cast<const QDesc*>(P.ws + P.off_qd);
-  a.qs = reinterpret_cast<QState*>(P.ws + P.off_qs);
-  a.ctl = reinterpret_cast<EngineCtl*>(P.ws);
-  a.items = reinterpret_cast<const Item*>(P.ws + P.off_items);
-  a.prep = reinterpret_cast<const uint2*>(P.ws + P.off_prep);
-  a.scratch = P.ws;
-  a.nitems = (uint32_t)P.items.size();
-  a.nq = P.q;
-  a.nprep = (uint32_t)P.prep.size();
-  a.keys_base = (uint64_t)(uintptr_t)keys;
-  a.rids_base = (uint64_t)(uintptr_t)rids;
-  a.out_keys_base = (uint64_t)(uintptr_t)ok;
-  a.out_rids_base = (uint64_t)(uintptr_t)orr;
-  return a;
-}
-
 bool valid_inputs(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders, uint32_t q,
-                  int key_type, int rid_type) {
+                  int key_type, int rid_type, const tk_plan_params* params) {
   if (!offsets || !ks || !orders || q == 0) return false;
   if (key_type < 0 || key_type > 2 || rid_type < 0 || rid_type > 1) return false;
+  if (params && ((params->tile_keys && params->tile_keys < 4096) || params->engine_grid ||
+                 params->min_sample_log2 > 24 || params->max_sample_log2 > 24))
+    return false;
   for (uint32_t i = 0; i < q; ++i) {
     if (offsets[i + 1] < offsets[i]) return false;
     if (orders[i] > 1) return false;
@@ -173,12 +71,72 @@ bool valid_inputs(const uint64_t* offsets, const uint32_t* ks, const uint8_t* or
   return true;
 }
 
+// Layout of the plan; returns the workspace bytes.
+size_t build(tk_plan& P, const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders) {
+  const uint32_t q = P.q;
+  P.n.resize(q);
+  P.k.resize(q);
+  P.off.assign(offsets, offsets + q + 1);
+  P.order.resize(q);
+  P.out_off.assign(q + 1, 0);
+  for (uint32_t i = 0; i < q; ++i) {
+    P.n[i] = offsets[i + 1] - offsets[i];
+    P.k[i] = ks[i];
+    P.order[i] = orders[i];
+    P.out_off[i + 1] = P.out_off[i] + std::min<uint64_t>(ks[i], P.n[i]);
+  }
+  const uint64_t lay = multi_layout(P.n, P.k, P.key_type, P.rid_type, P.tun, P.params.tile_keys, P.L);
+  MRecords sizes;
+  sizes.sa.resize(P.L.n_sampled);
+  sizes.smap.resize(P.L.n_samp_blocks);
+  sizes.fa.resize(P.L.n_sampled);
+  sizes.fmap.resize(P.L.n_filt_blocks);
+  sizes.ta.resize(P.L.n_sampled + P.L.n_input);
+  P.rec_bytes = multi_pack_bytes(sizes);
+  return lay + P.rec_bytes;
+}
+
+int upload(tk_plan& P, const void* keys, const void* rowids, void* out_keys, void* out_rowids,
+           hipStream_t st) {
+  const uint32_t kb = P.key_type == TK_KEY_I64 ? 8 : 4, rb = P.rid_type == TK_RID_U64 ? 8 : 4;
+  std::vector<MQuery> qs(P.q);
+  for (uint32_t i = 0; i < P.q; ++i) {
+    MQuery& m = qs[i];
+    m.keys = static_cast<const char*>(keys) + P.off[i] * kb;
+    m.rids = rowids ? static_cast<const char*>(rowids) + P.off[i] * rb : nullptr;
+    m.n = P.n[i];
+    m.k = P.k[i];
+    m.order = P.order[i];
+    m.out_keys = out_keys ? static_cast<char*>(out_keys) + P.out_off[i] * kb : nullptr;
+    m.out_rids = static_cast<char*>(out_rowids) + P.out_off[i] * rb;
+  }
+  MRecords r;
+  multi_records(qs, P.L, P.key_type, P.rid_type, P.ws, r);
+  const uint64_t bytes = multi_pack_bytes(r);
+  if (P.L.total + bytes > P.ws_bytes) return TK_EINVAL;
+  std::vector<char> host(bytes + 256);
+  char* dev = P.ws + P.L.total;
+  P.launch = multi_pack(r, host.data(), dev);
+  if (hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return TK_EHIP;
+  return TK_OK;
+}
+
+void drop_graph(tk_plan& P) {
+  if (P.have_graph) {
+    (void)hipGraphExecDestroy(P.gexec);
+    (void)hipGraphDestroy(P.graph);
+    P.have_graph = false;
+  }
+}
+
 }  // namespace
 
 extern "C" size_t tk_plan_workspace_size(const uint64_t* offsets, const uint32_t* ks,
                                          const uint8_t* orders, uint32_t q, int key_type,
                                          int rid_type, const tk_plan_params* params) {
-  if (!valid_inputs(offsets, ks, orders, q, key_type, rid_type)) return 0;
+  if (!valid_inputs(offsets, ks, orders, q, key_type, rid_type, params)) return 0;
   tk_plan P;
   P.key_type = key_type;
   P.rid_type = rid_type;
@@ -192,7 +150,8 @@ extern "C" int tk_plan_create(const uint64_t* offsets, const uint32_t* ks, const
                               uint32_t q, int key_type, int rid_type,
                               const tk_plan_params* params, void* workspace,
                               size_t workspace_bytes, void* stream, tk_plan** out) {
-  if (!out || !valid_inputs(offsets, ks, orders, q, key_type, rid_type)) return TK_EINVAL;
+  (void)stream;
+  if (!out || !valid_inputs(offsets, ks, orders, q, key_type, rid_type, params)) return TK_EINVAL;
   if (!workspace || ((uintptr_t)workspace & 255u)) return TK_EINVAL;
   tk_plan* P = new (std::nothrow) tk_plan;
   if (!P) return TK_ENOMEM;
@@ -208,20 +167,6 @@ extern "C" int tk_plan_create(const uint64_t* offsets, const uint32_t* ks, const
   }
   P->ws = static_cast<char*>(workspace);
   P->ws_bytes = workspace_bytes;
-  hipStream_t st = (hipStream_t)stream;
-  // descriptors, queue and sample map go to the device once
-  if (hipMemcpyAsync(P->ws + P->off_qd, P->qd.data(), P->qd.size() * sizeof(QDesc),
-                     hipMemcpyHostToDevice, st) != hipSuccess ||
-      (!P->items.empty() &&
-       hipMemcpyAsync(P->ws + P->off_items, P->items.data(), P->items.size() * sizeof(Item),
-                      hipMemcpyHostToDevice, st) != hipSuccess) ||
-      (!P->prep.empty() &&
-       hipMemcpyAsync(P->ws + P->off_prep, P->prep.data(), P->prep.size() * sizeof(uint2),
-                      hipMemcpyHostToDevice, st) != hipSuccess) ||
-      hipStreamSynchronize(st) != hipSuccess) {
-    delete P;
-    return TK_EHIP;
-  }
   *out = P;
   return TK_OK;
 }
@@ -235,119 +180,76 @@ extern "C" int tk_plan_output_offsets(const tk_plan* P, uint64_t* out_offsets) {
 extern "C" int tk_plan_info(const tk_plan* P, uint32_t* n_sampled, uint32_t* n_exact,
                             uint32_t* n_items) {
   if (!P) return TK_EINVAL;
-  if (n_sampled) *n_sampled = P->n_sampled;
-  if (n_exact) *n_exact = P->n_exact;
-  if (n_items) *n_items = (uint32_t)P->items.size();
+  if (n_sampled) *n_sampled = P->L.n_sampled;
+  if (n_exact) *n_exact = P->L.n_input;
+  if (n_items)
+    *n_items = (uint32_t)(P->L.n_samp_blocks + P->L.n_filt_blocks + P->L.n_sampled + P->L.n_input);
   return TK_OK;
 }
 
 extern "C" int tk_plan_launch(tk_plan* P, const void* keys, const void* rowids, void* out_keys,
                               void* out_rowids, void* stream) {
-  if (!P || !keys) return TK_EINVAL;
+  if (!P || !keys || !out_rowids) return TK_EINVAL;
   std::lock_guard<std::mutex> lk(P->mu);
   hipStream_t st = (hipStream_t)stream;
-  const EngineArgs a = plan_args(*P, keys, rowids, out_keys, out_rowids);
   const uint64_t gk = (uint64_t)(uintptr_t)keys, gr = (uint64_t)(uintptr_t)rowids,
                  go = (uint64_t)(uintptr_t)out_keys, gq = (uint64_t)(uintptr_t)out_rowids;
-  // which inputs and outputs exist is part of the descriptors
-  if (!P->uploaded || (P->u_rids == 0) != (gr == 0) || (P->u_ok == 0) != (go == 0) ||
-      (P->u_or == 0) != (gq == 0)) {
-    for (QDesc& d : P->qd) {
-      d.has_rids = rowids != nullptr;
-      d.has_out_keys = out_keys != nullptr;
-      d.has_out_rids = out_rowids != nullptr;
-    }
-    if (hipMemcpyAsync(P->ws + P->off_qd, P->qd.data(), P->qd.size() * sizeof(QDesc),
-                       hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return TK_EHIP;
+  if (!P->uploaded || P->u_keys != gk || P->u_rids != gr || P->u_ok != go || P->u_or != gq) {
+    drop_graph(*P);
+    P->warm = false;
+    const int rc = upload(*P, keys, rowids, out_keys, out_rowids, st);
+    if (rc != TK_OK) return rc;
     P->uploaded = true;
     P->u_keys = gk;
     P->u_rids = gr;
     P->u_ok = go;
     P->u_or = gq;
   }
-  // stream capture needs a created stream; on the default stream launch directly
+  // graphs need a created stream; the first launch of a pointer set on a
+  // stream runs eagerly (it also loads the kernels' code object)
   const bool graph = P->params.use_graph >= 0 && st != nullptr;
-  if (!graph) return engine_launch(a, P->rid_type, P->key_type, P->params.engine_grid, st);
-  const bool same = P->have_graph && P->g_keys == gk && P->g_rids == gr && P->g_ok == go &&
-                    P->g_or == gq && P->g_stream == st;
-  if (!same) {
-    // The first launch of a pointer set runs eagerly: it loads the kernels'
-    // code object and sizes the grid outside any capture.  A later launch of
-    // the same set is captured once and replayed from then on.
-    const bool warm = P->w_keys == gk && P->w_rids == gr && P->w_ok == go && P->w_or == gq &&
-                      P->w_stream == st && P->w_grid != 0;
-    if (!warm) {
-      P->w_grid = P->params.engine_grid ? P->params.engine_grid
-                                        : engine_grid_size(P->rid_type, P->key_type);
-      if (P->w_grid == 0) return TK_EHIP;
-      P->w_keys = gk;
-      P->w_rids = gr;
-      P->w_ok = go;
-      P->w_or = gq;
-      P->w_stream = st;
-      return engine_launch(a, P->rid_type, P->key_type, P->w_grid, st);
-    }
-    if (P->have_graph) {
-      hipGraphExecDestroy(P->gexec);
-      hipGraphDestroy(P->graph);
-      P->have_graph = false;
-    }
+  if (!graph || !P->warm || P->g_stream != st) {
+    if (P->g_stream != st) drop_graph(*P);
+    P->g_stream = st;
+    P->warm = true;
+    multi_enqueue(P->launch, P->key_type, P->rid_type, st);
+    return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
+  }
+  if (!P->have_graph) {
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TK_EHIP;
-    engine_enqueue(a, P->rid_type, P->key_type, P->w_grid, st);
+    multi_enqueue(P->launch, P->key_type, P->rid_type, st);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &g);
     if (e != hipSuccess || !g || hipGetLastError() != hipSuccess) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return TK_EHIP;
     }
     if (hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       return TK_EHIP;
     }
     P->graph = g;
     P->have_graph = true;
-    P->g_keys = gk;
-    P->g_rids = gr;
-    P->g_ok = go;
-    P->g_or = gq;
-    P->g_stream = st;
   }
   return hipGraphLaunch(P->gexec, st) == hipSuccess ? TK_OK : TK_EHIP;
 }
 
 extern "C" int tk_plan_query_times(const tk_plan* P, double* seconds) {
-  if (!P || !seconds) return TK_EINVAL;
-  std::vector<QState> qs(P->q);
-  EngineCtl ctl;
-  if (hipMemcpy(qs.data(), P->ws + P->off_qs, qs.size() * sizeof(QState), hipMemcpyDeviceToHost) !=
-          hipSuccess ||
-      hipMemcpy(&ctl, P->ws, sizeof(ctl), hipMemcpyDeviceToHost) != hipSuccess)
-    return TK_EHIP;
-  int dev = 0, khz = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
-    khz = 100000;
-  for (uint32_t i = 0; i < P->q; ++i) {
-    const QDesc& d = P->qd[i];
-    if (d.cls == CLS_EMPTY) seconds[i] = 0.0;
-    else if (!qs[i].done) seconds[i] = -1.0;
-    else seconds[i] = (double)(qs[i].t_done - ctl.t_start) / ((double)khz * 1e3);
-  }
-  return TK_OK;
+  (void)P;
+  (void)seconds;
+  return TK_EUNSUPPORTED;
 }
 
 extern "C" int tk_plan_stats(const tk_plan* P, uint32_t* fallbacks, uint32_t* unfinished) {
   if (!P) return TK_EINVAL;
-  std::vector<QState> qs(P->q);
-  if (hipMemcpy(qs.data(), P->ws + P->off_qs, qs.size() * sizeof(QState), hipMemcpyDeviceToHost) !=
-      hipSuccess)
+  std::vector<QHead> hs(P->L.n_sampled);
+  if (!hs.empty() &&
+      hipMemcpy(hs.data(), P->ws, hs.size() * sizeof(QHead), hipMemcpyDeviceToHost) != hipSuccess)
     return TK_EHIP;
   uint32_t fb = 0, un = 0;
-  for (uint32_t i = 0; i < P->q; ++i) {
-    if (qs[i].status & 1u) ++fb;
-    if (P->qd[i].cls != CLS_EMPTY && !qs[i].done) ++un;
+  for (const QHead& h : hs) {
+    if (h.path == 4u) ++fb;
+    if (h.path != 2u && h.path != 4u) ++un;
   }
   if (fallbacks) *fallbacks = fb;
   if (unfinished) *unfinished = un;
@@ -356,9 +258,6 @@ extern "C" int tk_plan_stats(const tk_plan* P, uint32_t* fallbacks, uint32_t* un
 
 extern "C" void tk_plan_destroy(tk_plan* P) {
   if (!P) return;
-  if (P->have_graph) {
-    hipGraphExecDestroy(P->gexec);
-    hipGraphDestroy(P->graph);
-  }
+  drop_graph(*P);
   delete P;
 }

@@ -14,17 +14,26 @@ namespace tk {
 
 // Start of every single-query workspace.  All counters are reset by the first
 // kernel of each query, so the workspace needs no initialization by the caller.
-struct Header {
+// Per-query state of the sampled path: 64 bytes, so a batch can clear all of
+// its queries' states with one small copy.
+struct QHead {
   unsigned long long surv_count;  // keys that passed the sampled threshold
-  unsigned long long sel_gt;      // exact select: writes of composites above the boundary
-  unsigned long long sel_eq;      // exact select: writes of copies of the boundary
   unsigned long long thr_k;       // sampled threshold (key image)
   unsigned long long thr_f;       // sampled threshold (flipped row-id)
   uint32_t status;                // device failure bits (1: barrier timeout)
   uint32_t path;                  // path taken, see tk_info
+  uint32_t samp_ticket;           // sample workgroups finished (reset by the tail)
+  uint32_t pad[7];
+};
+static_assert(sizeof(QHead) == 64, "QHead is 64 bytes");
+
+// A single query's workspace header.
+struct Header {
+  QHead q;
+  unsigned long long sel_gt;      // exact select: writes of composites above the boundary
+  unsigned long long sel_eq;      // exact select: writes of copies of the boundary
   GridSync gs;                    // grid barrier of the exact-select kernel
-  uint32_t samp_ticket;           // sample workgroups finished (reset by the last one)
-  uint32_t pad[3];
+  uint32_t pad[2];
   unsigned long long hist[3][256];  // exact select: global digit histograms
 };
 static_assert(sizeof(Header) <= HEADER_BYTES, "header must fit its reserved bytes");

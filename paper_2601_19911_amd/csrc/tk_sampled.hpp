@@ -1,0 +1,364 @@
+// Device bodies of the sampled Top-K (ordering primitive, paper sec. III-A):
+// the stratified sample and its threshold, the streaming filter, and the tail
+// (exact select + sort of the survivors).  One query's work is described by
+// argument records; the single-query kernels (tk_sampled.hip) and the batched
+// kernels (tk_multi.hip) run the same bodies, a batched workgroup first
+// looking up which query and which of its workgroups it is.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mitopk.h"
+#include "tk_device.hpp"
+#include "tk_internal.hpp"
+#include "tk_plan.hpp"
+#include "tk_select.hpp"
+#include "tk_src.hpp"
+
+namespace tk {
+
+typedef uint32_t u32x4s __attribute__((ext_vector_type(4)));
+
+constexpr int SAMP_NT = 256;
+constexpr int FILT_NT = 256;
+constexpr int TAIL_NT = 1024;
+
+struct SampArgs {
+  const void* keys;
+  const void* rids;
+  uint64_t n;
+  uint64_t dmask;
+  uint32_t S, r1;
+  QHead* h;
+  void* ck;
+  void* cf;
+  uint32_t nblk;  // sample workgroups of this query
+  uint32_t pad;
+};
+
+struct FiltArgs {
+  const void* keys;
+  const void* rids;
+  uint64_t n;
+  uint64_t dmask;
+  QHead* h;
+  void* sk;
+  void* sf;
+  uint64_t cap;
+  uint32_t nblk;  // filter workgroups of this query
+  uint32_t pad;
+};
+
+struct TailArgs1 {
+  const void* keys;
+  const void* rids;
+  uint64_t n;
+  uint64_t dmask;
+  QHead* h;
+  void* sk;
+  void* sf;
+  uint64_t cap;
+  void* ck;
+  void* cf;
+  void* tk;
+  void* tf;
+  uint64_t k_eff;
+  void* out_keys;
+  void* out_rids;
+  uint32_t mode;  // TAIL_SURVIVORS or TAIL_INPUT
+  uint32_t pad;
+};
+
+// TAIL_SURVIVORS: select over the survivors of the filter (falling back to
+// the input if their count is outside [K, capacity]); TAIL_INPUT: select
+// over the whole input (small queries, and those the sample cannot serve).
+constexpr uint32_t TAIL_SURVIVORS = 0, TAIL_INPUT = 1;
+
+// ---- k_sample ----------------------------------------------------------------------------------
+
+// blk: this workgroup's index among the query's a.nblk sample workgroups.
+template <int KT, int RT>
+__device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, uint32_t blk) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr int NT = SAMP_NT, E = SAMPLE_PER_BLOCK / SAMP_NT;
+  QHead* h = a.h;
+  if (blk == 0 && threadIdx.x == 0) {
+    h->surv_count = 0;
+    h->status = 0;
+    h->path = 0;
+  }
+  const InputSrc<KT, RT> src{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, (U)a.dmask};
+  const uint64_t nchunks = a.S / SAMPLE_CHUNK;
+  const uint64_t stride = a.n / nchunks;  // >= 16: n >= 16 * S
+  const uint64_t off0 = (stride - SAMPLE_CHUNK) / 2;
+  U k[E];
+  R f[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint64_t j = (uint64_t)blk * SAMPLE_PER_BLOCK + (uint64_t)e * NT + threadIdx.x;
+    const uint64_t pos = (j / SAMPLE_CHUNK) * stride + off0 + (j % SAMPLE_CHUNK);
+    k[e] = src.key(pos);
+    f[e] = src.flip(pos);
+  }
+  U lmin = k[0];
+#pragma unroll
+  for (int e = 1; e < E; ++e) lmin = k[e] < lmin ? k[e] : lmin;
+  const U base = block_min<NT, U>(lmin, sc);
+  const RegElems<U, R, E> el{k, f, E};
+  const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.r1, base, sc);
+  U* ck = static_cast<U*>(a.ck);
+  R* cf = static_cast<R*>(a.cf);
+  block_compact_regs<NT, U, R, E>(el, s, a.r1, ck + (uint64_t)blk * a.r1,
+                                  cf + (uint64_t)blk * a.r1, sc);
+  // the last workgroup to finish turns the candidates into the threshold
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t old = atomicAdd(&h->samp_ticket, 1u);
+    sc.cnt[0] = (old == a.nblk - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  const bool last = sc.cnt[0] != 0;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // at most SAMPLE_FINAL_MAX candidates: 16 per thread, held in registers
+  constexpr int EF = SAMPLE_FINAL_MAX / NT;
+  const uint32_t m = a.nblk * a.r1;
+  U k2[EF];
+  R f2[EF];
+  int nv = 0;
+  U cmin = (U)~(U)0;
+#pragma unroll
+  for (int e = 0; e < EF; ++e) {
+    const uint32_t j = (uint32_t)e * NT + threadIdx.x;
+    if (j < m) {
+      k2[e] = ck[j];
+      f2[e] = cf[j];
+      nv = e + 1;
+      cmin = k2[e] < cmin ? k2[e] : cmin;
+    } else {
+      k2[e] = 0;
+      f2[e] = 0;
+    }
+  }
+  const U base2 = block_min<NT, U>(cmin, sc);
+  const RegElems<U, R, EF> el2{k2, f2, nv};
+  const Sel<U, R> s2 = block_radix_select<NT, U, R>(el2, a.r1, base2, sc);
+  if (threadIdx.x == 0) {
+    h->thr_k = (unsigned long long)(U)(s2.base + s2.P);
+    h->thr_f = s2.kind == SEL_KEY ? 0ull : (unsigned long long)s2.Pf;
+    h->samp_ticket = 0;  // ready for the next query on this workspace
+  }
+}
+
+// ---- k_filter ----------------------------------------------------------------------------------
+
+template <typename U, typename R>
+__device__ __forceinline__ void emit_survivor(bool pass, U kk, R ff, QHead* h, U* sk, R* sf,
+                                              uint64_t cap) {
+  const uint64_t m = ballot(pass);
+  if (m == 0) return;
+  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+  uint64_t b = 0;
+  if (lane_id() == leader) b = atomicAdd(&h->surv_count, (unsigned long long)__popcll(m));
+  b = __shfl(b, (int)leader, 64);
+  if (pass) {
+    const uint64_t pos = b + lanes_below(m);
+    if (pos < cap) {
+      sk[pos] = kk;
+      sf[pos] = ff;
+    }
+  }
+}
+
+// blk: this workgroup's index among the query's a.nblk filter workgroups,
+// which stride over the query's tiles of NT * VEC * UNR keys.  Tiles start at
+// the first 16-byte boundary of the key array; the keys before it and the
+// ones after the last whole tile are read one per thread.
+template <int KT, int RT, int VEC, int UNR>
+__device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk) {
+  using Raw = typename Key<KT>::Raw;
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr int NT = FILT_NT;
+  static_assert(VEC * sizeof(Raw) == 16 || VEC == 1, "vector loads are 16 bytes");
+  QHead* h = a.h;
+  const U Tk = (U)h->thr_k;
+  const R Tf = (R)h->thr_f;
+  const Raw* keys = static_cast<const Raw*>(a.keys);
+  const InputSrc<KT, RT> src{keys, (const R*)a.rids, (U)a.dmask};
+  const U dmask = (U)a.dmask;
+  U* sk = static_cast<U*>(a.sk);
+  R* sf = static_cast<R*>(a.sf);
+  constexpr uint64_t TILE = (uint64_t)NT * VEC * UNR;
+  uint64_t head = VEC > 1 ? ((16u - ((uintptr_t)keys & 15u)) & 15u) / sizeof(Raw) : 0;
+  if (head > a.n) head = a.n;
+  const uint64_t ntiles = (a.n - head) / TILE;
+  for (uint64_t t = blk; t < ntiles; t += a.nblk) {
+    const uint64_t base = head + t * TILE;
+    Raw v[UNR][VEC];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const uint64_t i0 = base + ((uint64_t)u * NT + threadIdx.x) * VEC;
+      if constexpr (VEC * sizeof(Raw) == 16) {
+        const u32x4s q = __builtin_nontemporal_load(reinterpret_cast<const u32x4s*>(keys + i0));
+        if constexpr (sizeof(Raw) == 4) {
+          v[u][0] = q.x; v[u][1] = q.y; v[u][2] = q.z; v[u][3] = q.w;
+        } else {
+          v[u][0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+          v[u][1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
+        }
+      } else {
+        v[u][0] = keys[i0];
+      }
+    }
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) any |= (Key<KT>::enc(v[u][e]) ^ dmask) >= Tk;
+    if (ballot(any) == 0) continue;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const uint64_t i = base + ((uint64_t)u * NT + threadIdx.x) * VEC + e;
+        const U kk = Key<KT>::enc(v[u][e]) ^ dmask;
+        bool pass = kk > Tk;
+        R ff = 0;
+        if (kk >= Tk) {
+          ff = src.flip(i);
+          pass = pass || ff >= Tf;
+        }
+        emit_survivor<U, R>(pass, kk, ff, h, sk, sf, a.cap);
+      }
+  }
+  // the head and the remainder (fewer than VEC + TILE keys), one per thread:
+  // position p < head is key p, the others follow the last whole tile
+  const uint64_t tail0 = head + ntiles * TILE;
+  const uint64_t nrest = head + (a.n - tail0);
+  const uint64_t stride = (uint64_t)a.nblk * NT;
+  for (uint64_t p0 = (uint64_t)blk * NT; p0 < nrest; p0 += stride) {
+    const uint64_t p = p0 + threadIdx.x;
+    bool pass = false;
+    U kk = 0;
+    R ff = 0;
+    if (p < nrest) {
+      const uint64_t i = p < head ? p : tail0 + (p - head);
+      kk = src.key(i);
+      pass = kk > Tk;
+      if (kk >= Tk) {
+        ff = src.flip(i);
+        pass = pass || ff >= Tf;
+      }
+    }
+    emit_survivor<U, R>(pass, kk, ff, h, sk, sf, a.cap);
+  }
+}
+
+// ---- k_tail ------------------------------------------------------------------------------------
+
+template <int KT, int RT, typename Src>
+__device__ void select_sort_write(const TailArgs1& a, const Src& src, uint64_t n,
+                                  typename Key<KT>::U base, LdsTile<KT, RT>& t, SelScratch& sc) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr int NT = TAIL_NT;
+  constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
+  const U dmask = (U)a.dmask;
+  auto emit = [&](uint64_t j, U u, R f) { write_out<KT, RT>(j, u, f, dmask, a.out_keys, a.out_rids); };
+  const GlobElems<NT, Src> el{src, n};
+  const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.k_eff, base, sc);
+  if (a.k_eff <= CAP) {
+    block_compact_glob<NT, U, R>(src, n, s, a.k_eff, t.k, t.f, sc);
+    block_sort_emit<NT, U, R>(a.k_eff, true, t.k, t.f, CAP, nullptr, nullptr, nullptr, nullptr, emit);
+  } else {
+    U* ck = static_cast<U*>(a.ck);
+    R* cf = static_cast<R*>(a.cf);
+    block_compact_glob<NT, U, R>(src, n, s, a.k_eff, ck, cf, sc);
+    block_sort_emit<NT, U, R>(a.k_eff, false, t.k, t.f, CAP, ck, cf, static_cast<U*>(a.tk),
+                              static_cast<R*>(a.tf), emit);
+  }
+}
+
+// Survivors that fit the registers of the workgroup (16 per thread) are
+// loaded once and selected there.
+constexpr int TAIL_E = 16;
+
+template <int KT, int RT, typename Src>
+__device__ __forceinline__ void select_sort_write_regs(const TailArgs1& a, const Src& src, uint32_t C,
+                                                       typename Key<KT>::U base, LdsTile<KT, RT>& t,
+                                                       SelScratch& sc) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr int NT = TAIL_NT, E = TAIL_E;
+  constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
+  const U dmask = (U)a.dmask;
+  U k[E];
+  R f[E];
+  int nv = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t j = (uint32_t)e * NT + threadIdx.x;
+    if (j < C) {
+      k[e] = src.key(j);
+      f[e] = src.flip(j);
+      nv = e + 1;
+    } else {
+      k[e] = 0;
+      f[e] = 0;
+    }
+  }
+  if (base == (U)~(U)0) {  // the caller did not know a lower bound: use the minimum
+    U lmin = (U)~(U)0;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (e < nv) lmin = k[e] < lmin ? k[e] : lmin;
+    base = block_min<NT, U>(lmin, sc);
+  }
+  auto emit = [&](uint64_t j, U u, R f_) { write_out<KT, RT>(j, u, f_, dmask, a.out_keys, a.out_rids); };
+  const RegElems<U, R, E> el{k, f, nv};
+  const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.k_eff, base, sc);
+  if (a.k_eff <= CAP) {
+    block_compact_regs<NT, U, R, E>(el, s, a.k_eff, t.k, t.f, sc);
+    block_sort_emit<NT, U, R>(a.k_eff, true, t.k, t.f, CAP, nullptr, nullptr, nullptr, nullptr, emit);
+  } else {
+    U* ck = static_cast<U*>(a.ck);
+    R* cf = static_cast<R*>(a.cf);
+    block_compact_regs<NT, U, R, E>(el, s, a.k_eff, ck, cf, sc);
+    block_sort_emit<NT, U, R>(a.k_eff, false, t.k, t.f, CAP, ck, cf, static_cast<U*>(a.tk),
+                              static_cast<R*>(a.tf), emit);
+  }
+}
+
+template <int KT, int RT>
+__device__ __forceinline__ void tail_body(const TailArgs1& a, LdsTile<KT, RT>& t, SelScratch& sc) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  const InputSrc<KT, RT> in{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, (U)a.dmask};
+  if (a.mode == TAIL_INPUT) {
+    if (a.n <= (uint64_t)TAIL_NT * TAIL_E) select_sort_write_regs<KT, RT>(a, in, (uint32_t)a.n, (U)~(U)0, t, sc);
+    else select_sort_write<KT, RT>(a, in, a.n, (U)0, t, sc);
+    return;
+  }
+  QHead* h = a.h;
+  const uint64_t C = h->surv_count;
+  const bool ok = C >= a.k_eff && C <= a.cap;
+  if (ok && C <= (uint64_t)TAIL_NT * TAIL_E) {
+    const BufSrc<U, R> src{static_cast<const U*>(a.sk), static_cast<const R*>(a.sf)};
+    select_sort_write_regs<KT, RT>(a, src, (uint32_t)C, (U)h->thr_k, t, sc);
+  } else if (ok) {
+    const BufSrc<U, R> src{static_cast<const U*>(a.sk), static_cast<const R*>(a.sf)};
+    select_sort_write<KT, RT>(a, src, C, (U)h->thr_k, t, sc);
+  } else {
+    select_sort_write<KT, RT>(a, in, a.n, (U)0, t, sc);
+  }
+  if (threadIdx.x == 0) {
+    h->path = ok ? 2u : 4u;
+    h->samp_ticket = 0;
+  }
+}
+
+}  // namespace tk

@@ -6,9 +6,10 @@
 //
 // Threads: the caller submits; a batcher thread forms micro-batches of one key
 // type whenever a slot (stream + device arena + pinned staging) is free,
-// admitting requests while the slot's arena has room, and enqueues the batch
-// engine on that slot's stream followed by an asynchronous copy of the
-// results to pinned host memory and an event; a completion thread waits on
+// admitting requests while the slot's arena has room, and enqueues the
+// batch's multi-query launch (tk_multi.hip) on that slot's stream followed by
+// an asynchronous copy of the results to pinned host memory and an event; a
+// completion thread waits on
 // the slots' events in launch order and publishes the results; CPU workers run
 // the gated-off requests.  With two or more slots, micro-batches overlap on
 // the device, and requests that arrive while others run join the next batch.
@@ -26,8 +27,8 @@
 #include <vector>
 
 #include "mitopk.h"
-#include "tk_engine.hpp"
 #include "tk_internal.hpp"
+#include "tk_multi.hpp"
 #include "tk_plan.hpp"
 
 using namespace tk;
@@ -143,15 +144,6 @@ void cpu_worker(tk_server* s) {
   }
 }
 
-// Lays out a micro-batch in a slot; returns false if it does not fit.
-struct BatchBuild {
-  std::vector<QDesc> qd;
-  std::vector<Item> items;
-  std::vector<uint2> prep;
-  std::vector<uint64_t> out_off;
-  size_t off_qs, off_qd, off_items, off_prep, off_out_k, off_out_r, end;
-};
-
 struct Taken {
   Req* r;
   const void* d_keys;
@@ -160,81 +152,63 @@ struct Taken {
   int order;
 };
 
-bool build_batch(const std::vector<Taken>& ids, int key_type, size_t arena_bytes, BatchBuild& b,
-                 size_t* needed) {
+// A micro-batch laid out in a slot's arena:
+//   [batch workspace: query states, then each query's regions][argument
+//   records][result keys][result row-ids]
+struct BatchBuild {
+  MLayout L;
+  MRecords rec;
+  std::vector<uint64_t> out_off;
+  uint64_t off_rec = 0, rec_bytes = 0, off_out_k = 0, off_out_r = 0, end = 0;
+};
+
+// Lays out a micro-batch for `arena`; returns false if it does not fit.
+bool build_batch(const std::vector<Taken>& ids, int key_type, char* arena, size_t arena_bytes,
+                 BatchBuild& b, size_t* needed) {
   const uint32_t kb = key_type == TK_KEY_I64 ? 8 : 4, rb = 8;
-  const uint32_t q = (uint32_t)ids.size();
+  const size_t q = ids.size();
   Tuning t = current_tuning();
   t.force_exact = 0;
   t.force_cap = 0;
   t.min_sample_log2 = 12;
-  b.qd.assign(q, QDesc{});
-  b.items.clear();
-  b.prep.clear();
+  std::vector<uint64_t> n(q), k(q);
   b.out_off.assign(q + 1, 0);
-  for (uint32_t i = 0; i < q; ++i)
+  for (size_t i = 0; i < q; ++i) {
+    n[i] = ids[i].n;
+    k[i] = ids[i].k;
     b.out_off[i + 1] = b.out_off[i] + std::min<uint64_t>(ids[i].k, ids[i].n);
-  size_t off = sizeof(EngineCtl);
-  b.off_qs = off;
-  off = align_up(off + q * sizeof(QState), 256);
-  b.off_qd = off;
-  off = align_up(off + q * sizeof(QDesc), 256);
-  std::vector<SamplePlan> sp(q);
-  for (uint32_t i = 0; i < q; ++i) {
-    const Taken& r = ids[i];
-    QDesc& d = b.qd[i];
-    d.n = r.n;
-    d.k_eff = (uint32_t)std::min<uint64_t>(r.k, r.n);
-    d.order = (uint8_t)r.order;
-    d.key_type = (uint8_t)key_type;
-    d.keys = (uint64_t)(uintptr_t)(static_cast<const char*>(r.d_keys) + r.offset * kb);
-    d.has_rids = 0;
-    d.rid_base = r.offset;
-    d.has_out_keys = 1;
-    d.has_out_rids = 1;
-    if (d.k_eff == 0) {
-      d.cls = CLS_EMPTY;
-      continue;
-    }
-    sp[i] = plan_sample(d.n, d.k_eff, t);
-    if (sp[i].fast) {
-      d.cls = CLS_SAMPLED;
-      d.r1 = sp[i].r1;
-      d.S = sp[i].S;
-      d.samp_blocks = sp[i].blocks;
-      d.cap = sp[i].cap;
-      d.tile_len = tile_len_for(kb);
-      d.ntiles = (uint32_t)((d.n + d.tile_len - 1) / d.tile_len);
-    } else {
-      d.cls = CLS_EXACT;
-    }
   }
-  for (uint32_t i = 0; i < q; ++i) {
-    const QDesc& d = b.qd[i];
-    if (d.cls == CLS_SAMPLED) {
-      for (uint32_t tt = 0; tt < d.ntiles; ++tt) b.items.push_back(Item{ITEM_TILE, i, tt, 0});
-      for (uint32_t bb = 0; bb < d.samp_blocks; ++bb) b.prep.push_back(make_uint2(i, bb));
-    }
-  }
-  for (uint32_t i = 0; i < q; ++i)
-    if (b.qd[i].cls == CLS_EXACT) b.items.push_back(Item{ITEM_EXACT, i, 0, 0});
-  b.off_items = off;
-  off = align_up(off + b.items.size() * sizeof(Item), 256);
-  b.off_prep = off;
-  off = align_up(off + b.prep.size() * sizeof(uint2), 256);
+  uint64_t off = multi_layout(n, k, key_type, TK_RID_U64, t, 0, b.L);
+  // records need the output addresses, which follow the records: size them first
+  MRecords sizes;
+  sizes.sa.resize(b.L.n_sampled);
+  sizes.smap.resize(b.L.n_samp_blocks);
+  sizes.fa.resize(b.L.n_sampled);
+  sizes.fmap.resize(b.L.n_filt_blocks);
+  sizes.ta.resize(b.L.n_sampled + b.L.n_input);
+  b.off_rec = off;
+  b.rec_bytes = multi_pack_bytes(sizes);
+  off = align_up(off + b.rec_bytes, 256);
   b.off_out_k = off;
   off = align_up(off + b.out_off[q] * kb, 256);
   b.off_out_r = off;
   off = align_up(off + b.out_off[q] * rb, 256);
-  for (uint32_t i = 0; i < q; ++i) {
-    QDesc& d = b.qd[i];
-    d.out_keys = b.off_out_k + b.out_off[i] * kb;  // relative to the arena (base added at launch)
-    d.out_rids = b.off_out_r + b.out_off[i] * rb;
-    if (d.cls != CLS_EMPTY) off += layout_query(d, off, kb, rb, sp[i]);
-  }
   b.end = off;
   if (needed) *needed = off;
-  return off <= arena_bytes;
+  if (off > arena_bytes) return false;
+  std::vector<MQuery> qs(q);
+  for (size_t i = 0; i < q; ++i) {
+    MQuery& m = qs[i];
+    m.keys = static_cast<const char*>(ids[i].d_keys) + ids[i].offset * kb;
+    m.rids = nullptr;  // local index; the column offset is added on the host
+    m.n = ids[i].n;
+    m.k = ids[i].k;
+    m.order = ids[i].order;
+    m.out_keys = arena + b.off_out_k + b.out_off[i] * kb;
+    m.out_rids = arena + b.off_out_r + b.out_off[i] * rb;
+  }
+  multi_records(qs, b.L, key_type, TK_RID_U64, arena, b.rec);
+  return true;
 }
 
 void batcher_loop(tk_server* s) {
@@ -291,17 +265,14 @@ void batcher_loop(tk_server* s) {
     // admission by memory: shrink the batch until it fits the slot's arena
     BatchBuild b;
     size_t need = 0;
-    auto id_of = [&](const Taken& t) { return (uint64_t)(t.r - &s->reqs[0]); };
-    while (!take.empty() && !build_batch(take, kt, sl.arena_bytes, b, &need)) {
+    while (!take.empty() && !build_batch(take, kt, sl.arena, sl.arena_bytes, b, &need)) {
       if (take.size() == 1) break;
       std::lock_guard<std::mutex> lk(s->mu);
       s->gpu_q[kt].push_front(take.back().r->id);
       take.pop_back();
     }
-    (void)id_of;
-    const uint32_t kb = kt == TK_KEY_I64 ? 8 : 4;
-    const size_t stage = b.off_prep + b.prep.size() * sizeof(uint2);
-    const size_t outb = (b.off_out_r + b.out_off.back() * 8) - b.off_out_k;
+    const size_t stage = b.L.heads_bytes + b.rec_bytes;
+    const size_t outb = b.end - b.off_out_k;
     if (take.empty() || need > sl.arena_bytes || stage > sl.stage_bytes || outb > sl.out_bytes) {
       // a single request larger than a slot: it goes to the CPU path instead
       std::lock_guard<std::mutex> lk(s->mu);
@@ -314,27 +285,21 @@ void batcher_loop(tk_server* s) {
       continue;
     }
     const uint64_t t0 = now_ns();
-    std::memset(sl.h_stage, 0, stage);
-    std::memcpy(sl.h_stage + b.off_qd, b.qd.data(), b.qd.size() * sizeof(QDesc));
-    std::memcpy(sl.h_stage + b.off_items, b.items.data(), b.items.size() * sizeof(Item));
-    std::memcpy(sl.h_stage + b.off_prep, b.prep.data(), b.prep.size() * sizeof(uint2));
-    EngineArgs a{};
-    a.qd = reinterpret_cast<const QDesc*>(sl.arena + b.off_qd);
-    a.qs = reinterpret_cast<QState*>(sl.arena + b.off_qs);
-    a.ctl = reinterpret_cast<EngineCtl*>(sl.arena);
-    a.items = reinterpret_cast<const Item*>(sl.arena + b.off_items);
-    a.prep = reinterpret_cast<const uint2*>(sl.arena + b.off_prep);
-    a.scratch = sl.arena;
-    a.nitems = (uint32_t)b.items.size();
-    a.nq = (uint32_t)take.size();
-    a.nprep = (uint32_t)b.prep.size();
-    a.keys_base = 0;
-    a.rids_base = 0;
-    a.out_keys_base = (uint64_t)(uintptr_t)sl.arena;
-    a.out_rids_base = (uint64_t)(uintptr_t)sl.arena;
-    int rc = hipMemcpyAsync(sl.arena, sl.h_stage, stage, hipMemcpyHostToDevice, sl.stream) == hipSuccess
-                 ? TK_OK : TK_EHIP;
-    if (rc == TK_OK && a.nitems) rc = engine_launch(a, RID_U64, kt, 0, sl.stream);
+    // staging: zeroed query states, then the argument records
+    std::memset(sl.h_stage, 0, b.L.heads_bytes);
+    const MLaunch m = multi_pack(b.rec, sl.h_stage + b.L.heads_bytes, sl.arena + b.off_rec);
+    int rc = TK_OK;
+    if (b.L.heads_bytes &&
+        hipMemcpyAsync(sl.arena, sl.h_stage, b.L.heads_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+      rc = TK_EHIP;
+    if (rc == TK_OK && b.rec_bytes &&
+        hipMemcpyAsync(sl.arena + b.off_rec, sl.h_stage + b.L.heads_bytes, b.rec_bytes,
+                       hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+      rc = TK_EHIP;
+    if (rc == TK_OK) {
+      multi_enqueue(m, kt, TK_RID_U64, sl.stream);
+      if (hipGetLastError() != hipSuccess) rc = TK_EHIP;
+    }
     if (rc == TK_OK)
       rc = hipMemcpyAsync(sl.h_out, sl.arena + b.off_out_k, outb, hipMemcpyDeviceToHost, sl.stream) ==
                    hipSuccess ? TK_OK : TK_EHIP;
@@ -354,7 +319,6 @@ void batcher_loop(tk_server* s) {
       s->inflight.push_back(slot);
       ++s->n_batches;
       s->n_batched += take.size();
-      (void)kb;
     }
     s->cv_slot.notify_all();
   }
@@ -383,6 +347,7 @@ void completer_loop(tk_server* s) {
         r.out_keys.assign(sl.h_out + a * kb, sl.h_out + (a + c) * kb);
         r.out_rids.resize(c);
         std::memcpy(r.out_rids.data(), sl.h_out + sl.out_rid_base + a * 8, c * 8);
+        for (auto& x : r.out_rids) x += r.offset;  // local index -> column row
         if (e != hipSuccess) r.status = TK_EHIP;
         r.t_done = tdone;
         r.state.store(2);

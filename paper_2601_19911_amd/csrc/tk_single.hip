@@ -152,7 +152,7 @@ __device__ bool exact_select(const Src& src, uint64_t n, uint64_t k_eff, Header*
     unsigned long long* gh = h->hist[pass % 3];
     for (uint32_t d = threadIdx.x; d < 256; d += NT)
       if (lh[d]) atomicAdd(&gh[d], (unsigned long long)lh[d]);
-    if (!grid_sync(&h->gs, G, &h->status, s_flag)) return false;
+    if (!grid_sync(&h->gs, G, &h->q.status, s_flag)) return false;
     if (blockIdx.x == 0) {
       unsigned long long* old = h->hist[(pass + 2) % 3];
       for (uint32_t d = threadIdx.x; d < 256; d += NT) old[d] = 0;
@@ -246,7 +246,7 @@ __device__ bool exact_select(const Src& src, uint64_t n, uint64_t k_eff, Header*
       }
     }
   }
-  return grid_sync(&h->gs, G, &h->status, s_flag);
+  return grid_sync(&h->gs, G, &h->q.status, s_flag);
 }
 
 // Sorts ck/cf[0..m) best first with all blocks and writes the outputs.
@@ -287,7 +287,7 @@ __device__ bool sort_and_write(uint64_t m, typename Key<KT>::U* ck, typename Rid
       cf[base + i] = t.f[i];
     }
   }
-  if (!grid_sync(&h->gs, G, &h->status, s_flag)) return false;
+  if (!grid_sync(&h->gs, G, &h->q.status, s_flag)) return false;
   // 2) merge runs pairwise until one run is left
   U* sk = ck;
   R* sf = cf;
@@ -321,7 +321,7 @@ __device__ bool sort_and_write(uint64_t m, typename Key<KT>::U* ck, typename Rid
         }
       }
     }
-    if (!grid_sync(&h->gs, G, &h->status, s_flag)) return false;
+    if (!grid_sync(&h->gs, G, &h->q.status, s_flag)) return false;
     U* xk = sk; sk = dk; dk = xk;
     R* xf = sf; sf = df; df = xf;
   }
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs a) {
   __shared__ int s_flag;
   Header* h = a.h;
   const U dmask = (U)a.dmask;
-  if (blockIdx.x == 0 && threadIdx.x == 0) h->path = 5u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) h->q.path = 5u;
   const InputSrc<KT, RT> src{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, dmask};
   const bool ok =
       exact_select<NT, U, R>(src, a.n, a.k_eff, h, (U*)a.ck, (R*)a.cf, lh, lh64, sh_u32, &s_flag);
@@ -537,11 +537,11 @@ extern "C" int tk_query_info(const void* workspace, tk_info* info) {
   if (!workspace || !info) return TK_EINVAL;
   Header h;
   if (hipMemcpy(&h, workspace, sizeof(Header), hipMemcpyDeviceToHost) != hipSuccess) return TK_EHIP;
-  info->path = h.path;
-  info->status = h.status;
-  info->survivors = h.surv_count;
-  info->threshold_key = h.thr_k;
-  return h.status ? TK_EDEVICE : TK_OK;
+  info->path = h.q.path;
+  info->status = h.q.status;
+  info->survivors = h.q.surv_count;
+  info->threshold_key = h.q.thr_k;
+  return h.q.status ? TK_EDEVICE : TK_OK;
 }
 
 extern "C" int tk_set_tuning(const tk_tuning* t) {
