@@ -35,9 +35,10 @@ __global__ __launch_bounds__(SAMP_NT) void k_msample(const SampArgs* __restrict_
 template <int KT, int RT>
 __global__ __launch_bounds__(FILT_NT) void k_mfilter(const FiltArgs* __restrict__ fa,
                                                      const uint2* __restrict__ map) {
+  __shared__ SurvStage<typename Key<KT>::U, typename Rid<RT>::R> st;
   const uint2 m = map[blockIdx.x];
   const FiltArgs a = fa[m.x];
-  filter_body<KT, RT, 16 / sizeof(typename Key<KT>::Raw), 4>(a, m.y);
+  filter_body<KT, RT, 16 / sizeof(typename Key<KT>::Raw), 4>(a, m.y, st);
 }
 
 template <int KT, int RT>

@@ -6,8 +6,8 @@
 //             workgroup that finishes last (an atomic ticket) selects the
 //             r1-th best of all of them: the threshold T.
 //   k_filter  the single streaming pass over the keys: composites >= T are
-//             appended to the survivor buffer (wave ballot, one atomic per
-//             wave that has survivors).
+//             staged in LDS (wave ballot + LDS atomic) and appended to the
+//             survivor buffer with one global atomic per workgroup.
 //   k_tail    one workgroup: if K <= survivors <= capacity, radix-selects the
 //             best K of the survivors, bitonic-sorts them in LDS and writes
 //             the result; otherwise (the sample misjudged) it radix-selects
@@ -30,7 +30,8 @@ __global__ __launch_bounds__(SAMP_NT) void k_sample(SampArgs a) {
 
 template <int KT, int RT, int VEC, int UNR>
 __global__ __launch_bounds__(FILT_NT) void k_filter(FiltArgs a) {
-  filter_body<KT, RT, VEC, UNR>(a, blockIdx.x);
+  __shared__ SurvStage<typename Key<KT>::U, typename Rid<RT>::R> st;
+  filter_body<KT, RT, VEC, UNR>(a, blockIdx.x, st);
 }
 
 template <int KT, int RT>

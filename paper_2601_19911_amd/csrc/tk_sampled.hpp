@@ -155,17 +155,45 @@ __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, u
 
 // ---- k_filter ----------------------------------------------------------------------------------
 
+// Survivors of one filter workgroup are staged in LDS and appended to the
+// query's survivor buffer with one global atomic at the end: a global atomic
+// per wave that meets a survivor costs far more than the pass itself once the
+// survivors number thousands.  A stage that fills up sends the rest straight
+// to the buffer (one atomic per wave).
+constexpr uint32_t FILT_STAGE = 1024;
+
 template <typename U, typename R>
-__device__ __forceinline__ void emit_survivor(bool pass, U kk, R ff, QHead* h, U* sk, R* sf,
-                                              uint64_t cap) {
+struct SurvStage {
+  U k[FILT_STAGE];
+  R f[FILT_STAGE];
+  uint32_t cnt;
+  uint32_t pad;
+  unsigned long long base;
+};
+
+template <typename U, typename R>
+__device__ __forceinline__ void stage_survivor(bool pass, U kk, R ff, SurvStage<U, R>& st, QHead* h,
+                                               U* sk, R* sf, uint64_t cap) {
   const uint64_t m = ballot(pass);
   if (m == 0) return;
   const uint32_t leader = (uint32_t)__builtin_ctzll(m);
-  uint64_t b = 0;
-  if (lane_id() == leader) b = atomicAdd(&h->surv_count, (unsigned long long)__popcll(m));
+  uint32_t b = 0;
+  if (lane_id() == leader) b = atomicAdd(&st.cnt, (uint32_t)__popcll(m));
   b = __shfl(b, (int)leader, 64);
-  if (pass) {
-    const uint64_t pos = b + lanes_below(m);
+  const uint32_t p = b + lanes_below(m);
+  const bool spill = pass && p >= FILT_STAGE;
+  if (pass && !spill) {
+    st.k[p] = kk;
+    st.f[p] = ff;
+  }
+  const uint64_t ms = ballot(spill);
+  if (ms == 0) return;
+  const uint32_t l2 = (uint32_t)__builtin_ctzll(ms);
+  uint64_t g = 0;
+  if (lane_id() == l2) g = atomicAdd(&h->surv_count, (unsigned long long)__popcll(ms));
+  g = __shfl(g, (int)l2, 64);
+  if (spill) {
+    const uint64_t pos = g + lanes_below(ms);
     if (pos < cap) {
       sk[pos] = kk;
       sf[pos] = ff;
@@ -178,11 +206,14 @@ __device__ __forceinline__ void emit_survivor(bool pass, U kk, R ff, QHead* h, U
 // the first 16-byte boundary of the key array; the keys before it and the
 // ones after the last whole tile are read one per thread.
 template <int KT, int RT, int VEC, int UNR>
-__device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk) {
+__device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
+                                            SurvStage<typename Key<KT>::U, typename Rid<RT>::R>& st) {
   using Raw = typename Key<KT>::Raw;
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
   constexpr int NT = FILT_NT;
+  if (threadIdx.x == 0) st.cnt = 0;
+  __syncthreads();
   static_assert(VEC * sizeof(Raw) == 16 || VEC == 1, "vector loads are 16 bytes");
   QHead* h = a.h;
   const U Tk = (U)h->thr_k;
@@ -232,7 +263,7 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk) {
           ff = src.flip(i);
           pass = pass || ff >= Tf;
         }
-        emit_survivor<U, R>(pass, kk, ff, h, sk, sf, a.cap);
+        stage_survivor<U, R>(pass, kk, ff, st, h, sk, sf, a.cap);
       }
   }
   // the head and the remainder (fewer than VEC + TILE keys), one per thread:
@@ -254,7 +285,19 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk) {
         pass = pass || ff >= Tf;
       }
     }
-    emit_survivor<U, R>(pass, kk, ff, h, sk, sf, a.cap);
+    stage_survivor<U, R>(pass, kk, ff, st, h, sk, sf, a.cap);
+  }
+  // append the stage to the query's survivor buffer
+  __syncthreads();
+  const uint32_t c = st.cnt < FILT_STAGE ? st.cnt : FILT_STAGE;
+  if (threadIdx.x == 0) st.base = c ? atomicAdd(&h->surv_count, (unsigned long long)c) : 0ull;
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < c; j += NT) {
+    const uint64_t pos = st.base + j;
+    if (pos < a.cap) {
+      sk[pos] = st.k[j];
+      sf[pos] = st.f[j];
+    }
   }
 }
 
