@@ -34,18 +34,39 @@ def parse(argv=None):
                     help="CPU budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the result")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args(argv)
 
 
 def traffic_from_profiles(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if any."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_traffic.txt, a line "hbm_bytes_per_launch: B"), if any."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"{kernel}_traffic.txt")
     try:
         with open(path) as f:
-            d = json.load(f)
-        return d.get(kernel)
+            for line in f:
+                if line.startswith("hbm_bytes_per_launch:"):
+                    return float(line.split(":", 1)[1])
     except (OSError, ValueError):
         return None
+    return None
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of 1 GiB, five times: the reference
+    against which the FETCH_SIZE / WRITE_SIZE counters are scaled."""
+    import torch
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": n,
+                      "bytes_written_per_copy": n, "copies": 5}), flush=True)
 
 
 def measure(args) -> dict:
@@ -203,6 +224,9 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     print(json.dumps(measure(args)), flush=True)
 
 
