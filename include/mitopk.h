@@ -69,11 +69,8 @@ size_t tk_workspace_size(uint64_t n, uint64_t k, int key_type, int rid_type);
  *   out_rowids  device array of >= min(k, n) row-ids of rid_type, or NULL
  *   out_count   host pointer, set to min(k, n) before return (may be NULL)
  *   workspace   device buffer of >= tk_workspace_size(...) bytes, 256-byte
- *               aligned, scratch until the stream passes the call.  Zero-fill
- *               it once before its first use: every query leaves it ready for
- *               the next one.  Results are exact whatever it holds; a buffer
- *               that was never zeroed only costs its first query the slower
- *               exact path
+ *               aligned, scratch until the stream passes the call.  Needs no
+ *               initialization: every query sets up the state it reads
  *   stream      hipStream_t (NULL: default stream)
  * k = 0 or n = 0 is valid and enqueues nothing.  Returns TK_OK or an error. */
 int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int key_type,
@@ -138,8 +135,8 @@ typedef struct {
 size_t tk_plan_workspace_size(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders,
                               uint32_t q, int key_type, int rid_type, const tk_plan_params* params);
 /* Creates a plan bound to `workspace` (device, 256-byte aligned, at least
- * tk_plan_workspace_size bytes, zero-filled by the caller before the first
- * launch, owned by the caller and reserved for the plan until
+ * tk_plan_workspace_size bytes, needing no initialization, owned by the
+ * caller and reserved for the plan until
  * tk_plan_destroy).  *plan receives an object owned by the library.
  * `stream` is kept for compatibility and not used. */
 int tk_plan_create(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders, uint32_t q,

@@ -125,7 +125,8 @@ def workspace_size(n: int, k: int, key_type: int, rid_type: int) -> int:
 
 
 def new_workspace(n: int, k: int, key_type: int, rid_type: int, device="cuda"):
-    """A zero-filled workspace for tk_topk (zeroed once; queries keep it ready)."""
+    """A workspace for tk_topk (zero-filled here only for reproducible contents;
+    the library needs no initialization)."""
     import torch
     return torch.zeros(workspace_size(n, k, key_type, rid_type), dtype=torch.uint8, device=device)
 

@@ -10,8 +10,8 @@
 //
 // A workgroup reads which query (and which of its workgroups) it is from a
 // block map, then runs the body the single-query kernels run.  No workgroup
-// waits for another; the hand-offs are the launch boundaries and the sample's
-// atomic ticket, as in the single query.
+// waits for another or hands it data within a kernel: the hand-offs are the
+// launch boundaries, as in the single query.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,9 +36,10 @@ template <int KT, int RT>
 __global__ __launch_bounds__(FILT_NT) void k_mfilter(const FiltArgs* __restrict__ fa,
                                                      const uint2* __restrict__ map) {
   __shared__ SurvStage<typename Key<KT>::U, typename Rid<RT>::R> st;
+  __shared__ SelScratch sc;
   const uint2 m = map[blockIdx.x];
   const FiltArgs a = fa[m.x];
-  filter_body<KT, RT, 16 / sizeof(typename Key<KT>::Raw), 4>(a, m.y, st);
+  filter_body<KT, RT, 16 / sizeof(typename Key<KT>::Raw), 4>(a, m.y, st, sc);
 }
 
 template <int KT, int RT>
@@ -159,7 +160,8 @@ void multi_records(const std::vector<MQuery>& q, const MLayout& L, int key_type,
       r.sa.push_back(SampArgs{Q.keys, Q.rids, Q.n, dmask, p.S, p.r1, h, pk, pf, p.blocks, 0});
       for (uint32_t b = 0; b < p.blocks; ++b) r.smap.push_back(uint2{si, b});
       const uint32_t fi = (uint32_t)r.fa.size();
-      r.fa.push_back(FiltArgs{Q.keys, Q.rids, Q.n, dmask, h, sk, sf, p.cap, L.fblocks[i], 0});
+      r.fa.push_back(FiltArgs{Q.keys, Q.rids, Q.n, dmask, h, sk, sf, p.cap, L.fblocks[i], p.r1, pk,
+                              pf, p.blocks * p.r1, 0});
       for (uint32_t b = 0; b < L.fblocks[i]; ++b) r.fmap.push_back(uint2{fi, b});
     }
     r.ta.push_back(TailArgs1{Q.keys, Q.rids, Q.n, dmask, h, sk, sf, sampled ? p.cap : 0, ck, cf,

@@ -14,8 +14,9 @@ namespace tk {
 inline uint32_t lds_cap_for(uint32_t cb) { return cb <= 8 ? 16384u : 8192u; }
 
 constexpr uint32_t SAMPLE_CHUNK = 16;        // contiguous keys per sample chunk
-constexpr uint32_t SAMPLE_PER_BLOCK = 1024;  // sample keys per local-select block
-constexpr uint32_t SAMPLE_FINAL_MAX = 4096;  // candidates the final select holds in registers
+constexpr uint32_t SAMPLE_PER_BLOCK = 2048;  // sample keys per local-select block
+constexpr uint32_t SAMPLE_FINAL_MAX = 2048;  // candidates of the final select (registers of a
+                                             // filter workgroup)
 
 struct SamplePlan {
   bool fast = false;     // sample -> filter -> tail; else exact radix select

@@ -1,11 +1,12 @@
 // Sampled single-query Top-K (ordering primitive, paper sec. III-A): three
-// plain kernels on the caller's stream, no workgroup ever waits for another.
+// plain kernels on the caller's stream; no workgroup waits for or hands data
+// to another within a kernel, so no device-wide fence is needed.
 //
-//   k_sample  S keys in 16-key chunks spread over the query, 1024 per
-//             workgroup; each workgroup keeps its best r1 composites.  The
-//             workgroup that finishes last (an atomic ticket) selects the
-//             r1-th best of all of them: the threshold T.
-//   k_filter  the single streaming pass over the keys: composites >= T are
+//   k_sample  S keys in 16-key chunks spread over the query, 2048 per
+//             workgroup; each workgroup keeps its best r1 composites.
+//   k_filter  every workgroup first selects the r1-th best of those
+//             candidates (the same threshold T in all of them), then streams
+//             its share of the keys: composites >= T are
 //             staged in LDS (wave ballot + LDS atomic) and appended to the
 //             survivor buffer with one global atomic per workgroup.
 //   k_tail    one workgroup: if K <= survivors <= capacity, radix-selects the
@@ -16,6 +17,9 @@
 // misjudged one falls back to the exact select, so the result never depends on
 // the sample.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
 
 #include "tk_sampled.hpp"
 
@@ -31,7 +35,8 @@ __global__ __launch_bounds__(SAMP_NT) void k_sample(SampArgs a) {
 template <int KT, int RT, int VEC, int UNR>
 __global__ __launch_bounds__(FILT_NT) void k_filter(FiltArgs a) {
   __shared__ SurvStage<typename Key<KT>::U, typename Rid<RT>::R> st;
-  filter_body<KT, RT, VEC, UNR>(a, blockIdx.x, st);
+  __shared__ SelScratch sc;
+  filter_body<KT, RT, VEC, UNR>(a, blockIdx.x, st, sc);
 }
 
 template <int KT, int RT>
@@ -42,6 +47,24 @@ __global__ __launch_bounds__(TAIL_NT) void k_tail1(TailArgs1 a) {
 }
 
 // ---- host ------------------------------------------------------------------------------------
+
+// Workgroups of the streaming pass: as many as are resident at once, so the
+// pass runs as one wave of workgroups (computed once per kernel and device).
+template <int KT, int RT, int VEC, int UNR>
+static uint32_t filter_grid(int dev) {
+  static std::mutex mu;
+  static std::vector<uint32_t> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0u);
+  if (cache[dev] == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_filter<KT, RT, VEC, UNR>,
+                                                     FILT_NT, 0) != hipSuccess || nb < 1)
+      nb = 4;
+    cache[dev] = (uint32_t)nb * (uint32_t)device_cus(dev);
+  }
+  return cache[dev];
+}
 
 template <typename T>
 static T* wsp(void* ws, size_t off) {
@@ -71,10 +94,11 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
   if (hipGetDevice(&dev) != hipSuccess) return TK_EHIP;
   const SampArgs sa{keys, rids, n, dmask, p.S, p.r1, h, samp_k, samp_f, p.blocks, 0};
   hipLaunchKernelGGL((k_sample<KT, RT>), dim3(p.blocks), dim3(SAMP_NT), 0, st, sa);
-  const uint32_t grid = tun.filter_grid ? tun.filter_grid : (uint32_t)device_cus(dev) * 8u;
-  const FiltArgs fa{keys, rids, n, dmask, h, surv_k, surv_f, p.cap, grid, 0};
-  profile_mark(st, true);
   constexpr int VEC = 16 / sizeof(Raw);
+  const uint32_t grid = tun.filter_grid ? tun.filter_grid : filter_grid<KT, RT, VEC, 4>(dev);
+  const FiltArgs fa{keys, rids, n, dmask, h, surv_k, surv_f, p.cap, grid, p.r1, samp_k, samp_f,
+                    p.blocks * p.r1, 0};
+  profile_mark(st, true);
   hipLaunchKernelGGL((k_filter<KT, RT, VEC, 4>), dim3(grid), dim3(FILT_NT), 0, st, fa);
   profile_mark(st, false);
   const TailArgs1 ta{keys, rids, n, dmask, h, surv_k, surv_f, p.cap, cand_k, cand_f,

@@ -45,7 +45,11 @@ struct FiltArgs {
   void* sk;
   void* sf;
   uint64_t cap;
-  uint32_t nblk;  // filter workgroups of this query
+  uint32_t nblk;   // filter workgroups of this query
+  uint32_t r1;     // sample rank of the threshold
+  const void* ck;  // the sample's candidates: ncand composites (key images, flipped row-ids)
+  const void* cf;
+  uint32_t ncand;
   uint32_t pad;
 };
 
@@ -77,6 +81,10 @@ constexpr uint32_t TAIL_SURVIVORS = 0, TAIL_INPUT = 1;
 // ---- k_sample ----------------------------------------------------------------------------------
 
 // blk: this workgroup's index among the query's a.nblk sample workgroups.
+// Each keeps the best r1 composites of its SAMPLE_PER_BLOCK sampled keys
+// (the union of these holds the sample's best r1); the filter workgroups
+// select the r1-th best of the union, after the launch boundary, so no
+// workgroup hands data to another inside this kernel.
 template <int KT, int RT>
 __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, uint32_t blk) {
   using U = typename Key<KT>::U;
@@ -111,46 +119,6 @@ __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, u
   R* cf = static_cast<R*>(a.cf);
   block_compact_regs<NT, U, R, E>(el, s, a.r1, ck + (uint64_t)blk * a.r1,
                                   cf + (uint64_t)blk * a.r1, sc);
-  // the last workgroup to finish turns the candidates into the threshold
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t old = atomicAdd(&h->samp_ticket, 1u);
-    sc.cnt[0] = (old == a.nblk - 1) ? 1u : 0u;
-  }
-  __syncthreads();
-  const bool last = sc.cnt[0] != 0;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // at most SAMPLE_FINAL_MAX candidates: 16 per thread, held in registers
-  constexpr int EF = SAMPLE_FINAL_MAX / NT;
-  const uint32_t m = a.nblk * a.r1;
-  U k2[EF];
-  R f2[EF];
-  int nv = 0;
-  U cmin = (U)~(U)0;
-#pragma unroll
-  for (int e = 0; e < EF; ++e) {
-    const uint32_t j = (uint32_t)e * NT + threadIdx.x;
-    if (j < m) {
-      k2[e] = ck[j];
-      f2[e] = cf[j];
-      nv = e + 1;
-      cmin = k2[e] < cmin ? k2[e] : cmin;
-    } else {
-      k2[e] = 0;
-      f2[e] = 0;
-    }
-  }
-  const U base2 = block_min<NT, U>(cmin, sc);
-  const RegElems<U, R, EF> el2{k2, f2, nv};
-  const Sel<U, R> s2 = block_radix_select<NT, U, R>(el2, a.r1, base2, sc);
-  if (threadIdx.x == 0) {
-    h->thr_k = (unsigned long long)(U)(s2.base + s2.P);
-    h->thr_f = s2.kind == SEL_KEY ? 0ull : (unsigned long long)s2.Pf;
-    h->samp_ticket = 0;  // ready for the next query on this workspace
-  }
 }
 
 // ---- k_filter ----------------------------------------------------------------------------------
@@ -205,19 +173,59 @@ __device__ __forceinline__ void stage_survivor(bool pass, U kk, R ff, SurvStage<
 // which stride over the query's tiles of NT * VEC * UNR keys.  Tiles start at
 // the first 16-byte boundary of the key array; the keys before it and the
 // ones after the last whole tile are read one per thread.
+// The threshold: the r1-th best of the sample workgroups' candidates, held in
+// registers (at most SAMPLE_FINAL_MAX).  Every filter workgroup computes the
+// same value; workgroup 0 records it for the tail.
+template <int KT, int RT>
+__device__ __forceinline__ void sample_threshold(const FiltArgs& a, uint32_t blk, SelScratch& sc,
+                                                 typename Key<KT>::U& Tk, typename Rid<RT>::R& Tf) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  constexpr int NT = FILT_NT, EF = SAMPLE_FINAL_MAX / FILT_NT;
+  const U* ck = static_cast<const U*>(a.ck);
+  const R* cf = static_cast<const R*>(a.cf);
+  U k2[EF];
+  R f2[EF];
+  int nv = 0;
+  U cmin = (U)~(U)0;
+#pragma unroll
+  for (int e = 0; e < EF; ++e) {
+    const uint32_t j = (uint32_t)e * NT + threadIdx.x;
+    if (j < a.ncand) {
+      k2[e] = ck[j];
+      f2[e] = cf[j];
+      nv = e + 1;
+      cmin = k2[e] < cmin ? k2[e] : cmin;
+    } else {
+      k2[e] = 0;
+      f2[e] = 0;
+    }
+  }
+  const U base = block_min<NT, U>(cmin, sc);
+  const RegElems<U, R, EF> el{k2, f2, nv};
+  const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.r1, base, sc);
+  Tk = (U)(s.base + s.P);
+  Tf = s.kind == SEL_KEY ? (R)0 : s.Pf;
+  if (blk == 0 && threadIdx.x == 0) {
+    a.h->thr_k = (unsigned long long)Tk;
+    a.h->thr_f = (unsigned long long)Tf;
+  }
+}
+
 template <int KT, int RT, int VEC, int UNR>
 __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
-                                            SurvStage<typename Key<KT>::U, typename Rid<RT>::R>& st) {
+                                            SurvStage<typename Key<KT>::U, typename Rid<RT>::R>& st,
+                                            SelScratch& sc) {
   using Raw = typename Key<KT>::Raw;
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
   constexpr int NT = FILT_NT;
   if (threadIdx.x == 0) st.cnt = 0;
-  __syncthreads();
+  U Tk;
+  R Tf;
+  sample_threshold<KT, RT>(a, blk, sc, Tk, Tf);
   static_assert(VEC * sizeof(Raw) == 16 || VEC == 1, "vector loads are 16 bytes");
   QHead* h = a.h;
-  const U Tk = (U)h->thr_k;
-  const R Tf = (R)h->thr_f;
   const Raw* keys = static_cast<const Raw*>(a.keys);
   const InputSrc<KT, RT> src{keys, (const R*)a.rids, (U)a.dmask};
   const U dmask = (U)a.dmask;
@@ -398,10 +406,7 @@ __device__ __forceinline__ void tail_body(const TailArgs1& a, LdsTile<KT, RT>& t
   } else {
     select_sort_write<KT, RT>(a, in, a.n, (U)0, t, sc);
   }
-  if (threadIdx.x == 0) {
-    h->path = ok ? 2u : 4u;
-    h->samp_ticket = 0;
-  }
+  if (threadIdx.x == 0) h->path = ok ? 2u : 4u;
 }
 
 }  // namespace tk
