@@ -113,10 +113,11 @@ int tk_set_tuning(const tk_tuning* t);
  * (exclusive prefix sum, see tk_plan_output_offsets).  The plan classifies
  * every query: the sampled path (sample, streaming filter, tail over the
  * survivors), or, for queries too small for a sample or whose K is a large
- * share of N, one workgroup's radix select over the query.  A launch is three
- * kernels over all queries (sample workgroups, filter workgroups, one tail
- * workgroup per query); from the second launch with the same pointers and
- * stream they are replayed from a captured hipGraph.  Results equal tk_topk on
+ * share of N, one workgroup's radix select over the query.  A launch is four
+ * kernels over all queries (sample workgroups, one threshold workgroup per
+ * sampled query, filter workgroups, one tail workgroup per query); from the
+ * second launch with the same pointers and stream they are replayed from a
+ * captured hipGraph.  Results equal tk_topk on
  * each query alone. */
 typedef struct tk_plan tk_plan;
 typedef struct {

@@ -1,7 +1,8 @@
 // Batched Top-K plans: thousands of independent queries of uneven N and K
 // over one packed key buffer, run as one multi-query launch (tk_multi.hip):
-// sample, filter and tail workgroups of every query in three kernels,
-// replayed from a hipGraph once the pointer set is known.  Host code only.
+// sample, threshold, filter and tail workgroups of every query in four
+// kernels, replayed from a hipGraph once the pointer set is known.  Host code
+// only.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -183,7 +184,8 @@ extern "C" int tk_plan_info(const tk_plan* P, uint32_t* n_sampled, uint32_t* n_e
   if (n_sampled) *n_sampled = P->L.n_sampled;
   if (n_exact) *n_exact = P->L.n_input;
   if (n_items)
-    *n_items = (uint32_t)(P->L.n_samp_blocks + P->L.n_filt_blocks + P->L.n_sampled + P->L.n_input);
+    *n_items = (uint32_t)(P->L.n_samp_blocks + P->L.n_sampled + P->L.n_filt_blocks +
+                          P->L.n_sampled + P->L.n_input);
   return TK_OK;
 }
 

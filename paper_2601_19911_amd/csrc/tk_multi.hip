@@ -1,7 +1,8 @@
-// Batched Top-K in three plain launches (ordering primitive, paper sec.
+// Batched Top-K in four plain launches (ordering primitive, paper sec.
 // III-A, applied to many queries at once):
 //
 //   k_msample  every sample workgroup of every sampled query;
+//   k_msfinal  one workgroup per sampled query: its threshold;
 //   k_mfilter  every filter workgroup of every sampled query (slices of
 //              64 Ki keys), appending survivors to the query's buffer;
 //   k_mtail    one workgroup per non-empty query: the exact select and sort
@@ -33,13 +34,19 @@ __global__ __launch_bounds__(SAMP_NT) void k_msample(const SampArgs* __restrict_
 }
 
 template <int KT, int RT>
+__global__ __launch_bounds__(FILT_NT) void k_msfinal(const FiltArgs* __restrict__ fa) {
+  __shared__ SelScratch sc;
+  const FiltArgs a = fa[blockIdx.x];
+  sample_final_body<KT, RT>(a, sc);
+}
+
+template <int KT, int RT>
 __global__ __launch_bounds__(FILT_NT) void k_mfilter(const FiltArgs* __restrict__ fa,
                                                      const uint2* __restrict__ map) {
   __shared__ SurvStage<typename Key<KT>::U, typename Rid<RT>::R> st;
-  __shared__ SelScratch sc;
   const uint2 m = map[blockIdx.x];
   const FiltArgs a = fa[m.x];
-  filter_body<KT, RT, 16 / sizeof(typename Key<KT>::Raw), 4>(a, m.y, st, sc);
+  filter_body<KT, RT, 16 / sizeof(typename Key<KT>::Raw), 4>(a, m.y, st);
 }
 
 template <int KT, int RT>
@@ -191,6 +198,7 @@ MLaunch multi_pack(const MRecords& r, char* dst, char* dev) {
   m.fmap = reinterpret_cast<const uint2*>(put(r.fmap.data(), r.fmap.size() * sizeof(uint2)));
   m.ta = reinterpret_cast<const TailArgs1*>(put(r.ta.data(), r.ta.size() * sizeof(TailArgs1)));
   m.n_samp = (uint32_t)r.smap.size();
+  m.n_fa = (uint32_t)r.fa.size();
   m.n_filt = (uint32_t)r.fmap.size();
   m.n_tail = (uint32_t)r.ta.size();
   return m;
@@ -202,6 +210,7 @@ namespace {
 template <int KT, int RT>
 void enqueue_typed(const MLaunch& m, hipStream_t st) {
   if (m.n_samp) hipLaunchKernelGGL((k_msample<KT, RT>), dim3(m.n_samp), dim3(SAMP_NT), 0, st, m.sa, m.smap);
+  if (m.n_fa) hipLaunchKernelGGL((k_msfinal<KT, RT>), dim3(m.n_fa), dim3(FILT_NT), 0, st, m.fa);
   profile_mark(st, true);
   if (m.n_filt) hipLaunchKernelGGL((k_mfilter<KT, RT>), dim3(m.n_filt), dim3(FILT_NT), 0, st, m.fa, m.fmap);
   profile_mark(st, false);

@@ -1,6 +1,7 @@
-// Batched Top-K: many queries of uneven N and K in three launches (sample,
-// filter, tail), each workgroup running the same body as in the single-query
-// kernels for the query and slice its block map names.  Shared by the plan
+// Batched Top-K: many queries of uneven N and K in four launches (sample,
+// threshold, filter, tail), each workgroup running the same body as in the
+// single-query kernels for the query and slice its block map names.  Shared
+// by the plan
 // API (tk_batched.hip) and the served form (tk_serve.hip).  Host code.
 #pragma once
 
@@ -64,6 +65,7 @@ struct MLaunch {
   const uint2* smap = nullptr;
   uint32_t n_samp = 0;
   const FiltArgs* fa = nullptr;
+  uint32_t n_fa = 0;  // sampled queries (one threshold workgroup each)
   const uint2* fmap = nullptr;
   uint32_t n_filt = 0;
   const TailArgs1* ta = nullptr;
@@ -76,7 +78,7 @@ uint64_t multi_pack_bytes(const MRecords& r);
 // returns the launch description for the same layout at device address dev.
 MLaunch multi_pack(const MRecords& r, char* dst, char* dev);
 
-// Enqueues the three launches on st.  Makes no runtime query, so it may run
+// Enqueues the four launches on st.  Makes no runtime query, so it may run
 // inside a stream capture; launch errors surface through hipGetLastError.
 void multi_enqueue(const MLaunch& m, int key_type, int rid_type, hipStream_t st);
 

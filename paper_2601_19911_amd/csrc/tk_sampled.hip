@@ -1,12 +1,12 @@
-// Sampled single-query Top-K (ordering primitive, paper sec. III-A): three
+// Sampled single-query Top-K (ordering primitive, paper sec. III-A): four
 // plain kernels on the caller's stream; no workgroup waits for or hands data
 // to another within a kernel, so no device-wide fence is needed.
 //
 //   k_sample  S keys in 16-key chunks spread over the query, 2048 per
 //             workgroup; each workgroup keeps its best r1 composites.
-//   k_filter  every workgroup first selects the r1-th best of those
-//             candidates (the same threshold T in all of them), then streams
-//             its share of the keys: composites >= T are
+//   k_sfinal  one workgroup selects the r1-th best of those candidates: the
+//             threshold T.
+//   k_filter  the single streaming pass over the keys: composites >= T are
 //             staged in LDS (wave ballot + LDS atomic) and appended to the
 //             survivor buffer with one global atomic per workgroup.
 //   k_tail    one workgroup: if K <= survivors <= capacity, radix-selects the
@@ -32,11 +32,16 @@ __global__ __launch_bounds__(SAMP_NT) void k_sample(SampArgs a) {
   sample_body<KT, RT>(a, sc, blockIdx.x);
 }
 
+template <int KT, int RT>
+__global__ __launch_bounds__(FILT_NT) void k_sfinal(FiltArgs a) {
+  __shared__ SelScratch sc;
+  sample_final_body<KT, RT>(a, sc);
+}
+
 template <int KT, int RT, int VEC, int UNR>
 __global__ __launch_bounds__(FILT_NT) void k_filter(FiltArgs a) {
   __shared__ SurvStage<typename Key<KT>::U, typename Rid<RT>::R> st;
-  __shared__ SelScratch sc;
-  filter_body<KT, RT, VEC, UNR>(a, blockIdx.x, st, sc);
+  filter_body<KT, RT, VEC, UNR>(a, blockIdx.x, st);
 }
 
 template <int KT, int RT>
@@ -98,6 +103,7 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
   const uint32_t grid = tun.filter_grid ? tun.filter_grid : filter_grid<KT, RT, VEC, 4>(dev);
   const FiltArgs fa{keys, rids, n, dmask, h, surv_k, surv_f, p.cap, grid, p.r1, samp_k, samp_f,
                     p.blocks * p.r1, 0};
+  hipLaunchKernelGGL((k_sfinal<KT, RT>), dim3(1), dim3(FILT_NT), 0, st, fa);
   profile_mark(st, true);
   hipLaunchKernelGGL((k_filter<KT, RT, VEC, 4>), dim3(grid), dim3(FILT_NT), 0, st, fa);
   profile_mark(st, false);

@@ -82,9 +82,9 @@ constexpr uint32_t TAIL_SURVIVORS = 0, TAIL_INPUT = 1;
 
 // blk: this workgroup's index among the query's a.nblk sample workgroups.
 // Each keeps the best r1 composites of its SAMPLE_PER_BLOCK sampled keys
-// (the union of these holds the sample's best r1); the filter workgroups
-// select the r1-th best of the union, after the launch boundary, so no
-// workgroup hands data to another inside this kernel.
+// (the union of these holds the sample's best r1); the next launch selects
+// the r1-th best of the union, so no workgroup hands data to another inside
+// a kernel.
 template <int KT, int RT>
 __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, uint32_t blk) {
   using U = typename Key<KT>::U;
@@ -173,12 +173,11 @@ __device__ __forceinline__ void stage_survivor(bool pass, U kk, R ff, SurvStage<
 // which stride over the query's tiles of NT * VEC * UNR keys.  Tiles start at
 // the first 16-byte boundary of the key array; the keys before it and the
 // ones after the last whole tile are read one per thread.
-// The threshold: the r1-th best of the sample workgroups' candidates, held in
-// registers (at most SAMPLE_FINAL_MAX).  Every filter workgroup computes the
-// same value; workgroup 0 records it for the tail.
+// The threshold: the r1-th best of the sample workgroups' candidates (at most
+// SAMPLE_FINAL_MAX, held in registers), selected by one workgroup of FILT_NT
+// threads in a launch of its own and recorded in the query state.
 template <int KT, int RT>
-__device__ __forceinline__ void sample_threshold(const FiltArgs& a, uint32_t blk, SelScratch& sc,
-                                                 typename Key<KT>::U& Tk, typename Rid<RT>::R& Tf) {
+__device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch& sc) {
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
   constexpr int NT = FILT_NT, EF = SAMPLE_FINAL_MAX / FILT_NT;
@@ -204,28 +203,25 @@ __device__ __forceinline__ void sample_threshold(const FiltArgs& a, uint32_t blk
   const U base = block_min<NT, U>(cmin, sc);
   const RegElems<U, R, EF> el{k2, f2, nv};
   const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.r1, base, sc);
-  Tk = (U)(s.base + s.P);
-  Tf = s.kind == SEL_KEY ? (R)0 : s.Pf;
-  if (blk == 0 && threadIdx.x == 0) {
-    a.h->thr_k = (unsigned long long)Tk;
-    a.h->thr_f = (unsigned long long)Tf;
+  if (threadIdx.x == 0) {
+    a.h->thr_k = (unsigned long long)(U)(s.base + s.P);
+    a.h->thr_f = s.kind == SEL_KEY ? 0ull : (unsigned long long)s.Pf;
   }
 }
 
 template <int KT, int RT, int VEC, int UNR>
 __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
-                                            SurvStage<typename Key<KT>::U, typename Rid<RT>::R>& st,
-                                            SelScratch& sc) {
+                                            SurvStage<typename Key<KT>::U, typename Rid<RT>::R>& st) {
   using Raw = typename Key<KT>::Raw;
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
   constexpr int NT = FILT_NT;
-  if (threadIdx.x == 0) st.cnt = 0;
-  U Tk;
-  R Tf;
-  sample_threshold<KT, RT>(a, blk, sc, Tk, Tf);
   static_assert(VEC * sizeof(Raw) == 16 || VEC == 1, "vector loads are 16 bytes");
+  if (threadIdx.x == 0) st.cnt = 0;
+  __syncthreads();
   QHead* h = a.h;
+  const U Tk = (U)h->thr_k;
+  const R Tf = (R)h->thr_f;
   const Raw* keys = static_cast<const Raw*>(a.keys);
   const InputSrc<KT, RT> src{keys, (const R*)a.rids, (U)a.dmask};
   const U dmask = (U)a.dmask;

@@ -473,6 +473,44 @@ __device__ __forceinline__ void bitonic_regs_desc_e(U (&k)[E], R (&f)[E], uint32
   }
 }
 
+// Bitonic sort, best first, of m <= NT composites of 4-byte key image and
+// 4-byte flipped row-id, packed as (key << 32 | flipped row-id) so that one
+// 64-bit compare orders them and each stage is a compare and two selects:
+// strides below the wave width exchange through lane shuffles, wider ones
+// through LDS (two halves of 8 P bytes each, one barrier per stage).  Thread t
+// emits the composite of rank t.
+template <int NT, typename U, typename R, typename Emit>
+__device__ __forceinline__ void sort_emit_packed(uint32_t m, U* lk, R* lf, Emit&& emit) {
+  static_assert(sizeof(U) == 4 && sizeof(R) == 4, "packed sort: 4-byte key image and row-id");
+  const uint32_t t = threadIdx.x;
+  uint32_t P = 1;
+  while (P < m) P <<= 1;
+  uint64_t v = t < m ? ((uint64_t)lk[t] << 32) | (uint64_t)lf[t] : 0ull;
+  __syncthreads();  // the tile is reused as the exchange buffer
+  uint64_t* xb = reinterpret_cast<uint64_t*>(lk);
+  uint32_t buf = 0;
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      uint64_t o;
+      if (stride >= 64) {
+        uint64_t* x = xb + buf * P;
+        if (t < P) x[t] = v;
+        __syncthreads();
+        o = t < P ? x[t ^ stride] : v;
+        buf ^= 1u;
+      } else {
+        o = __shfl_xor(v, (int)stride, 64);
+      }
+      const bool keep_max = ((t & stride) == 0) == ((t & size) == 0);
+      const uint64_t hi = o > v ? o : v;
+      const uint64_t lo = o > v ? v : o;
+      v = keep_max ? hi : lo;
+    }
+  }
+  if (t < m) emit((uint64_t)t, (U)(v >> 32), (R)(uint32_t)v);
+  __syncthreads();
+}
+
 // Sorts m <= NT * E composites sitting at the start of the LDS tile (lk, lf)
 // (2P <= CAP) in registers and emits them.
 template <int NT, int E, typename U, typename R, typename Emit>
@@ -502,6 +540,13 @@ __device__ __forceinline__ void block_sort_emit(uint64_t m, bool in_lds, U* lk, 
     // registers: up to 4 (or 16) composites per thread, exchange buffer 2P <= CAP
     uint32_t P = 1;
     while (P < m) P <<= 1;
+    if constexpr (sizeof(U) == 4 && sizeof(R) == 4) {
+      // exchange buffer: 2P 8-byte words in the tile's 8 CAP bytes
+      if (m <= NT && 2 * P <= CAP) {
+        sort_emit_packed<NT, U, R>((uint32_t)m, lk, lf, emit);
+        return;
+      }
+    }
     if (m <= NT && 2 * P <= CAP) {
       sort_emit_regs<NT, 1, U, R>((uint32_t)m, lk, lf, emit);
       return;

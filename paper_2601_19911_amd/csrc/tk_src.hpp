@@ -26,7 +26,7 @@ struct BufSrc {
 };
 
 template <int KT, int RT>
-struct LdsTile {
+struct alignas(16) LdsTile {
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
   static constexpr uint32_t CAP = (sizeof(U) + sizeof(R)) <= 8 ? 16384u : 8192u;
