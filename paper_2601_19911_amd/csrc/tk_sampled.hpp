@@ -307,27 +307,41 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
 
 // ---- k_tail ------------------------------------------------------------------------------------
 
+// Where a tail writes its results (scalars, so the kernel arguments stay in
+// registers on the fast path).
+struct TailOut {
+  uint64_t k_eff, dmask;
+  void *out_keys, *out_rids, *ck, *cf, *tk, *tf;
+};
+
+// Select + sort over an array in global memory (survivors beyond the register
+// capacity, or the whole input when the sample misjudged): out of line, so
+// its registers do not weigh on the register-resident fast path.
 template <int KT, int RT, typename Src>
-__device__ void select_sort_write(const TailArgs1& a, const Src& src, uint64_t n,
-                                  typename Key<KT>::U base, LdsTile<KT, RT>& t, SelScratch& sc) {
+__device__ __noinline__ void select_sort_write(const Src src, uint64_t n, typename Key<KT>::U base,
+                                               const TailOut o, LdsTile<KT, RT>& t, SelScratch& sc) {
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
   constexpr int NT = TAIL_NT;
   constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
-  const U dmask = (U)a.dmask;
-  auto emit = [&](uint64_t j, U u, R f) { write_out<KT, RT>(j, u, f, dmask, a.out_keys, a.out_rids); };
+  const U dmask = (U)o.dmask;
+  auto emit = [&](uint64_t j, U u, R f) { write_out<KT, RT>(j, u, f, dmask, o.out_keys, o.out_rids); };
   const GlobElems<NT, Src> el{src, n};
-  const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.k_eff, base, sc);
-  if (a.k_eff <= CAP) {
-    block_compact_glob<NT, U, R>(src, n, s, a.k_eff, t.k, t.f, sc);
-    block_sort_emit<NT, U, R>(a.k_eff, true, t.k, t.f, CAP, nullptr, nullptr, nullptr, nullptr, emit);
+  const Sel<U, R> s = block_radix_select<NT, U, R>(el, o.k_eff, base, sc);
+  if (o.k_eff <= CAP) {
+    block_compact_glob<NT, U, R>(src, n, s, o.k_eff, t.k, t.f, sc);
+    block_sort_emit<NT, U, R>(o.k_eff, true, t.k, t.f, CAP, nullptr, nullptr, nullptr, nullptr, emit);
   } else {
-    U* ck = static_cast<U*>(a.ck);
-    R* cf = static_cast<R*>(a.cf);
-    block_compact_glob<NT, U, R>(src, n, s, a.k_eff, ck, cf, sc);
-    block_sort_emit<NT, U, R>(a.k_eff, false, t.k, t.f, CAP, ck, cf, static_cast<U*>(a.tk),
-                              static_cast<R*>(a.tf), emit);
+    U* ck = static_cast<U*>(o.ck);
+    R* cf = static_cast<R*>(o.cf);
+    block_compact_glob<NT, U, R>(src, n, s, o.k_eff, ck, cf, sc);
+    block_sort_emit<NT, U, R>(o.k_eff, false, t.k, t.f, CAP, ck, cf, static_cast<U*>(o.tk),
+                              static_cast<R*>(o.tf), emit);
   }
+}
+
+__device__ __forceinline__ TailOut tail_out(const TailArgs1& a) {
+  return TailOut{a.k_eff, a.dmask, a.out_keys, a.out_rids, a.ck, a.cf, a.tk, a.tf};
 }
 
 // Survivors that fit the registers of the workgroup (16 per thread) are
@@ -387,7 +401,7 @@ __device__ __forceinline__ void tail_body(const TailArgs1& a, LdsTile<KT, RT>& t
   const InputSrc<KT, RT> in{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, (U)a.dmask};
   if (a.mode == TAIL_INPUT) {
     if (a.n <= (uint64_t)TAIL_NT * TAIL_E) select_sort_write_regs<KT, RT>(a, in, (uint32_t)a.n, (U)~(U)0, t, sc);
-    else select_sort_write<KT, RT>(a, in, a.n, (U)0, t, sc);
+    else select_sort_write<KT, RT>(in, a.n, (U)0, tail_out(a), t, sc);
     return;
   }
   QHead* h = a.h;
@@ -398,9 +412,9 @@ __device__ __forceinline__ void tail_body(const TailArgs1& a, LdsTile<KT, RT>& t
     select_sort_write_regs<KT, RT>(a, src, (uint32_t)C, (U)h->thr_k, t, sc);
   } else if (ok) {
     const BufSrc<U, R> src{static_cast<const U*>(a.sk), static_cast<const R*>(a.sf)};
-    select_sort_write<KT, RT>(a, src, C, (U)h->thr_k, t, sc);
+    select_sort_write<KT, RT>(src, C, (U)h->thr_k, tail_out(a), t, sc);
   } else {
-    select_sort_write<KT, RT>(a, in, a.n, (U)0, t, sc);
+    select_sort_write<KT, RT>(in, a.n, (U)0, tail_out(a), t, sc);
   }
   if (threadIdx.x == 0) h->path = ok ? 2u : 4u;
 }

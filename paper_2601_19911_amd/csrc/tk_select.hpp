@@ -358,11 +358,6 @@ __device__ __forceinline__ uint64_t merge_split(const U* ak, const R* af, uint64
   return lo;
 }
 
-// One workgroup sorts m selected composites best first and hands each to
-// emit(j, u, f).  in_lds: the composites sit at the start of the LDS tile
-// (lk, lf) of CAP elements and m <= CAP.  Otherwise they are in (ck, cf) in
-// global memory: tiles of CAP are bitonic-sorted in LDS, then merged pairwise
-// through (tk, tf) with merge-path splits.
 // Bitonic sort, best first, of P <= NT composites held one per thread
 // (thread t holds element t; P a power of two).  Strides below the wave
 // width exchange through lane shuffles; wider strides through LDS, ping-
@@ -488,8 +483,10 @@ __device__ __forceinline__ void sort_emit_packed(uint32_t m, U* lk, R* lf, Emit&
   uint64_t v = t < m ? ((uint64_t)lk[t] << 32) | (uint64_t)lf[t] : 0ull;
   __syncthreads();  // the tile is reused as the exchange buffer
   uint64_t* xb = reinterpret_cast<uint64_t*>(lk);
+  const int lane4 = (int)(lane_id() << 2);
   uint32_t buf = 0;
   for (uint32_t size = 2; size <= P; size <<= 1) {
+    const bool up = (t & size) == 0;  // this run ends up descending
     for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
       uint64_t o;
       if (stride >= 64) {
@@ -499,12 +496,15 @@ __device__ __forceinline__ void sort_emit_packed(uint32_t m, U* lk, R* lf, Emit&
         o = t < P ? x[t ^ stride] : v;
         buf ^= 1u;
       } else {
-        o = __shfl_xor(v, (int)stride, 64);
+        const int addr = lane4 ^ (int)(stride << 2);
+        const uint32_t olo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)v);
+        const uint32_t ohi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(v >> 32));
+        o = ((uint64_t)ohi << 32) | olo;
       }
-      const bool keep_max = ((t & stride) == 0) == ((t & size) == 0);
-      const uint64_t hi = o > v ? o : v;
-      const uint64_t lo = o > v ? v : o;
-      v = keep_max ? hi : lo;
+      // the lower position of a descending pair (or the upper of an
+      // ascending one) keeps the larger composite
+      const bool keep_max = ((t & stride) == 0) == up;
+      v = ((o > v) == keep_max) ? o : v;
     }
   }
   if (t < m) emit((uint64_t)t, (U)(v >> 32), (R)(uint32_t)v);
@@ -533,20 +533,17 @@ __device__ __forceinline__ void sort_emit_regs(uint32_t m, U* lk, R* lf, Emit&& 
   __syncthreads();
 }
 
+// The general sort of block_sort_emit: composites in LDS are sorted in
+// registers (up to 16 per thread) or by an LDS bitonic network; composites in
+// global memory (ck, cf) are bitonic-sorted in LDS tiles of CAP, then merged
+// pairwise through (tk, tf) with merge-path splits.
 template <int NT, typename U, typename R, typename Emit>
-__device__ __forceinline__ void block_sort_emit(uint64_t m, bool in_lds, U* lk, R* lf, uint32_t CAP, U* ck, R* cf,
-                                U* tk, R* tf, Emit&& emit) {
+__device__ __noinline__ void block_sort_emit_general(uint64_t m, bool in_lds, U* lk, R* lf, uint32_t CAP, U* ck, R* cf,
+                                U* tk, R* tf, Emit emit) {
   if (in_lds) {
     // registers: up to 4 (or 16) composites per thread, exchange buffer 2P <= CAP
     uint32_t P = 1;
     while (P < m) P <<= 1;
-    if constexpr (sizeof(U) == 4 && sizeof(R) == 4) {
-      // exchange buffer: 2P 8-byte words in the tile's 8 CAP bytes
-      if (m <= NT && 2 * P <= CAP) {
-        sort_emit_packed<NT, U, R>((uint32_t)m, lk, lf, emit);
-        return;
-      }
-    }
     if (m <= NT && 2 * P <= CAP) {
       sort_emit_regs<NT, 1, U, R>((uint32_t)m, lk, lf, emit);
       return;
@@ -623,6 +620,23 @@ __device__ __forceinline__ void block_sort_emit(uint64_t m, bool in_lds, U* lk, 
   }
   for (uint64_t j = threadIdx.x; j < m; j += NT) emit(j, sk[j], sf[j]);
   __syncthreads();
+}
+
+
+// One workgroup sorts m selected composites best first and hands each to
+// emit(j, u, f).  in_lds: the composites sit at the start of the LDS tile
+// (lk, lf) of CAP elements and m <= CAP.  The common case (m <= NT composites
+// of 8 bytes) is sorted inline; the others go to block_sort_emit_general.
+template <int NT, typename U, typename R, typename Emit>
+__device__ __forceinline__ void block_sort_emit(uint64_t m, bool in_lds, U* lk, R* lf, uint32_t CAP,
+                                                U* ck, R* cf, U* tk, R* tf, Emit&& emit) {
+  if constexpr (sizeof(U) == 4 && sizeof(R) == 4) {
+    if (in_lds && m <= NT && 2 * (uint64_t)NT <= CAP) {  // exchange buffer: 2P words in 8 CAP bytes
+      sort_emit_packed<NT, U, R>((uint32_t)m, lk, lf, emit);
+      return;
+    }
+  }
+  block_sort_emit_general<NT, U, R>(m, in_lds, lk, lf, CAP, ck, cf, tk, tf, emit);
 }
 
 }  // namespace tk
