@@ -511,6 +511,91 @@ __device__ __forceinline__ void sort_emit_packed(uint32_t m, U* lk, R* lf, Emit&
   __syncthreads();
 }
 
+// The packed bitonic sort with 4 composites per thread on the first 256
+// threads (m <= 1024): composite i sits in thread i / 4, slot i % 4, so the
+// strides 1 and 2 are compare-exchanges in registers, strides 4 to 128 are
+// lane permutes of 4 values, and only strides 256 and 512 go through LDS.
+// Fewer dependent exchange steps than one composite per thread.
+template <int NT, typename U, typename R, typename Emit>
+__device__ __forceinline__ void sort_emit_packed4(uint32_t m, U* lk, R* lf, Emit&& emit) {
+  static_assert(sizeof(U) == 4 && sizeof(R) == 4, "packed sort: 4-byte key image and row-id");
+  static_assert(NT >= 256 && NT % 64 == 0, "at least 256 threads");
+  constexpr uint32_t W = 256;
+  const uint32_t t = threadIdx.x;
+  const bool act = t < W;  // whole waves
+  const uint32_t i0 = 4 * t;
+  uint32_t P = 4;
+  while (P < m) P <<= 1;
+  uint64_t v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    v[e] = (act && i0 + e < m) ? ((uint64_t)lk[i0 + e] << 32) | (uint64_t)lf[i0 + e] : 0ull;
+  __syncthreads();  // the tile is reused as the exchange buffer
+  uint64_t* xb = reinterpret_cast<uint64_t*>(lk);
+  const int lane4 = (int)(lane_id() << 2);
+  uint32_t buf = 0;
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride >= 4; stride >>= 1) {
+      const uint32_t ts = stride >> 2;
+      uint64_t o[4];
+      if (ts >= 64) {
+        uint64_t* x = xb + buf * P;
+        if (act && i0 < P) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[i0 + e] = v[e];
+        }
+        __syncthreads();
+        if (act && i0 < P) {
+          const uint32_t j0 = 4 * (t ^ ts);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) o[e] = x[j0 + e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) o[e] = v[e];
+        }
+        buf ^= 1u;
+      } else if (act) {
+        const int addr = lane4 ^ (int)(ts << 2);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t olo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)v[e]);
+          const uint32_t ohi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(v[e] >> 32));
+          o[e] = ((uint64_t)ohi << 32) | olo;
+        }
+      }
+      if (act) {
+        // same direction for the 4 slots: i0 is a multiple of 4 and stride >= 4
+        const bool keep_max = ((i0 & stride) == 0) == ((i0 & size) == 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = ((o[e] > v[e]) == keep_max) ? o[e] : v[e];
+      }
+    }
+    if (act) {
+      const bool desc = (i0 & size) == 0;  // size >= 4 here shares i0's bit; size 2 uses slot bit
+#pragma unroll
+      for (int s2 = 2; s2 >= 1; s2 >>= 1) {
+        if ((uint32_t)s2 >= size) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (e & s2) continue;
+          const int e2 = e | s2;
+          const bool d = size >= 4 ? desc : (((i0 + e) & size) == 0);
+          const bool sw = d ? (v[e2] > v[e]) : (v[e] > v[e2]);
+          const uint64_t a = v[e], b = v[e2];
+          v[e] = sw ? b : a;
+          v[e2] = sw ? a : b;
+        }
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (i0 + e < m) emit((uint64_t)(i0 + e), (U)(v[e] >> 32), (R)(uint32_t)v[e]);
+  }
+  __syncthreads();
+}
+
 // Sorts m <= NT * E composites sitting at the start of the LDS tile (lk, lf)
 // (2P <= CAP) in registers and emits them.
 template <int NT, int E, typename U, typename R, typename Emit>
@@ -631,7 +716,14 @@ template <int NT, typename U, typename R, typename Emit>
 __device__ __forceinline__ void block_sort_emit(uint64_t m, bool in_lds, U* lk, R* lf, uint32_t CAP,
                                                 U* ck, R* cf, U* tk, R* tf, Emit&& emit) {
   if constexpr (sizeof(U) == 4 && sizeof(R) == 4) {
-    if (in_lds && m <= NT && 2 * (uint64_t)NT <= CAP) {  // exchange buffer: 2P words in 8 CAP bytes
+    // exchange buffer: 2P 8-byte words in the tile's 8 CAP bytes
+    if constexpr (NT >= 256) {
+      if (in_lds && m <= 1024 && 2048 <= CAP) {
+        sort_emit_packed4<NT, U, R>((uint32_t)m, lk, lf, emit);
+        return;
+      }
+    }
+    if (in_lds && m <= NT && 2 * (uint64_t)NT <= CAP) {
       sort_emit_packed<NT, U, R>((uint32_t)m, lk, lf, emit);
       return;
     }
