@@ -81,8 +81,10 @@ int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int ke
  * few words from the device synchronously; call after the stream has passed
  * the query. */
 typedef struct {
-  uint32_t path;        /* 2 sampled: streaming filter, then select + sort of the
-                           survivors; 4 sampled, but the sample misjudged: exact select
+  uint32_t path;        /* 2 sampled: streaming filter, then one workgroup's select +
+                           sort of the survivors; 3 sampled: streaming filter, then the
+                           survivors ranked across workgroups; 4 sampled, but the
+                           sample misjudged: exact select
                            over the input; 5 exact radix select over the input
                            (K a large share of N); 0 after a one-workgroup query */
   uint32_t status;      /* 0, or device failure bits (1: a grid barrier timed out,
@@ -98,9 +100,14 @@ typedef struct {
   double sample_sigma;       /* margin of the sampled threshold (std devs), default 3 */
   double cap_sigma;          /* survivor capacity margin (std devs), default 6 */
   int32_t max_sample_log2;   /* largest sample, default 20 */
-  int32_t filter_grid;       /* workgroups of the streaming pass, default 8 per CU */
+  int32_t filter_grid;       /* workgroups of the streaming pass (< 0: back to the default,
+                                3 per CU) */
   int64_t force_cap;         /* > 0: fixed survivor capacity (forces the fallback) */
   int32_t force_exact;       /* 1: always the exact radix select, 2: back to default */
+  int32_t tail_mode;         /* 1: the survivors are ranked across workgroups when they fit
+                                (default), 2: one workgroup selects and sorts them */
+  int32_t filter_unroll;     /* 16-byte loads in flight per thread in the streaming pass:
+                                4 or 8 (others leave it unchanged) */
 } tk_tuning;
 int tk_set_tuning(const tk_tuning* t);
 

@@ -1,0 +1,284 @@
+// Tail of the sampled single query over many workgroups: the exact best K
+// of the filter's survivors, written in order, without a sort.
+//
+// Every survivor is at or above the sampled threshold T.  Each workgroup
+//   1. loads all C survivors into registers and builds an LDS histogram of
+//      a logarithmic bucket of their distance D = c - T (c the composite,
+//      key image above flipped row-id, read as one wide integer): 64 exact
+//      buckets for D < 64, then 32 per octave.  The bucket is monotone in the
+//      composite, so everything better than an element lies in its bucket or
+//      above;
+//   2. finds the boundary bucket b*, the one holding rank K counted from the
+//      top, and collects the hot set H (bucket >= b*, |H| >= K) in LDS;
+//   3. counts, for each hot survivor it owns (survivor index mod the grid),
+//      the members of H better than it: that count is the survivor's rank,
+//      and ranks below K are its output position.  Identical composites
+//      (possible only with repeated row-ids) are ordered by survivor index.
+// All workgroups build the same H, so the ranks agree and each output slot is
+// written exactly once.  The histogram keeps H near K + C/64 for spread-out
+// keys; ties on the key are split by the row-id bits of D.  A query outside
+// this path's limits (survivors beyond the register capacity, or a hot set
+// beyond the LDS capacity) is finished by workgroup 0 with the one-workgroup
+// select + sort.
+#pragma once
+
+#include "tk_sampled.hpp"
+
+namespace tk {
+
+constexpr int RANK_NT = 1024;
+constexpr uint32_t RANK_E = 16;                    // survivors per thread
+constexpr uint32_t RANK_CMAX = RANK_NT * RANK_E;  // survivors one workgroup holds
+constexpr uint32_t RANK_HMAX = 4096;               // hot set capacity
+constexpr uint32_t RANK_GMIN = 16, RANK_GMAX = 64;
+constexpr uint32_t RANK_MMAX = (RANK_CMAX + RANK_GMIN - 1) / RANK_GMIN;  // owned per workgroup
+
+// The composite (u, f) as one unsigned integer of sizeof(U) + sizeof(R) bytes.
+template <typename U, typename R>
+struct Wide {
+  using T = __uint128_t;
+  static constexpr int W = 8 * (int)(sizeof(U) + sizeof(R));
+};
+template <>
+struct Wide<uint32_t, uint32_t> {
+  using T = uint64_t;
+  static constexpr int W = 64;
+};
+
+template <typename U, typename R>
+__device__ __forceinline__ typename Wide<U, R>::T wide(U u, R f) {
+  using T = typename Wide<U, R>::T;
+  return ((T)u << (8 * sizeof(R))) | (T)f;
+}
+
+__device__ __forceinline__ int wbitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
+__device__ __forceinline__ int wbitlen(__uint128_t x) {
+  const uint64_t hi = (uint64_t)(x >> 64);
+  return hi ? 64 + wbitlen(hi) : wbitlen((uint64_t)x);
+}
+
+// Logarithmic bucket: D itself below 64, then 32 buckets per octave (the five
+// bits under the leading one).  Non-decreasing in D; W-bit D gives
+// 32 W - 128 buckets.
+template <typename T>
+__device__ __forceinline__ uint32_t log_bucket(T d) {
+  const int L = wbitlen(d);
+  if (L <= 6) return (uint32_t)d;
+  return 64u + (uint32_t)(L - 7) * 32u + ((uint32_t)(d >> (L - 6)) & 31u);
+}
+
+template <int KT, int RT>
+struct RankLds {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  static constexpr uint32_t NB = 32u * Wide<U, R>::W - 128u;
+  uint32_t hist[NB];
+  U hu[RANK_HMAX];
+  R hf[RANK_HMAX];
+  uint32_t hi[RANK_HMAX];      // survivor index
+  uint32_t mine[RANK_MMAX];    // hot-set slots this workgroup ranks
+  uint32_t gt[RANK_MMAX];      // members of H better than it
+  uint32_t eq[RANK_MMAX];      // members of H equal to it (itself included)
+  uint32_t wsum[RANK_NT / 64];
+  uint32_t bstar, hcount;
+};
+
+// Bytes of LDS for the tail kernel: the rank state, or the one-workgroup
+// select + sort state (tile, then scratch at a 16-byte boundary).
+template <int KT, int RT>
+constexpr size_t rank_smem_bytes() {
+  const size_t tile = (sizeof(LdsTile<KT, RT>) + 15) / 16 * 16 + sizeof(SelScratch);
+  return sizeof(RankLds<KT, RT>) > tile ? sizeof(RankLds<KT, RT>) : tile;
+}
+
+template <int KT, int RT>
+__device__ __noinline__ void rank_tail_fallback(const TailArgs1 a, unsigned char* smem) {
+  LdsTile<KT, RT>& t = *reinterpret_cast<LdsTile<KT, RT>*>(smem);
+  SelScratch& sc =
+      *reinterpret_cast<SelScratch*>(smem + (sizeof(LdsTile<KT, RT>) + 15) / 16 * 16);
+  tail_body<KT, RT>(a, t, sc);
+}
+
+// The tail over gridDim.x workgroups of RANK_NT threads (RANK_GMIN <=
+// gridDim.x <= RANK_GMAX), in TAIL_SURVIVORS mode.
+template <int KT, int RT>
+__device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char* smem) {
+  using U = typename Key<KT>::U;
+  using R = typename Rid<RT>::R;
+  using T = typename Wide<U, R>::T;
+  using Lds = RankLds<KT, RT>;
+  constexpr int NT = RANK_NT, E = (int)RANK_E;
+  constexpr uint32_t NB = Lds::NB, BPT = (NB + NT - 1) / NT;
+  QHead* h = a.h;
+  Lds& L = *reinterpret_cast<Lds*>(smem);
+  const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
+  // The survivor loads do not wait for the survivor count: every slot below
+  // min(capacity, RANK_CMAX) is in the buffer, and slots past the count are
+  // ignored.  The count decides after the histogram (which consumes the
+  // loads) whether this path applies.
+  const U* sk = static_cast<const U*>(a.sk);
+  const R* sf = static_cast<const R*>(a.sf);
+  const uint32_t lim = a.cap < (uint64_t)RANK_CMAX ? (uint32_t)a.cap : RANK_CMAX;
+  U k[E];
+  R f[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t j = (uint32_t)e * NT + t;
+    k[e] = j < lim ? sk[j] : (U)0;
+    f[e] = j < lim ? sf[j] : (R)0;
+  }
+  for (uint32_t i = t; i < NB; i += NT) L.hist[i] = 0;
+  const uint64_t C64 = h->surv_count;
+  const uint64_t K = a.k_eff;
+  const bool ok = C64 >= K && C64 <= a.cap && C64 <= RANK_CMAX;
+  const uint32_t C = ok ? (uint32_t)C64 : 0u;
+  const T base = wide((U)h->thr_k, (R)h->thr_f);
+  __syncthreads();  // histogram cleared
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t j = (uint32_t)e * NT + t;
+    if (j < C) atomicAdd(&L.hist[log_bucket<T>(wide(k[e], f[e]) - base)], 1u);
+  }
+  __syncthreads();
+  if (!ok) {  // uniform; every thread is past its histogram updates
+    if (blockIdx.x == 0) rank_tail_fallback<KT, RT>(a, smem);
+    return;
+  }
+  // boundary bucket: thread t holds buckets [t BPT, t BPT + BPT); suffix sums
+  // from the top find the one where the count reaches K
+  uint32_t s = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < BPT; ++i) {
+    const uint32_t bin = t * BPT + i;
+    s += bin < NB ? L.hist[bin] : 0u;
+  }
+  uint32_t x = s;  // sum over lanes >= this one
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_down(x, o, 64);
+    if (lane + (uint32_t)o < 64) x += y;
+  }
+  if (lane == 0) L.wsum[w] = x;
+  __syncthreads();
+  uint32_t above = x - s;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) above += (uint32_t)i > w ? L.wsum[i] : 0u;
+  if (above < K && K <= (uint64_t)above + s) {
+    uint32_t acc = above;
+    for (int i = (int)BPT - 1; i >= 0; --i) {
+      const uint32_t bin = t * BPT + (uint32_t)i;
+      if (bin >= NB) continue;
+      acc += L.hist[bin];
+      if (acc >= K) {
+        L.bstar = bin;
+        L.hcount = acc;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t bstar = L.bstar, H = L.hcount;
+  if (H > RANK_HMAX) {
+    __syncthreads();  // every thread has read the boundary before the LDS is reused
+    if (blockIdx.x == 0) rank_tail_fallback<KT, RT>(a, smem);
+    return;
+  }
+  // the hot set, and the part of it this workgroup ranks: per-thread counts,
+  // one block-wide exclusive scan of (hot << 16 | owned), then plain stores
+  const uint32_t G = gridDim.x, me = blockIdx.x;
+  uint32_t hot_bits = 0, own_bits = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t j = (uint32_t)e * NT + t;
+    const bool hot = j < C && log_bucket<T>(wide(k[e], f[e]) - base) >= bstar;
+    hot_bits |= hot ? 1u << e : 0u;
+    own_bits |= hot && j % G == me ? 1u << e : 0u;
+  }
+  const uint32_t packed = ((uint32_t)__popc(hot_bits) << 16) | (uint32_t)__popc(own_bits);
+  uint32_t incl = packed;  // inclusive scan over the lanes
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= (uint32_t)o) incl += y;
+  }
+  if (lane == 63) L.wsum[w] = incl;
+  __syncthreads();
+  uint32_t excl = incl - packed, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const uint32_t v = L.wsum[i];
+    excl += (uint32_t)i < w ? v : 0u;
+    tot += v;
+  }
+  uint32_t pos = excl >> 16, qo = excl & 0xFFFFu;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (hot_bits & (1u << e)) {
+      L.hu[pos] = k[e];
+      L.hf[pos] = f[e];
+      L.hi[pos] = (uint32_t)e * NT + t;
+      if (own_bits & (1u << e)) {
+        L.mine[qo] = pos;
+        L.gt[qo] = 0;
+        L.eq[qo] = 1;  // itself
+        ++qo;
+      }
+      ++pos;
+    }
+  }
+  __syncthreads();
+  // ranks: thread -> (owned element q, slice s of H), every thread busy
+  const uint32_t M = tot & 0xFFFFu;
+  if (M > 0) {
+    const uint32_t Mr = M < (uint32_t)NT ? M : (uint32_t)NT;
+    const uint32_t P = (uint32_t)NT / Mr;  // slices of H
+    const uint32_t sl = t / Mr;
+    const uint32_t hs = (H + P - 1) / P;
+    const uint32_t j0 = sl * hs < H ? sl * hs : H;
+    const uint32_t j1 = j0 + hs < H ? j0 + hs : H;
+    for (uint32_t q0 = 0; q0 < M; q0 += Mr) {
+      const uint32_t q = q0 + t % Mr;
+      const bool act = sl < P && q < M;
+      const uint32_t p = act ? L.mine[q] : 0u;
+      const U ui = L.hu[p];
+      const R fi = L.hf[p];
+      uint32_t gt = 0, eq = 0;
+      if (act) {
+        for (uint32_t jj = j0; jj < j1; ++jj) {
+          const U uj = L.hu[jj];
+          const R fj = L.hf[jj];
+          gt += (uj > ui || (uj == ui && fj > fi)) ? 1u : 0u;
+          eq += (uj == ui && fj == fi && jj != p) ? 1u : 0u;
+        }
+      }
+      if (gt) atomicAdd(&L.gt[q], gt);
+      if (eq) atomicAdd(&L.eq[q], eq);
+    }
+  }
+  __syncthreads();
+  const U dmask = (U)a.dmask;
+  for (uint32_t q = t; q < M; q += NT) {
+    const uint32_t p = L.mine[q];
+    const U ui = L.hu[p];
+    const R fi = L.hf[p];
+    uint64_t rank = L.gt[q];
+    if (L.eq[q] > 1) {  // identical composites: the lower survivor index goes first
+      const uint32_t ii = L.hi[p];
+      for (uint32_t jj = 0; jj < H; ++jj)
+        rank += (L.hu[jj] == ui && L.hf[jj] == fi && L.hi[jj] < ii) ? 1u : 0u;
+    }
+    if (rank < K) write_out<KT, RT>(rank, ui, fi, dmask, a.out_keys, a.out_rids);
+  }
+  if (me == 0 && t == 0) h->path = 3u;
+}
+
+// Workgroups of the tail for k results: enough that each ranks a few dozen
+// hot survivors.
+inline uint32_t rank_grid(uint64_t k_eff) {
+  uint64_t g = (k_eff + 15) / 16;
+  if (g < RANK_GMIN) g = RANK_GMIN;
+  if (g > RANK_GMAX) g = RANK_GMAX;
+  return (uint32_t)g;
+}
+
+}  // namespace tk

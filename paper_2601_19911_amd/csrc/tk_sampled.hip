@@ -9,10 +9,15 @@
 //   k_filter  the single streaming pass over the keys: composites >= T are
 //             staged in LDS (wave ballot + LDS atomic) and appended to the
 //             survivor buffer with one global atomic per workgroup.
-//   k_tail    one workgroup: if K <= survivors <= capacity, radix-selects the
-//             best K of the survivors, bitonic-sorts them in LDS and writes
-//             the result; otherwise (the sample misjudged) it radix-selects
-//             over the whole input instead.
+//   k_rtail   the best K of the survivors over many workgroups: one
+//             histogram of the survivors' distance to the threshold bounds a
+//             small hot set, whose members are ranked by counting and written
+//             at their rank (tk_rank.hpp).
+//   k_tail1   the one-workgroup tail (k_rtail's fallback, and a tuning
+//             choice): if K <= survivors <= capacity, radix-selects the best
+//             K of the survivors, bitonic-sorts them in LDS and writes the
+//             result; otherwise (the sample misjudged) it radix-selects over
+//             the whole input instead.
 // Any threshold with at least K survivors yields the exact answer, and a
 // misjudged one falls back to the exact select, so the result never depends on
 // the sample.
@@ -21,6 +26,7 @@
 #include <mutex>
 #include <vector>
 
+#include "tk_rank.hpp"
 #include "tk_sampled.hpp"
 
 namespace tk {
@@ -51,25 +57,21 @@ __global__ __launch_bounds__(TAIL_NT) void k_tail1(TailArgs1 a) {
   tail_body<KT, RT>(a, t, sc);
 }
 
+template <int KT, int RT>
+__global__ __launch_bounds__(RANK_NT) void k_rtail(TailArgs1 a) {
+  __shared__ __align__(16) unsigned char smem[rank_smem_bytes<KT, RT>()];
+  rank_tail_body<KT, RT>(a, smem);
+}
+
 // ---- host ------------------------------------------------------------------------------------
 
-// Workgroups of the streaming pass: as many as are resident at once, so the
-// pass runs as one wave of workgroups (computed once per kernel and device).
-template <int KT, int RT, int VEC, int UNR>
-static uint32_t filter_grid(int dev) {
-  static std::mutex mu;
-  static std::vector<uint32_t> cache;
-  std::lock_guard<std::mutex> lk(mu);
-  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0u);
-  if (cache[dev] == 0) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_filter<KT, RT, VEC, UNR>,
-                                                     FILT_NT, 0) != hipSuccess || nb < 1)
-      nb = 4;
-    cache[dev] = (uint32_t)nb * (uint32_t)device_cus(dev);
-  }
-  return cache[dev];
-}
+// Workgroups of the streaming pass: FILT_WG_PER_CU per CU, each striding over
+// many tiles.  Fewer, longer-lived workgroups stream faster than a full-
+// occupancy grid: at N = 2^28 on MI355X, 2-3 per CU read at 6.9-7.2 TB/s
+// against 6.2-6.5 TB/s for 8 per CU (float32 and int64 keys).
+constexpr uint32_t FILT_WG_PER_CU = 3;
+
+static uint32_t filter_grid(int dev) { return FILT_WG_PER_CU * (uint32_t)device_cus(dev); }
 
 template <typename T>
 static T* wsp(void* ws, size_t off) {
@@ -100,16 +102,23 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
   const SampArgs sa{keys, rids, n, dmask, p.S, p.r1, h, samp_k, samp_f, p.blocks, 0};
   hipLaunchKernelGGL((k_sample<KT, RT>), dim3(p.blocks), dim3(SAMP_NT), 0, st, sa);
   constexpr int VEC = 16 / sizeof(Raw);
-  const uint32_t grid = tun.filter_grid ? tun.filter_grid : filter_grid<KT, RT, VEC, 4>(dev);
+  const bool u8 = tun.filter_unroll == 8;
+  const uint32_t grid = tun.filter_grid ? tun.filter_grid : filter_grid(dev);
   const FiltArgs fa{keys, rids, n, dmask, h, surv_k, surv_f, p.cap, grid, p.r1, samp_k, samp_f,
                     p.blocks * p.r1, 0};
   hipLaunchKernelGGL((k_sfinal<KT, RT>), dim3(1), dim3(FILT_NT), 0, st, fa);
   profile_mark(st, true);
-  hipLaunchKernelGGL((k_filter<KT, RT, VEC, 4>), dim3(grid), dim3(FILT_NT), 0, st, fa);
+  if (u8)
+    hipLaunchKernelGGL((k_filter<KT, RT, VEC, 8>), dim3(grid), dim3(FILT_NT), 0, st, fa);
+  else
+    hipLaunchKernelGGL((k_filter<KT, RT, VEC, 4>), dim3(grid), dim3(FILT_NT), 0, st, fa);
   profile_mark(st, false);
   const TailArgs1 ta{keys, rids, n, dmask, h, surv_k, surv_f, p.cap, cand_k, cand_f,
                      tmp_k, tmp_f, k_eff, out_keys, out_rids, TAIL_SURVIVORS, 0};
-  hipLaunchKernelGGL((k_tail1<KT, RT>), dim3(1), dim3(TAIL_NT), 0, st, ta);
+  if (tun.rank_tail)
+    hipLaunchKernelGGL((k_rtail<KT, RT>), dim3(rank_grid(k_eff)), dim3(RANK_NT), 0, st, ta);
+  else
+    hipLaunchKernelGGL((k_tail1<KT, RT>), dim3(1), dim3(TAIL_NT), 0, st, ta);
   return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
 }
 

@@ -203,9 +203,27 @@ __device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch&
   const U base = block_min<NT, U>(cmin, sc);
   const RegElems<U, R, EF> el{k2, f2, nv};
   const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.r1, base, sc);
+  // The threshold is the r1-th best candidate itself, the smallest of the
+  // selected ones.  The select may stop with low digits unresolved (its
+  // bucket held exactly the count needed); the prefix padded with zeros
+  // would also admit every key between it and that candidate, which for
+  // clustered keys (a presorted column) is a large share of the input.
+  const U lo = s.base + s.P;
+  const R lof = s.kind == SEL_KEY ? (R)0 : s.Pf;
+  U mk = (U)~(U)0;
+  R mf = (R)~(R)0;
+#pragma unroll
+  for (int e = 0; e < EF; ++e) {
+    const bool in = e < nv && (k2[e] > lo || (k2[e] == lo && f2[e] >= lof));
+    if (in && (k2[e] < mk || (k2[e] == mk && f2[e] < mf))) {
+      mk = k2[e];
+      mf = f2[e];
+    }
+  }
+  block_min_comp<NT, U, R>(mk, mf, sc);
   if (threadIdx.x == 0) {
-    a.h->thr_k = (unsigned long long)(U)(s.base + s.P);
-    a.h->thr_f = s.kind == SEL_KEY ? 0ull : (unsigned long long)s.Pf;
+    a.h->thr_k = (unsigned long long)mk;
+    a.h->thr_f = (unsigned long long)mf;
   }
 }
 
@@ -325,7 +343,11 @@ __device__ __noinline__ void select_sort_write(const Src src, uint64_t n, typena
   constexpr int NT = TAIL_NT;
   constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
   const U dmask = (U)o.dmask;
-  auto emit = [&](uint64_t j, U u, R f) { write_out<KT, RT>(j, u, f, dmask, o.out_keys, o.out_rids); };
+  void* const ok = o.out_keys;
+  void* const orr = o.out_rids;
+  // captures by value: a reference to the arguments handed to the out-of-line
+  // sort would move them to scratch and serialize every load behind them
+  auto emit = [=](uint64_t j, U u, R f) { write_out<KT, RT>(j, u, f, dmask, ok, orr); };
   const GlobElems<NT, Src> el{src, n};
   const Sel<U, R> s = block_radix_select<NT, U, R>(el, o.k_eff, base, sc);
   if (o.k_eff <= CAP) {
@@ -379,7 +401,9 @@ __device__ __forceinline__ void select_sort_write_regs(const TailArgs1& a, const
       if (e < nv) lmin = k[e] < lmin ? k[e] : lmin;
     base = block_min<NT, U>(lmin, sc);
   }
-  auto emit = [&](uint64_t j, U u, R f_) { write_out<KT, RT>(j, u, f_, dmask, a.out_keys, a.out_rids); };
+  void* const ok = a.out_keys;
+  void* const orr = a.out_rids;
+  auto emit = [=](uint64_t j, U u, R f_) { write_out<KT, RT>(j, u, f_, dmask, ok, orr); };
   const RegElems<U, R, E> el{k, f, nv};
   const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.k_eff, base, sc);
   if (a.k_eff <= CAP) {

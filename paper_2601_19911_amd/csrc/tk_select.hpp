@@ -50,6 +50,7 @@ __device__ __forceinline__ bool sel_maybe(const Sel<U, R>& s, U u) {
 struct SelScratch {
   uint32_t hist[256];
   unsigned long long red[16];
+  unsigned long long red2[16];
   uint32_t res[4];
   uint32_t cnt[2];
 };
@@ -100,6 +101,33 @@ __device__ __forceinline__ T block_min(T v, SelScratch& sc) {
     m = w < m ? w : m;
   }
   return m;
+}
+
+// Smallest composite (k, f) over the block, lexicographic; threads with
+// nothing to offer pass (~0, ~0).  NT <= 1024.
+template <int NT, typename U, typename R>
+__device__ __forceinline__ void block_min_comp(U& k, R& f, SelScratch& sc) {
+  const U wk = wave_min(k);
+  R wf = wave_min(k == wk ? f : (R)~(R)0);
+  __syncthreads();
+  if (lane_id() == 0) {
+    sc.red[threadIdx.x >> 6] = (unsigned long long)wk;
+    sc.red2[threadIdx.x >> 6] = (unsigned long long)wf;
+  }
+  __syncthreads();
+  U mk = (U)~(U)0;
+  R mf = (R)~(R)0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const U ck = (U)sc.red[i];
+    const R cf = (R)sc.red2[i];
+    if (ck < mk || (ck == mk && cf < mf)) {
+      mk = ck;
+      mf = cf;
+    }
+  }
+  k = mk;
+  f = mf;
 }
 
 // After the histogram is complete: finds digit b with (sum of bins above b) <

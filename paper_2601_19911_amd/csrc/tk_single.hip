@@ -446,6 +446,10 @@ void set_tuning(const tk_tuning* t) {
   if (t->force_cap < 0) g_tuning.force_cap = 0;
   if (t->force_exact == 1) g_tuning.force_exact = 1;
   if (t->force_exact == 2) g_tuning.force_exact = 0;
+  if (t->tail_mode == 1) g_tuning.rank_tail = 1;
+  if (t->tail_mode == 2) g_tuning.rank_tail = 0;
+  if (t->filter_unroll == 4 || t->filter_unroll == 8) g_tuning.filter_unroll = (uint32_t)t->filter_unroll;
+  if (t->filter_grid < 0) g_tuning.filter_grid = 0;
 }
 
 size_t single_ws_bytes(uint64_t n, uint64_t k_eff, uint32_t kb, uint32_t rb, const Tuning& t) {

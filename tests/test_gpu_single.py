@@ -156,15 +156,17 @@ def test_paths_are_taken_and_exact():
         assert info["path"] == expect_path
         assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"path {expect_path}")
 
-    go(2)
+    go(3)                                # survivors ranked across workgroups
     try:
-        tk.set_tuning(force_cap=64)      # survivors overflow: exact fallback over the input
+        tk.set_tuning(tail_mode=2)       # one workgroup selects and sorts the survivors
+        go(2)
+        tk.set_tuning(tail_mode=1, force_cap=64)  # survivors overflow: exact select over the input
         go(4)
         tk.set_tuning(force_cap=-1, force_exact=1)
         go(5)
     finally:
-        tk.set_tuning(force_cap=-1, force_exact=2)
-    go(2)
+        tk.set_tuning(force_cap=-1, force_exact=2, tail_mode=1)
+    go(3)
 
 
 def test_garbage_workspace_is_still_exact():
@@ -184,7 +186,7 @@ def test_garbage_workspace_is_still_exact():
         info = tk.query_info(ws)
         say(f"call {i}: {info}")
         if i == 1:
-            assert info["path"] == 2
+            assert info["path"] == 3
 
 
 def test_workspace_reuse_across_queries():
