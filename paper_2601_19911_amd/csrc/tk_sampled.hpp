@@ -273,20 +273,34 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
 #pragma unroll
       for (int e = 0; e < VEC; ++e) any |= (Key<KT>::enc(v[u][e]) ^ dmask) >= Tk;
     if (ballot(any) == 0) continue;
+    // A vector some lane of the wave reaches the threshold with: the row-ids
+    // of the whole vector are read at once (coalesced; keys tied with the
+    // threshold are common in skewed columns), then survivors are staged.
 #pragma unroll
-    for (int u = 0; u < UNR; ++u)
+    for (int u = 0; u < UNR; ++u) {
+      U kk[VEC];
+      bool hit = false;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        const uint64_t i = base + ((uint64_t)u * NT + threadIdx.x) * VEC + e;
-        const U kk = Key<KT>::enc(v[u][e]) ^ dmask;
-        bool pass = kk > Tk;
-        R ff = 0;
-        if (kk >= Tk) {
-          ff = src.flip(i);
-          pass = pass || ff >= Tf;
-        }
-        stage_survivor<U, R>(pass, kk, ff, st, h, sk, sf, a.cap);
+        kk[e] = Key<KT>::enc(v[u][e]) ^ dmask;
+        hit |= kk[e] >= Tk;
       }
+      if (ballot(hit) == 0) continue;
+      const uint64_t i0 = base + ((uint64_t)u * NT + threadIdx.x) * VEC;
+      R ff[VEC];
+      bool pass[VEC];
+      bool pv = false;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) ff[e] = src.flip(i0 + e);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        pass[e] = kk[e] > Tk || (kk[e] == Tk && ff[e] >= Tf);
+        pv |= pass[e];
+      }
+      if (ballot(pv) == 0) continue;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) stage_survivor<U, R>(pass[e], kk[e], ff[e], st, h, sk, sf, a.cap);
+    }
   }
   // the head and the remainder (fewer than VEC + TILE keys), one per thread:
   // position p < head is key p, the others follow the last whole tile

@@ -1,0 +1,105 @@
+"""Parity at the full size of the single-query workloads: N = 2^28 keys
+generated on the device, explicit iota row-ids and a caller workspace (the
+launch configuration bench.py times), every output compared with the CPU
+oracle bit for bit.  Presorted and Zipf-ascending inputs are also checked
+against their closed forms, which depend on neither side.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import inputgen
+import oracle
+import paper_2601_19911_amd as tk
+from inputgen import native as gen
+from tests.gpu_util import assert_same, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+N = 1 << 28
+
+KIND = {("float32", "uniform"): inputgen.KIND_U_F32, ("int64", "uniform"): inputgen.KIND_U_I64,
+        ("float32", "zipf"): inputgen.KIND_ZIPF_F32, ("int64", "zipf"): inputgen.KIND_ZIPF_I64,
+        ("float32", "sorted"): inputgen.KIND_SORTED_F32, ("int64", "sorted"): inputgen.KIND_SORTED_I64}
+
+
+def device_input(dtype: str, dist: str):
+    """(device keys, device iota row-ids, host keys) of the N = 2^28 workload."""
+    import torch
+    dev = torch.device("cuda:0")
+    tdt = {"float32": torch.float32, "int64": torch.int64}[dtype]
+    keys = torch.empty(N, dtype=tdt, device=dev)
+    cdf = cdf_dev = None
+    if dist == "zipf":
+        cdf = inputgen.zipf_cdf(1.1, 10 ** 6)
+        cdf_dev = torch.from_numpy(cdf).to(dev)
+    st = torch.cuda.current_stream().cuda_stream
+    gen.device_fill(KIND[(dtype, dist)], inputgen.config_seed(2), N, keys.data_ptr(), n_total=N,
+                    cdf_dev_ptr=None if cdf_dev is None else cdf_dev.data_ptr(),
+                    m=0 if cdf is None else len(cdf), stream=st)
+    rid_t = torch.uint64 if dtype == "int64" else torch.uint32
+    rids = torch.empty(N, dtype=rid_t, device=dev)
+    gen.device_fill(inputgen.KIND_IOTA_U64 if dtype == "int64" else inputgen.KIND_IOTA_U32, 0, N,
+                    rids.data_ptr(), stream=st)
+    torch.cuda.synchronize()
+    return keys, rids, keys.cpu().numpy()
+
+
+def run_query(keys, rids, k, order):
+    import torch
+    kc, rc = tk.key_code(keys.dtype), tk.rid_code(rids.dtype)
+    ws = tk.new_workspace(N, k, kc, rc, device=keys.device)
+    ok, orr = tk.topk(keys, k, rowids=rids, order=order, workspace=ws)
+    torch.cuda.synchronize()
+    info = tk.query_info(ws)
+    say(f"  path {info['path']} survivors {info['survivors']} status {info['status']}")
+    assert info["status"] == 0
+    return to_np(ok), to_np(orr), info
+
+
+def presorted_closed_form(dtype: str, k: int):
+    """Descending Top-K of key_i = (i >> 4) * 2^-24 (float32) or (i >> 4) - 2^23
+    (int64): groups of 16 equal keys from the top, row-ids ascending inside."""
+    g = N // 16
+    j = np.arange(k, dtype=np.int64)
+    grp = g - 1 - j // 16
+    rid = 16 * grp + j % 16
+    if dtype == "float32":
+        key = (grp.astype(np.float64) * 2.0 ** -24).astype(np.float32)
+    else:
+        key = grp - (1 << 23)
+    return key, rid
+
+
+CASES = [
+    ("float32", "uniform", 1000, "desc"),
+    ("float32", "uniform", 10, "desc"),
+    ("float32", "uniform", 100_000, "desc"),
+    ("float32", "zipf", 1000, "desc"),
+    ("float32", "zipf", 1000, "asc"),
+    ("float32", "sorted", 1000, "desc"),
+    ("int64", "uniform", 1000, "desc"),
+    ("int64", "zipf", 1000, "asc"),
+    ("int64", "sorted", 100_000, "desc"),
+]
+
+
+@pytest.mark.parametrize("dtype,dist,k,order", CASES,
+                         ids=[f"{d}-{s}-k{k}-{o}" for d, s, k, o in CASES])
+def test_full_size(dtype, dist, k, order):
+    say(f"full size: {dtype} {dist} N=2^28 K={k} {order}")
+    keys, rids, host = device_input(dtype, dist)
+    gk, gr, info = run_query(keys, rids, k, order)
+    del keys, rids
+    ek, er = oracle.topk(host, None, k, oracle.DESC if order == "desc" else oracle.ASC,
+                         rid_dtype=np.uint64 if dtype == "int64" else np.uint32)
+    assert_same(gk, gr, ek, er, what=f"{dtype} {dist} K={k} {order}")
+    if dist == "sorted" and order == "desc":
+        ck, cr = presorted_closed_form(dtype, k)
+        assert np.array_equal(gk.astype(ck.dtype), ck) and np.array_equal(gr.astype(np.int64), cr)
+    if dist == "zipf" and order == "asc":
+        # the smallest value is rank 1: the first K positions holding it
+        first = np.flatnonzero(host == host.dtype.type(1))[:k]
+        assert first.size == k
+        assert np.all(gk == host.dtype.type(1)) and np.array_equal(gr.astype(np.int64), first)
