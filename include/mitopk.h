@@ -83,8 +83,9 @@ int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int ke
 typedef struct {
   uint32_t path;        /* 2 sampled: streaming filter, then one workgroup's select +
                            sort of the survivors; 3 sampled: streaming filter, then the
-                           survivors ranked across workgroups; 4 sampled, but the
-                           sample misjudged: exact select
+                           survivors ranked across workgroups; 6 sampled, large K:
+                           survivors grouped by bucket, each hot bucket sorted in LDS;
+                           4 sampled, but the sample misjudged: exact select
                            over the input; 5 exact radix select over the input
                            (K a large share of N); 0 after a one-workgroup query */
   uint32_t status;      /* 0, or device failure bits (1: a grid barrier timed out,

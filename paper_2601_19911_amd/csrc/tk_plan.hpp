@@ -30,7 +30,7 @@ struct Tuning {
   double sample_sigma = 3.0;   // safety margin on the sample rank, in std devs
   double cap_sigma = 6.0;      // survivor capacity margin, in std devs
   uint32_t max_sample_log2 = 20;
-  uint32_t min_sample_log2 = 14;
+  uint32_t min_sample_log2 = 11;
   uint32_t filter_grid = 0;    // 0: automatic
   uint32_t filter_unroll = 4;  // 16-byte loads in flight per thread and tile: 4 or 8
   uint64_t force_cap = 0;      // >0: override the survivor capacity (tests)
@@ -71,6 +71,13 @@ inline SamplePlan plan_sample(uint64_t n, uint64_t k_eff, const Tuning& t) {
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// The bucketed tail (large K): logarithmic buckets of a W-bit composite
+// distance with 2^sub buckets per octave.
+constexpr uint64_t BUCKET_TAIL_MIN_K = 2049;  // smaller K: the survivors are ranked directly
+inline uint32_t bucket_sub(uint32_t w) { return w == 64 ? 8u : 7u; }
+inline uint32_t bucket_count(uint32_t w) { return (1u << bucket_sub(w)) * (w - bucket_sub(w) + 1); }
+inline bool bucket_tail_for(uint64_t k_eff) { return k_eff >= BUCKET_TAIL_MIN_K; }
+
 constexpr size_t HEADER_BYTES = 8192;
 
 // Byte offsets inside the caller's workspace for one query.
@@ -79,8 +86,16 @@ struct WsLayout {
   size_t surv = 0;     // survivors: cap composites (key image, flipped row-id), SoA
   size_t cand = 0;     // exact selection: k_eff composites, SoA
   size_t tmp = 0;      // merge ping-pong: k_eff composites, SoA
+  size_t btail = 0;    // bucketed tail (large K): histogram, cursors, offsets, state, and
+                       // cap composites grouped by bucket (0 when not used)
   size_t total = 0;
 };
+
+// Bytes of the bucketed tail's region for a query with survivor capacity cap.
+inline size_t btail_bytes(uint64_t cap, uint32_t kb, uint32_t rb) {
+  const size_t nb = bucket_count(8 * (kb + rb));
+  return align_up(3 * nb * 4 + 64, 256) + align_up(cap * kb, 256) + align_up(cap * rb, 256);
+}
 
 inline WsLayout ws_layout(uint64_t n, uint64_t k_eff, uint32_t kb, uint32_t rb, const SamplePlan& p) {
   WsLayout L;
@@ -94,6 +109,10 @@ inline WsLayout ws_layout(uint64_t n, uint64_t k_eff, uint32_t kb, uint32_t rb, 
   L.tmp = off;
   const uint32_t cap = lds_cap_for(kb + rb);
   if (k_eff > cap) off = align_up(off + (size_t)k_eff * (kb + rb) + 64, 256);
+  if (p.fast && bucket_tail_for(k_eff)) {
+    L.btail = off;
+    off += btail_bytes(p.cap, kb, rb);
+  }
   L.total = off;
   (void)n;
   return L;

@@ -33,40 +33,6 @@ constexpr uint32_t RANK_HMAX = 4096;               // hot set capacity
 constexpr uint32_t RANK_GMIN = 16, RANK_GMAX = 64;
 constexpr uint32_t RANK_MMAX = (RANK_CMAX + RANK_GMIN - 1) / RANK_GMIN;  // owned per workgroup
 
-// The composite (u, f) as one unsigned integer of sizeof(U) + sizeof(R) bytes.
-template <typename U, typename R>
-struct Wide {
-  using T = __uint128_t;
-  static constexpr int W = 8 * (int)(sizeof(U) + sizeof(R));
-};
-template <>
-struct Wide<uint32_t, uint32_t> {
-  using T = uint64_t;
-  static constexpr int W = 64;
-};
-
-template <typename U, typename R>
-__device__ __forceinline__ typename Wide<U, R>::T wide(U u, R f) {
-  using T = typename Wide<U, R>::T;
-  return ((T)u << (8 * sizeof(R))) | (T)f;
-}
-
-__device__ __forceinline__ int wbitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
-__device__ __forceinline__ int wbitlen(__uint128_t x) {
-  const uint64_t hi = (uint64_t)(x >> 64);
-  return hi ? 64 + wbitlen(hi) : wbitlen((uint64_t)x);
-}
-
-// Logarithmic bucket: D itself below 64, then 32 buckets per octave (the five
-// bits under the leading one).  Non-decreasing in D; W-bit D gives
-// 32 W - 128 buckets.
-template <typename T>
-__device__ __forceinline__ uint32_t log_bucket(T d) {
-  const int L = wbitlen(d);
-  if (L <= 6) return (uint32_t)d;
-  return 64u + (uint32_t)(L - 7) * 32u + ((uint32_t)(d >> (L - 6)) & 31u);
-}
-
 template <int KT, int RT>
 struct RankLds {
   using U = typename Key<KT>::U;
@@ -137,7 +103,7 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const uint32_t j = (uint32_t)e * NT + t;
-    if (j < C) atomicAdd(&L.hist[log_bucket<T>(wide(k[e], f[e]) - base)], 1u);
+    if (j < C) atomicAdd(&L.hist[log_bucket_s<5, T>(wide(k[e], f[e]) - base)], 1u);
   }
   __syncthreads();
   if (!ok) {  // uniform; every thread is past its histogram updates
@@ -190,7 +156,7 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const uint32_t j = (uint32_t)e * NT + t;
-    const bool hot = j < C && log_bucket<T>(wide(k[e], f[e]) - base) >= bstar;
+    const bool hot = j < C && log_bucket_s<5, T>(wide(k[e], f[e]) - base) >= bstar;
     hot_bits |= hot ? 1u << e : 0u;
     own_bits |= hot && j % G == me ? 1u << e : 0u;
   }

@@ -13,7 +13,11 @@
 //             histogram of the survivors' distance to the threshold bounds a
 //             small hot set, whose members are ranked by counting and written
 //             at their rank (tk_rank.hpp).
-//   k_tail1   the one-workgroup tail (k_rtail's fallback, and a tuning
+//   k_bhist, k_bscatter, k_bsort   the tail for large K (tk_bucket.hpp):
+//             survivors grouped by a logarithmic bucket of their distance to
+//             the threshold, runs of whole hot buckets sorted in LDS and
+//             written at their offset.
+//   k_tail1   the one-workgroup tail (the fallback of both, and a tuning
 //             choice): if K <= survivors <= capacity, radix-selects the best
 //             K of the survivors, bitonic-sorts them in LDS and writes the
 //             result; otherwise (the sample misjudged) it radix-selects over
@@ -26,6 +30,7 @@
 #include <mutex>
 #include <vector>
 
+#include "tk_bucket.hpp"
 #include "tk_rank.hpp"
 #include "tk_sampled.hpp"
 
@@ -61,6 +66,27 @@ template <int KT, int RT>
 __global__ __launch_bounds__(RANK_NT) void k_rtail(TailArgs1 a) {
   __shared__ __align__(16) unsigned char smem[rank_smem_bytes<KT, RT>()];
   rank_tail_body<KT, RT>(a, smem);
+}
+
+template <int KT, int RT>
+__global__ __launch_bounds__(BT_NT) void k_bhist(BTailArgs b) {
+  __shared__ uint32_t lh[BT<KT, RT>::NB];
+  bhist_body<KT, RT>(b, lh);
+}
+
+template <int KT, int RT>
+__global__ __launch_bounds__(BT_NT) void k_bscatter(BTailArgs b) {
+  __shared__ uint32_t loff[BT<KT, RT>::NB];
+  __shared__ uint32_t lcnt[BT<KT, RT>::NB];
+  __shared__ uint32_t red[32];
+  bscatter_body<KT, RT>(b, loff, lcnt, red);
+}
+
+template <int KT, int RT>
+__global__ __launch_bounds__(TAIL_NT) void k_bsort(BTailArgs b) {
+  __shared__ __align__(16) unsigned char smem[(sizeof(LdsTile<KT, RT>) + 15) / 16 * 16 +
+                                              sizeof(SelScratch)];
+  bsort_body<KT, RT>(b, smem);
 }
 
 // ---- host ------------------------------------------------------------------------------------
@@ -99,7 +125,11 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
   void* tmp_f = wsp<char>(ws, L.tmp + align_up((size_t)k_eff * sizeof(U), 16));
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return TK_EHIP;
-  const SampArgs sa{keys, rids, n, dmask, p.S, p.r1, h, samp_k, samp_f, p.blocks, 0};
+  const bool bucketed = tun.rank_tail && bucket_tail_for(k_eff);
+  const uint32_t nb = bucket_count(8 * (uint32_t)(sizeof(U) + sizeof(R)));
+  uint32_t* bt_words = bucketed ? wsp<uint32_t>(ws, L.btail) : nullptr;  // gh, cur, chunk
+  const SampArgs sa{keys, rids, n, dmask, p.S, p.r1, h, samp_k, samp_f, p.blocks, 0,
+                    bt_words, bucketed ? 2ull * nb : 0ull};
   hipLaunchKernelGGL((k_sample<KT, RT>), dim3(p.blocks), dim3(SAMP_NT), 0, st, sa);
   constexpr int VEC = 16 / sizeof(Raw);
   const bool u8 = tun.filter_unroll == 8;
@@ -115,7 +145,15 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
   profile_mark(st, false);
   const TailArgs1 ta{keys, rids, n, dmask, h, surv_k, surv_f, p.cap, cand_k, cand_f,
                      tmp_k, tmp_f, k_eff, out_keys, out_rids, TAIL_SURVIVORS, 0};
-  if (tun.rank_tail)
+  if (bucketed) {
+    const size_t hot = align_up((size_t)3 * nb * 4 + 64, 256);
+    const BTailArgs bt{ta, bt_words, bt_words + nb, bt_words + 2 * nb,
+                       wsp<BMeta>(ws, L.btail + (size_t)3 * nb * 4), wsp<char>(ws, L.btail + hot),
+                       wsp<char>(ws, L.btail + hot + align_up((size_t)p.cap * sizeof(U), 256))};
+    hipLaunchKernelGGL((k_bhist<KT, RT>), dim3(BT_SLICES), dim3(BT_NT), 0, st, bt);
+    hipLaunchKernelGGL((k_bscatter<KT, RT>), dim3(BT_SLICES), dim3(BT_NT), 0, st, bt);
+    hipLaunchKernelGGL((k_bsort<KT, RT>), dim3(BT_GRID), dim3(TAIL_NT), 0, st, bt);
+  } else if (tun.rank_tail)
     hipLaunchKernelGGL((k_rtail<KT, RT>), dim3(rank_grid(k_eff)), dim3(RANK_NT), 0, st, ta);
   else
     hipLaunchKernelGGL((k_tail1<KT, RT>), dim3(1), dim3(TAIL_NT), 0, st, ta);

@@ -14,6 +14,7 @@
 #include "tk_plan.hpp"
 #include "tk_select.hpp"
 #include "tk_src.hpp"
+#include "tk_wide.hpp"
 
 namespace tk {
 
@@ -34,6 +35,8 @@ struct SampArgs {
   void* cf;
   uint32_t nblk;  // sample workgroups of this query
   uint32_t pad;
+  uint32_t* zero;  // nzero words the sample workgroups clear for later launches, or nullptr
+  uint64_t nzero;
 };
 
 struct FiltArgs {
@@ -96,6 +99,9 @@ __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, u
     h->status = 0;
     h->path = 0;
   }
+  if (a.zero)
+    for (uint64_t i = (uint64_t)blk * NT + threadIdx.x; i < a.nzero; i += (uint64_t)a.nblk * NT)
+      a.zero[i] = 0u;
   const InputSrc<KT, RT> src{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, (U)a.dmask};
   const uint64_t nchunks = a.S / SAMPLE_CHUNK;
   const uint64_t stride = a.n / nchunks;  // >= 16: n >= 16 * S
@@ -273,25 +279,32 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
 #pragma unroll
       for (int e = 0; e < VEC; ++e) any |= (Key<KT>::enc(v[u][e]) ^ dmask) >= Tk;
     if (ballot(any) == 0) continue;
-    // A vector some lane of the wave reaches the threshold with: the row-ids
-    // of the whole vector are read at once (coalesced; keys tied with the
-    // threshold are common in skewed columns), then survivors are staged.
+    // A vector some lane of the wave reaches the threshold with.  When a key
+    // of the wave ties with the threshold (common in skewed columns) the
+    // row-ids of the whole vector are read at once, coalesced; otherwise only
+    // the lanes above the threshold read theirs.  Then survivors are staged.
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       U kk[VEC];
-      bool hit = false;
+      bool hit = false, tie = false;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         kk[e] = Key<KT>::enc(v[u][e]) ^ dmask;
         hit |= kk[e] >= Tk;
+        tie |= kk[e] == Tk;
       }
       if (ballot(hit) == 0) continue;
       const uint64_t i0 = base + ((uint64_t)u * NT + threadIdx.x) * VEC;
       R ff[VEC];
       bool pass[VEC];
       bool pv = false;
+      if (ballot(tie)) {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) ff[e] = src.flip(i0 + e);
+        for (int e = 0; e < VEC; ++e) ff[e] = src.flip(i0 + e);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) ff[e] = kk[e] > Tk ? src.flip(i0 + e) : (R)0;
+      }
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         pass[e] = kk[e] > Tk || (kk[e] == Tk && ff[e] >= Tf);

@@ -221,3 +221,29 @@ def test_gather_rows_device_matches_take():
     tk.gather_rows_device(dp, dr, out)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint64), pay[:, r].view(np.uint64))
+
+
+def test_bucketed_tail_path():
+    """K above the ranked tail's reach takes the bucketed tail (path 6); the
+    one-workgroup tail (tail_mode=2) gives the same exact result."""
+    import torch
+    n = 1 << 22
+    for dtype, k, order in (("float32", 5000, "desc"), ("int64", 30000, "asc"), ("int32", 2049, "desc")):
+        keys = inputgen.generate(KINDS[dtype], 41, n)
+        kd = to_dev(keys)
+        rdt = np.uint64 if dtype == "int64" else np.uint32
+        exp = oracle.topk(keys, None, k, order_code(order), rid_dtype=rdt)
+        for mode, expect in ((1, 6), (2, 2)):
+            try:
+                tk.set_tuning(tail_mode=mode)
+                ws = tk.new_workspace(n, k, tk.key_code(keys.dtype),
+                                      tk.TK_RID_U64 if rdt == np.uint64 else tk.TK_RID_U32)
+                ok, orr = tk.topk(kd, k, order=order, workspace=ws,
+                                  rid_dtype=torch.uint64 if rdt == np.uint64 else torch.uint32)
+                torch.cuda.synchronize()
+                info = tk.query_info(ws)
+                say(f"{dtype} k={k} {order} tail_mode={mode}: {info}")
+                assert info["status"] == 0 and info["path"] == expect
+                assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"{dtype} k={k} mode={mode}")
+            finally:
+                tk.set_tuning(tail_mode=1)
