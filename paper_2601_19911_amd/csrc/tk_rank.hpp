@@ -10,7 +10,7 @@
 //      above;
 //   2. finds the boundary bucket b*, the one holding rank K counted from the
 //      top, and collects the hot set H (bucket >= b*, |H| >= K) in LDS;
-//   3. counts, for each hot survivor it owns (survivor index mod the grid),
+//   3. counts, for each hot survivor it owns (a range of survivor indices),
 //      the members of H better than it: that count is the survivor's rank,
 //      and ranks below K are its output position.  Identical composites
 //      (possible only with repeated row-ids) are ordered by survivor index.
@@ -151,14 +151,16 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
   }
   // the hot set, and the part of it this workgroup ranks: per-thread counts,
   // one block-wide exclusive scan of (hot << 16 | owned), then plain stores
+  // workgroup me owns survivor indices [me * per, me * per + per)
   const uint32_t G = gridDim.x, me = blockIdx.x;
+  const uint32_t per = (C + G - 1) / G, jlo = me * per, jhi = jlo + per;
   uint32_t hot_bits = 0, own_bits = 0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const uint32_t j = (uint32_t)e * NT + t;
     const bool hot = j < C && log_bucket_s<5, T>(wide(k[e], f[e]) - base) >= bstar;
     hot_bits |= hot ? 1u << e : 0u;
-    own_bits |= hot && j % G == me ? 1u << e : 0u;
+    own_bits |= hot && j >= jlo && j < jhi ? 1u << e : 0u;
   }
   const uint32_t packed = ((uint32_t)__popc(hot_bits) << 16) | (uint32_t)__popc(own_bits);
   uint32_t incl = packed;  // inclusive scan over the lanes
