@@ -376,9 +376,9 @@ def suite_c5(a):
     n, k, off = req["n"], req["k"], req["offset"]
     cost = json.loads(a.cost) if a.cost else None
 
-    def run(gate, rate):
-        srv = Server(arena_bytes=a.arena_mb << 20, max_batch=a.max_batch, slots=a.slots,
-                     window_us=a.window_us, gate=gate, margin_ms=0.0, cpu_threads=a.cpu_threads,
+    def run(gate, rate, max_batch, slots, window_us):
+        srv = Server(arena_bytes=a.arena_mb << 20, max_batch=max_batch, slots=slots,
+                     window_us=window_us, gate=gate, margin_ms=0.0, cpu_threads=a.cpu_threads,
                      cost=cost)
         ids = [srv.add_column(d, h) for d, h in cols]
         # Poisson arrivals: exponential gaps from the recipe's uniforms
@@ -386,13 +386,14 @@ def suite_c5(a):
         t_arr = np.cumsum(gaps) - gaps[0]
         rids = srv.replay(t_arr, np.array(ids)[col_of], off, n, k, np.zeros(cnt, dtype=np.uint8))
         srv.drain()
-        lat, routes, sub = [], [], []
+        lat, routes, sub, done = [], [], [], []
         bad = 0
         for i in range(cnt):
             res = srv.result(int(rids[i]), int(col_of[i]), int(min(k[i], n[i])))
             gk, gr, info = res
             lat.append((info.t_done_ns - info.t_submit_ns) * 1e-9)
             sub.append(info.t_submit_ns)
+            done.append(info.t_done_ns)
             routes.append(info.route)
             if i % a.check_every == 0:
                 h = cols[int(col_of[i])][1][int(off[i]):int(off[i] + n[i])]
@@ -400,13 +401,22 @@ def suite_c5(a):
                 bad += not same(gk, gr, ek, er + np.uint64(off[i]))
         st = srv.stats()
         srv.close()
-        return np.array(lat), np.array(routes), st, bad
+        span = (max(done) - min(sub)) * 1e-9
+        return np.array(lat), np.array(routes), st, bad, span
 
-    results = {}
-    for gate, name in ((GATE_GPU, "always_gpu"), (GATE_COST, "cost_gate")):
+    # per_query: the same request loop, one request per launch and one slot (no
+    # batching, no overlap); always_gpu: continuous batching; cost_gate: batching
+    # with small requests routed to the CPU
+    modes = (("per_query", GATE_GPU, 1, 1, 0.0), ("always_gpu", GATE_GPU, a.max_batch, a.slots, a.window_us),
+             ("cost_gate", GATE_COST, a.max_batch, a.slots, a.window_us))
+    for name, gate, mb, sl, win in modes:
+        if a.modes and name not in a.modes:
+            continue
         for lam in a.rates:
-            lat, routes, st, bad = run(gate, lam)
-            emit({"suite": "c5", "gate": name, "rate_qps": lam, "requests": cnt,
+            lat, routes, st, bad, span = run(gate, lam, mb, sl, win)
+            emit({"suite": "c5", "mode": name, "rate_qps": lam, "requests": cnt,
+                  "columns": a.columns, "col_rows": col_len,
+                  "achieved_qps": cnt / span, "makespan_s": span,
                   "lat_p50_ms": pct(lat, 50) * 1e3, "lat_p95_ms": pct(lat, 95) * 1e3,
                   "lat_p99_ms": pct(lat, 99) * 1e3, "cpu_routed": float(np.mean(routes == 1)),
                   "stats": st, "oracle_checked": (cnt + a.check_every - 1) // a.check_every,
@@ -525,6 +535,8 @@ def main():
     ap.add_argument("--col-log2", type=int, default=28)
     ap.add_argument("--requests", type=int, default=4000)
     ap.add_argument("--rates", type=float, nargs="+", default=[2000.0])
+    ap.add_argument("--modes", nargs="+", default=[],
+                    help="c5: per_query, always_gpu, cost_gate (default: all)")
     ap.add_argument("--arena-mb", type=int, default=4096)
     ap.add_argument("--max-batch", type=int, default=256)
     ap.add_argument("--slots", type=int, default=2)
