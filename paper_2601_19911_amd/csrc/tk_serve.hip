@@ -369,6 +369,19 @@ extern "C" int tk_server_create(const tk_server_cfg* cfg, void* arena, size_t ar
   tk_server* s = new (std::nothrow) tk_server;
   if (!s) return TK_ENOMEM;
   s->cfg = *cfg;
+  const tk_server_cfg& c = s->cfg;
+  if (c.cpu_a == 0 && c.cpu_b == 0 && c.cpu_c == 0 && c.gpu_a == 0 && c.gpu_b == 0 && c.gpu_c == 0) {
+    // no cost model given: least-squares fit of measured request times for
+    // N = 2^8 .. 2^22, K in {10, 100, 1000}, int32/int64/float32 keys, on an
+    // MI355X (device-resident keys, launch to results on the host) against the
+    // CPU route on 16 host threads
+    s->cfg.cpu_a = 1.79e-10;
+    s->cfg.cpu_b = 1.26e-8;
+    s->cfg.cpu_c = 4.36e-5;
+    s->cfg.gpu_a = 0.0;
+    s->cfg.gpu_b = 1.48e-8;
+    s->cfg.gpu_c = 5.30e-5;
+  }
   if (s->cfg.max_batch == 0) s->cfg.max_batch = 256;
   if (s->cfg.slots == 0) s->cfg.slots = 2;
   if (s->cfg.cpu_threads <= 0) s->cfg.cpu_threads = 4;
