@@ -22,8 +22,7 @@ struct QHead {
   unsigned long long thr_f;       // sampled threshold (flipped row-id)
   uint32_t status;                // device failure bits (1: barrier timeout)
   uint32_t path;                  // path taken, see tk_info
-  uint32_t ticket;                // sample workgroups done (single query; the filter resets it)
-  uint32_t pad[7];
+  uint32_t pad[8];
 };
 static_assert(sizeof(QHead) == 64, "QHead is 64 bytes");
 

@@ -1,13 +1,11 @@
-// Sampled single-query Top-K (ordering primitive, paper sec. III-A): plain
-// kernels on the caller's stream.  No workgroup waits for another: hand-offs
-// are launch boundaries, except the threshold, which the last sample
-// workgroup to finish (an atomic ticket) computes from the others'
-// candidates.
+// Sampled single-query Top-K (ordering primitive, paper sec. III-A): four
+// plain kernels on the caller's stream; no workgroup waits for or hands data
+// to another within a kernel, so no device-wide fence is needed.
 //
-//   k_sample_t  S keys in 16-key chunks spread over the query, 2048 per
-//             workgroup; each workgroup keeps its best r1 composites, and the
-//             last workgroup to finish selects the r1-th best of all of them:
-//             the threshold T.
+//   k_sample  S keys in 16-key chunks spread over the query, 2048 per
+//             workgroup; each workgroup keeps its best r1 composites.
+//   k_sfinal  one workgroup selects the r1-th best of those candidates: the
+//             threshold T.
 //   k_filter  the single streaming pass over the keys: composites >= T are
 //             staged in LDS (wave ballot + LDS atomic) and appended to the
 //             survivor buffer with one global atomic per workgroup.
@@ -40,9 +38,15 @@ namespace tk {
 
 #ifndef TK_EMU
 template <int KT, int RT>
-__global__ __launch_bounds__(SAMP_NT) void k_sample_t(SampArgs a, FiltArgs fa) {
+__global__ __launch_bounds__(SAMP_NT) void k_sample(SampArgs a) {
   __shared__ SelScratch sc;
-  sample_fused_body<KT, RT>(a, fa, sc, blockIdx.x);
+  sample_body<KT, RT>(a, sc, blockIdx.x);
+}
+
+template <int KT, int RT>
+__global__ __launch_bounds__(FILT_NT) void k_sfinal(FiltArgs a) {
+  __shared__ SelScratch sc;
+  sample_final_body<KT, RT>(a, sc);
 }
 
 template <int KT, int RT, int VEC, int UNR>
@@ -126,13 +130,13 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
   uint32_t* bt_words = bucketed ? wsp<uint32_t>(ws, L.btail) : nullptr;  // gh, cur, chunk
   const SampArgs sa{keys, rids, n, dmask, p.S, p.r1, h, samp_k, samp_f, p.blocks, 0,
                     bt_words, bucketed ? 2ull * nb : 0ull};
+  hipLaunchKernelGGL((k_sample<KT, RT>), dim3(p.blocks), dim3(SAMP_NT), 0, st, sa);
   constexpr int VEC = 16 / sizeof(Raw);
   const bool u8 = tun.filter_unroll == 8;
   const uint32_t grid = tun.filter_grid ? tun.filter_grid : filter_grid(dev);
   const FiltArgs fa{keys, rids, n, dmask, h, surv_k, surv_f, p.cap, grid, p.r1, samp_k, samp_f,
                     p.blocks * p.r1, 0};
-  static_assert(SAMP_NT == FILT_NT, "the last sample workgroup runs the threshold select");
-  hipLaunchKernelGGL((k_sample_t<KT, RT>), dim3(p.blocks), dim3(SAMP_NT), 0, st, sa, fa);
+  hipLaunchKernelGGL((k_sfinal<KT, RT>), dim3(1), dim3(FILT_NT), 0, st, fa);
   profile_mark(st, true);
   if (u8)
     hipLaunchKernelGGL((k_filter<KT, RT, VEC, 8>), dim3(grid), dim3(FILT_NT), 0, st, fa);

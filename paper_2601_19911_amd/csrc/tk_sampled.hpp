@@ -233,27 +233,6 @@ __device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch&
   }
 }
 
-// The sample of a single query with its threshold selection folded in: each
-// workgroup keeps its best r1, and the last one to finish (a ticket in the
-// query state, reset by the streaming pass that follows) selects the r1-th
-// best of all of them.  A ticket that starts from garbage (a workspace never
-// used) can make the wrong workgroup last; the threshold is then wrong too,
-// which costs speed, never exactness (any threshold leads to the exact answer,
-// through the fallback when it admits too few or too many survivors).
-template <int KT, int RT>
-__device__ __forceinline__ void sample_fused_body(const SampArgs& a, const FiltArgs& fa,
-                                                  SelScratch& sc, uint32_t blk) {
-  sample_body<KT, RT>(a, sc, blk);
-  __threadfence();  // this workgroup's candidates, visible to the one that selects
-  __syncthreads();
-  if (threadIdx.x == 0)
-    sc.res[0] = atomicAdd(&a.h->ticket, 1u) == a.nblk - 1u ? 1u : 0u;
-  __syncthreads();
-  if (sc.res[0] == 0u) return;
-  __threadfence();  // every workgroup's candidates
-  sample_final_body<KT, RT>(fa, sc);
-}
-
 template <int KT, int RT, int VEC, int UNR>
 __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
                                             SurvStage<typename Key<KT>::U, typename Rid<RT>::R>& st) {
@@ -263,7 +242,6 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
   constexpr int NT = FILT_NT;
   static_assert(VEC * sizeof(Raw) == 16 || VEC == 1, "vector loads are 16 bytes");
   if (threadIdx.x == 0) st.cnt = 0;
-  if (blk == 0 && threadIdx.x == 0) a.h->ticket = 0u;  // every sample workgroup has finished
   __syncthreads();
   QHead* h = a.h;
   const U Tk = (U)h->thr_k;
