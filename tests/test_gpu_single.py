@@ -247,3 +247,29 @@ def test_bucketed_tail_path():
                 assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"{dtype} k={k} mode={mode}")
             finally:
                 tk.set_tuning(tail_mode=1)
+
+
+def test_repeated_rowids_identical_pairs():
+    """Row-ids may repeat: groups of four identical (key, row-id) pairs, so the
+    tails must order equal composites without dropping or doubling one
+    (ranked tail K <= 2048, bucketed tail, one-workgroup tail)."""
+    import torch
+    n = 1 << 21
+    i = np.arange(n, dtype=np.int64)
+    rids = (i // 4).astype(np.uint32)
+    keys = ((i // 4) * 2654435761 % 50021).astype(np.int32)  # many equal keys, in groups of 4
+    kd, rd = to_dev(keys), to_dev(rids)
+    for k, mode in ((777, 1), (6000, 1), (777, 2)):
+        for order in ("desc", "asc"):
+            try:
+                tk.set_tuning(tail_mode=mode)
+                ws = tk.new_workspace(n, k, tk.TK_KEY_I32, tk.TK_RID_U32)
+                ok, orr = tk.topk(kd, k, rowids=rd, order=order, workspace=ws)
+                torch.cuda.synchronize()
+                info = tk.query_info(ws)
+                say(f"k={k} mode={mode} {order}: {info}")
+                assert info["status"] == 0
+                exp = oracle.topk(keys, rids, k, order_code(order))
+                assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"k={k} mode={mode} {order}")
+            finally:
+                tk.set_tuning(tail_mode=1)
