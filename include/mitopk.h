@@ -130,7 +130,7 @@ int tk_set_tuning(const tk_tuning* t);
 typedef struct tk_plan tk_plan;
 typedef struct {
   uint32_t tile_keys;        /* keys each filter workgroup streams; 0: 65536 (>= 4096) */
-  uint32_t engine_grid;      /* reserved, must be 0 */
+  uint32_t filter_grid;      /* filter workgroups, each looping over the slices; 0: one per slice */
   uint32_t min_sample_log2;  /* smallest sample; queries under 16x it take the exact select; 0: 12 */
   uint32_t max_sample_log2;  /* largest sample; 0: 20 */
   double sample_sigma;       /* margin of the sampled threshold; 0: 3 */

@@ -11,7 +11,7 @@ from . import TopKError, check, key_code, lib, order_code, rid_code
 
 
 class tk_plan_params(ctypes.Structure):
-    _fields_ = [("tile_keys", ctypes.c_uint32), ("engine_grid", ctypes.c_uint32),
+    _fields_ = [("tile_keys", ctypes.c_uint32), ("filter_grid", ctypes.c_uint32),
                 ("min_sample_log2", ctypes.c_uint32), ("max_sample_log2", ctypes.c_uint32),
                 ("sample_sigma", ctypes.c_double), ("use_graph", ctypes.c_int32)]
 
@@ -52,7 +52,7 @@ class Plan:
 
     def __init__(self, offsets, ks, orders, key_dtype, rid_dtype, device="cuda", stream=None,
                  tile_keys=0, min_sample_log2=0, max_sample_log2=0, sample_sigma=0.0,
-                 use_graph=True):
+                 use_graph=True, filter_grid=0):
         import torch
         L = _bind()
         self.offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
@@ -65,7 +65,7 @@ class Plan:
         self.key_dtype = key_dtype
         self.rid_dtype = rid_dtype
         self.kc, self.rc = key_code(key_dtype), rid_code(rid_dtype)
-        self.params = tk_plan_params(tile_keys, 0, min_sample_log2, max_sample_log2,
+        self.params = tk_plan_params(tile_keys, filter_grid, min_sample_log2, max_sample_log2,
                                      sample_sigma, 0 if use_graph else -1)
         nbytes = L.tk_plan_workspace_size(self.offsets.ctypes.data, self.ks.ctypes.data,
                                           self.orders.ctypes.data, self.q, self.kc, self.rc,

@@ -61,7 +61,7 @@ bool valid_inputs(const uint64_t* offsets, const uint32_t* ks, const uint8_t* or
                   int key_type, int rid_type, const tk_plan_params* params) {
   if (!offsets || !ks || !orders || q == 0) return false;
   if (key_type < 0 || key_type > 2 || rid_type < 0 || rid_type > 1) return false;
-  if (params && ((params->tile_keys && params->tile_keys < 4096) || params->engine_grid ||
+  if (params && ((params->tile_keys && params->tile_keys < 4096) ||
                  params->min_sample_log2 > 24 || params->max_sample_log2 > 24))
     return false;
   for (uint32_t i = 0; i < q; ++i) {
@@ -118,6 +118,7 @@ int upload(tk_plan& P, const void* keys, const void* rowids, void* out_keys, voi
   std::vector<char> host(bytes + 256);
   char* dev = P.ws + P.L.total;
   P.launch = multi_pack(r, host.data(), dev);
+  P.launch.filt_grid = P.params.filter_grid;
   if (hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return TK_EHIP;

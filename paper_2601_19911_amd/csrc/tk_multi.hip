@@ -40,13 +40,17 @@ __global__ __launch_bounds__(FILT_NT) void k_msfinal(const FiltArgs* __restrict_
   sample_final_body<KT, RT>(a, sc);
 }
 
+// Workgroup w streams the slices w, w + grid, w + 2 grid, ... of the block map.
 template <int KT, int RT>
 __global__ __launch_bounds__(FILT_NT) void k_mfilter(const FiltArgs* __restrict__ fa,
-                                                     const uint2* __restrict__ map) {
+                                                     const uint2* __restrict__ map, uint32_t n) {
   __shared__ SurvStage<typename Key<KT>::U, typename Rid<RT>::R> st;
-  const uint2 m = map[blockIdx.x];
-  const FiltArgs a = fa[m.x];
-  filter_body<KT, RT, 16 / sizeof(typename Key<KT>::Raw), 4>(a, m.y, st);
+  for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const uint2 m = map[it];
+    const FiltArgs a = fa[m.x];
+    filter_body<KT, RT, 16 / sizeof(typename Key<KT>::Raw), 4>(a, m.y, st);
+    __syncthreads();  // the stage is reused by the next slice
+  }
 }
 
 template <int KT, int RT>
@@ -212,7 +216,8 @@ void enqueue_typed(const MLaunch& m, hipStream_t st) {
   if (m.n_samp) hipLaunchKernelGGL((k_msample<KT, RT>), dim3(m.n_samp), dim3(SAMP_NT), 0, st, m.sa, m.smap);
   if (m.n_fa) hipLaunchKernelGGL((k_msfinal<KT, RT>), dim3(m.n_fa), dim3(FILT_NT), 0, st, m.fa);
   profile_mark(st, true);
-  if (m.n_filt) hipLaunchKernelGGL((k_mfilter<KT, RT>), dim3(m.n_filt), dim3(FILT_NT), 0, st, m.fa, m.fmap);
+  const uint32_t fg = m.filt_grid && m.filt_grid < m.n_filt ? m.filt_grid : m.n_filt;
+  if (m.n_filt) hipLaunchKernelGGL((k_mfilter<KT, RT>), dim3(fg), dim3(FILT_NT), 0, st, m.fa, m.fmap, m.n_filt);
   profile_mark(st, false);
   if (m.n_tail) hipLaunchKernelGGL((k_mtail<KT, RT>), dim3(m.n_tail), dim3(TAIL_NT), 0, st, m.ta);
 }

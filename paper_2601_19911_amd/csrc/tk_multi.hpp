@@ -70,6 +70,7 @@ struct MLaunch {
   uint32_t n_filt = 0;
   const TailArgs1* ta = nullptr;
   uint32_t n_tail = 0;
+  uint32_t filt_grid = 0;  // filter workgroups looping over the slices; 0: one per slice
 };
 
 // Byte sizes of the records as laid out by multi_pack (each part 256-aligned).

@@ -36,7 +36,6 @@ struct Tuning {
   uint64_t force_cap = 0;      // >0: override the survivor capacity (tests)
   int force_exact = 0;         // 1: always take the exact radix path (tests)
   uint32_t tile_len = 0;       // keys per streaming tile of the engine (0: 256 KiB of keys)
-  uint32_t engine_grid = 0;    // engine workgroups (0: as many as fit)
   int rank_tail = 1;           // 1: survivors ranked across workgroups when they fit; 0: one
                                // workgroup selects and sorts them
 };
