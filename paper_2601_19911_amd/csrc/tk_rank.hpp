@@ -38,9 +38,9 @@ struct RankLds {
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
   static constexpr uint32_t NB = 32u * Wide<U, R>::W - 128u;
+  using T = typename Wide<U, R>::T;
+  T hw[RANK_HMAX];             // hot composites, as one wide integer each
   uint32_t hist[NB];
-  U hu[RANK_HMAX];
-  R hf[RANK_HMAX];
   uint32_t hi[RANK_HMAX];      // survivor index
   uint32_t mine[RANK_MMAX];    // hot-set slots this workgroup ranks
   uint32_t gt[RANK_MMAX];      // members of H better than it
@@ -154,11 +154,15 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
   // workgroup me owns survivor indices [me * per, me * per + per)
   const uint32_t G = gridDim.x, me = blockIdx.x;
   const uint32_t per = (C + G - 1) / G, jlo = me * per, jhi = jlo + per;
+  // hot iff D reaches the lower edge of the boundary bucket (the bucket is
+  // monotone in D): D itself below 64, then (32 + sub) << (octave - 6)
+  const T dlo = bstar < 64u ? (T)bstar
+                            : (T)(32u + (bstar - 64u) % 32u) << ((bstar - 64u) / 32u + 1u);
   uint32_t hot_bits = 0, own_bits = 0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const uint32_t j = (uint32_t)e * NT + t;
-    const bool hot = j < C && log_bucket_s<5, T>(wide(k[e], f[e]) - base) >= bstar;
+    const bool hot = j < C && wide(k[e], f[e]) - base >= dlo;
     hot_bits |= hot ? 1u << e : 0u;
     own_bits |= hot && j >= jlo && j < jhi ? 1u << e : 0u;
   }
@@ -182,8 +186,7 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     if (hot_bits & (1u << e)) {
-      L.hu[pos] = k[e];
-      L.hf[pos] = f[e];
+      L.hw[pos] = wide(k[e], f[e]);
       L.hi[pos] = (uint32_t)e * NT + t;
       if (own_bits & (1u << e)) {
         L.mine[qo] = pos;
@@ -208,15 +211,13 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
       const uint32_t q = q0 + t % Mr;
       const bool act = sl < P && q < M;
       const uint32_t p = act ? L.mine[q] : 0u;
-      const U ui = L.hu[p];
-      const R fi = L.hf[p];
+      const T ci = L.hw[p];
       uint32_t gt = 0, eq = 0;
       if (act) {
         for (uint32_t jj = j0; jj < j1; ++jj) {
-          const U uj = L.hu[jj];
-          const R fj = L.hf[jj];
-          gt += (uj > ui || (uj == ui && fj > fi)) ? 1u : 0u;
-          eq += (uj == ui && fj == fi && jj != p) ? 1u : 0u;
+          const T cj = L.hw[jj];
+          gt += cj > ci ? 1u : 0u;
+          eq += (cj == ci && jj != p) ? 1u : 0u;
         }
       }
       if (gt) atomicAdd(&L.gt[q], gt);
@@ -227,15 +228,14 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
   const U dmask = (U)a.dmask;
   for (uint32_t q = t; q < M; q += NT) {
     const uint32_t p = L.mine[q];
-    const U ui = L.hu[p];
-    const R fi = L.hf[p];
+    const T ci = L.hw[p];
     uint64_t rank = L.gt[q];
     if (L.eq[q] > 1) {  // identical composites: the lower survivor index goes first
       const uint32_t ii = L.hi[p];
-      for (uint32_t jj = 0; jj < H; ++jj)
-        rank += (L.hu[jj] == ui && L.hf[jj] == fi && L.hi[jj] < ii) ? 1u : 0u;
+      for (uint32_t jj = 0; jj < H; ++jj) rank += (L.hw[jj] == ci && L.hi[jj] < ii) ? 1u : 0u;
     }
-    if (rank < K) write_out<KT, RT>(rank, ui, fi, dmask, a.out_keys, a.out_rids);
+    if (rank < K)
+      write_out<KT, RT>(rank, (U)(ci >> (8 * sizeof(R))), (R)ci, dmask, a.out_keys, a.out_rids);
   }
   if (me == 0 && t == 0) h->path = 3u;
 }
