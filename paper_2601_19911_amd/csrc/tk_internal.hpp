@@ -22,7 +22,8 @@ struct QHead {
   unsigned long long thr_f;       // sampled threshold (flipped row-id)
   uint32_t status;                // device failure bits (1: barrier timeout)
   uint32_t path;                  // path taken, see tk_info
-  uint32_t pad[8];
+  uint32_t tie_heavy;             // 1: most sample candidates share the threshold's key
+  uint32_t pad[7];
 };
 static_assert(sizeof(QHead) == 64, "QHead is 64 bytes");
 

@@ -227,9 +227,89 @@ __device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch&
     }
   }
   block_min_comp<NT, U, R>(mk, mf, sc);
+  // candidates sharing the threshold's key: when they are most of them, keys
+  // tied with the threshold are common and the streaming pass reads row-ids
+  // along with the keys
+  uint64_t ties = 0;
+#pragma unroll
+  for (int e = 0; e < EF; ++e) ties += (e < nv && k2[e] == mk) ? 1u : 0u;
+  ties = wave_sum64(ties);
+  __syncthreads();  // block_min_comp's reads of the scratch are done
+  if (lane_id() == 0) sc.red[threadIdx.x >> 6] = ties;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    uint64_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) tot += sc.red[i];
     a.h->thr_k = (unsigned long long)mk;
     a.h->thr_f = (unsigned long long)mf;
+    a.h->tie_heavy = 2 * tot >= a.ncand ? 1u : 0u;
+  }
+}
+
+// Row-ids of VEC consecutive keys: 16-byte loads when the rows allow.
+template <typename R, int VEC>
+__device__ __forceinline__ void load_rowids(const R* p, bool aligned16, R (&out)[VEC]) {
+  if constexpr ((VEC * sizeof(R)) % 16 == 0) {
+    if (aligned16) {
+      constexpr int NQ = (int)(VEC * sizeof(R) / 16);
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) {
+        const u32x4s q = __builtin_nontemporal_load(reinterpret_cast<const u32x4s*>(p) + c);
+        if constexpr (sizeof(R) == 4) {
+          out[4 * c] = q.x; out[4 * c + 1] = q.y; out[4 * c + 2] = q.z; out[4 * c + 3] = q.w;
+        } else {
+          out[2 * c] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+          out[2 * c + 1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
+        }
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) out[e] = p[e];
+}
+
+// Stages the survivors among one VEC-key vector of every lane of the wave:
+// one LDS reservation for all of them; the ones past the stage go straight to
+// the survivor buffer (one global reservation).
+template <typename U, typename R, int VEC>
+__device__ __forceinline__ void stage_vector(const bool (&pass)[VEC], const U (&kk)[VEC],
+                                             const R (&ff)[VEC], SurvStage<U, R>& st, QHead* h,
+                                             U* sk, R* sf, uint64_t cap) {
+  uint64_t m[VEC];
+  uint32_t pre[VEC], tot = 0;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    m[e] = ballot(pass[e]);
+    pre[e] = tot;
+    tot += (uint32_t)__popcll(m[e]);
+  }
+  if (tot == 0) return;
+  uint32_t b = 0;
+  if (lane_id() == 0) b = atomicAdd(&st.cnt, tot);
+  b = __shfl(b, 0, 64);
+  const uint32_t sb = b > FILT_STAGE ? b : FILT_STAGE;  // first position past the stage
+  const uint32_t nspill = b + tot > sb ? b + tot - sb : 0u;
+  uint64_t g = 0;
+  if (nspill) {
+    if (lane_id() == 0) g = atomicAdd(&h->surv_count, (unsigned long long)nspill);
+    g = __shfl(g, 0, 64);
+  }
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    if (!pass[e]) continue;
+    const uint32_t p = b + pre[e] + lanes_below(m[e]);
+    if (p < FILT_STAGE) {
+      st.k[p] = kk[e];
+      st.f[p] = ff[e];
+    } else {
+      const uint64_t pos = g + (p - sb);
+      if (pos < cap) {
+        sk[pos] = kk[e];
+        sf[pos] = ff[e];
+      }
+    }
   }
 }
 
@@ -246,6 +326,8 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
   QHead* h = a.h;
   const U Tk = (U)h->thr_k;
   const R Tf = (R)h->thr_f;
+  const R* rids = static_cast<const R*>(a.rids);
+  const bool tie_rows = rids != nullptr && h->tie_heavy != 0;
   const Raw* keys = static_cast<const Raw*>(a.keys);
   const InputSrc<KT, RT> src{keys, (const R*)a.rids, (U)a.dmask};
   const U dmask = (U)a.dmask;
@@ -254,6 +336,8 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
   constexpr uint64_t TILE = (uint64_t)NT * VEC * UNR;
   uint64_t head = VEC > 1 ? ((16u - ((uintptr_t)keys & 15u)) & 15u) / sizeof(Raw) : 0;
   if (head > a.n) head = a.n;
+  // every lane's row-id vector starts head + a multiple of VEC rows in
+  const bool ralign = rids != nullptr && (((uintptr_t)(rids + head)) & 15u) == 0;
   const uint64_t ntiles = (a.n - head) / TILE;
   for (uint64_t t = blk; t < ntiles; t += a.nblk) {
     const uint64_t base = head + t * TILE;
@@ -272,6 +356,12 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
       } else {
         v[u][0] = keys[i0];
       }
+    }
+    R rv[UNR][VEC];
+    if (tie_rows) {  // with the keys, so both loads are in flight together
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+        load_rowids<R, VEC>(rids + base + ((uint64_t)u * NT + threadIdx.x) * VEC, ralign, rv[u]);
     }
     bool any = false;
 #pragma unroll
@@ -298,7 +388,10 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
       R ff[VEC];
       bool pass[VEC];
       bool pv = false;
-      if (ballot(tie)) {
+      if (tie_rows) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) ff[e] = ~rv[u][e];
+      } else if (ballot(tie)) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) ff[e] = src.flip(i0 + e);
       } else {
@@ -311,8 +404,7 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
         pv |= pass[e];
       }
       if (ballot(pv) == 0) continue;
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) stage_survivor<U, R>(pass[e], kk[e], ff[e], st, h, sk, sf, a.cap);
+      stage_vector<U, R, VEC>(pass, kk, ff, st, h, sk, sf, a.cap);
     }
   }
   // the head and the remainder (fewer than VEC + TILE keys), one per thread:
