@@ -85,6 +85,8 @@ typedef struct {
                            sort of the survivors; 3 sampled: streaming filter, then the
                            survivors ranked across workgroups; 6 sampled, large K:
                            survivors grouped by bucket, each hot bucket sorted in LDS;
+                           7 a small query (N within one LDS tile) ranked across
+                           workgroups over the whole input;
                            4 sampled, but the sample misjudged: exact select
                            over the input; 5 exact radix select over the input
                            (K a large share of N); 0 after a one-workgroup query */

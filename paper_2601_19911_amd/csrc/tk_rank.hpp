@@ -46,6 +46,7 @@ struct RankLds {
   uint32_t gt[RANK_MMAX];      // members of H better than it
   uint32_t eq[RANK_MMAX];      // members of H equal to it (itself included)
   uint32_t wsum[RANK_NT / 64];
+  unsigned long long redk[RANK_NT / 64], redf[RANK_NT / 64];  // minimum of the input
   uint32_t bstar, hcount;
 };
 
@@ -66,8 +67,11 @@ __device__ __noinline__ void rank_tail_fallback(const TailArgs1 a, unsigned char
 }
 
 // The tail over gridDim.x workgroups of RANK_NT threads (RANK_GMIN <=
-// gridDim.x <= RANK_GMAX), in TAIL_SURVIVORS mode.
-template <int KT, int RT>
+// gridDim.x <= RANK_GMAX).  INPUT = false: over the filter's survivors
+// (TAIL_SURVIVORS), distances taken from the threshold.  INPUT = true: over
+// the whole input of a query with n <= RANK_CMAX (TAIL_INPUT), distances taken
+// from the input's smallest composite; a.h may be null.
+template <int KT, int RT, bool INPUT = false>
 __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char* smem) {
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
@@ -84,29 +88,70 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
   // loads) whether this path applies.
   const U* sk = static_cast<const U*>(a.sk);
   const R* sf = static_cast<const R*>(a.sf);
-  const uint32_t lim = a.cap < (uint64_t)RANK_CMAX ? (uint32_t)a.cap : RANK_CMAX;
+  const InputSrc<KT, RT> in{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, (U)a.dmask};
+  const uint32_t lim = INPUT ? (uint32_t)a.n
+                             : (a.cap < (uint64_t)RANK_CMAX ? (uint32_t)a.cap : RANK_CMAX);
   U k[E];
   R f[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const uint32_t j = (uint32_t)e * NT + t;
-    k[e] = j < lim ? sk[j] : (U)0;
-    f[e] = j < lim ? sf[j] : (R)0;
+    if constexpr (INPUT) {
+      k[e] = j < lim ? in.key(j) : (U)0;
+      f[e] = j < lim ? in.flip(j) : (R)0;
+    } else {
+      k[e] = j < lim ? sk[j] : (U)0;
+      f[e] = j < lim ? sf[j] : (R)0;
+    }
   }
   for (uint32_t i = t; i < NB; i += NT) L.hist[i] = 0;
-  const uint64_t C64 = h->surv_count;
+  const uint64_t C64 = INPUT ? a.n : h->surv_count;
   const uint64_t K = a.k_eff;
-  const bool ok = C64 >= K && C64 <= a.cap && C64 <= RANK_CMAX;
+  const bool ok = INPUT || (C64 >= K && C64 <= a.cap && C64 <= RANK_CMAX);
   const uint32_t C = ok ? (uint32_t)C64 : 0u;
-  const T base = wide((U)h->thr_k, (R)h->thr_f);
-  __syncthreads();  // histogram cleared
+  T base;
+  if constexpr (INPUT) {
+    // the smallest composite of the input: every distance is >= 0
+    U mk = (U)~(U)0;
+    R mf = (R)~(R)0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t j = (uint32_t)e * NT + t;
+      if (j < C && (k[e] < mk || (k[e] == mk && f[e] < mf))) {
+        mk = k[e];
+        mf = f[e];
+      }
+    }
+    const U wk = wave_min(mk);
+    const R wf = wave_min(mk == wk ? mf : (R)~(R)0);
+    if (lane == 0) {
+      L.redk[w] = (unsigned long long)wk;
+      L.redf[w] = (unsigned long long)wf;
+    }
+    __syncthreads();  // histogram cleared, wave minima written
+    mk = (U)~(U)0;
+    mf = (R)~(R)0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+      const U ck = (U)L.redk[i];
+      const R cf = (R)L.redf[i];
+      if (ck < mk || (ck == mk && cf < mf)) {
+        mk = ck;
+        mf = cf;
+      }
+    }
+    base = wide(mk, mf);
+  } else {
+    base = wide((U)h->thr_k, (R)h->thr_f);
+    __syncthreads();  // histogram cleared
+  }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const uint32_t j = (uint32_t)e * NT + t;
     if (j < C) atomicAdd(&L.hist[log_bucket_s<5, T>(wide(k[e], f[e]) - base)], 1u);
   }
   __syncthreads();
-  if (!ok) {  // uniform; every thread is past its histogram updates
+  if (!ok) {  // uniform; every thread is past its histogram updates (never with INPUT)
     if (blockIdx.x == 0) rank_tail_fallback<KT, RT>(a, smem);
     return;
   }
@@ -237,7 +282,7 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
     if (rank < K)
       write_out<KT, RT>(rank, (U)(ci >> (8 * sizeof(R))), (R)ci, dmask, a.out_keys, a.out_rids);
   }
-  if (me == 0 && t == 0) h->path = 3u;
+  if (me == 0 && t == 0 && h) h->path = INPUT ? 7u : 3u;
 }
 
 // Workgroups of the tail for k results: enough that each ranks a few dozen

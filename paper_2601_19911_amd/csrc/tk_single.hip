@@ -1,7 +1,9 @@
 // Single-query entry point of key-only Top-K (ordering primitive, paper
 // sec. III-A) and the two paths that do not go through the engine:
-//   - queries that fit one workgroup (k_small): the keys are loaded once,
-//     the best K found by radix select and bitonic-sorted in LDS;
+//   - queries that fit one LDS tile: ranked across workgroups over the whole
+//     input (k_rsmall, tk_rank.hpp), or, as a tuning choice, by one
+//     workgroup (k_small): the keys are loaded once, the best K found by
+//     radix select and bitonic-sorted in LDS;
 //   - queries whose K is a large share of N (or forced, for tests): an exact
 //     radix select over the whole input by a cooperative grid (k_tail with
 //     exact_only): 8-bit digits of the key image from the top, then of the
@@ -19,6 +21,7 @@
 #include "tk_device.hpp"
 #include "tk_internal.hpp"
 #include "tk_plan.hpp"
+#include "tk_rank.hpp"
 #include "tk_select.hpp"
 #include "tk_src.hpp"
 
@@ -91,6 +94,14 @@ __global__ __launch_bounds__(1024) void k_small(const typename Key<KT>::Raw* key
   __shared__ uint32_t ws[NT / 64];
   const InputSrc<KT, RT> src{keys, rids, dmask};
   lds_select_sort<KT, RT, NT>(src, n, k_eff, dmask, out_keys, out_rids, t, red, ws);
+}
+
+// ---- kernel: whole query ranked across workgroups (n <= LDS capacity) ----------------------
+
+template <int KT, int RT>
+__global__ __launch_bounds__(RANK_NT) void k_rsmall(TailArgs1 a) {
+  __shared__ __align__(16) unsigned char smem[rank_smem_bytes<KT, RT>()];
+  rank_tail_body<KT, RT, true>(a, smem);
 }
 
 // ---- kernel 4: tail (cooperative) -----------------------------------------------------------
@@ -467,6 +478,16 @@ int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, i
   const U dmask = order == TK_ASC ? (U)~(U)0 : (U)0;
   constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
   if (n <= CAP && !tun.force_exact) {
+    if (tun.rank_tail && n <= RANK_CMAX) {
+      // ranked over the input by several workgroups; the header reports the path
+      // when the caller passed a workspace
+      QHead* h = ws && ws_bytes >= HEADER_BYTES && !((uintptr_t)ws & 255u)
+                     ? &ws_ptr<Header>(ws, 0)->q : nullptr;
+      const TailArgs1 ta{keys, rids, n, (uint64_t)dmask, h, nullptr, nullptr, 0, nullptr, nullptr,
+                         nullptr, nullptr, k_eff, out_keys, out_rids, TAIL_INPUT, 0};
+      hipLaunchKernelGGL((k_rsmall<KT, RT>), dim3(rank_grid(k_eff)), dim3(RANK_NT), 0, st, ta);
+      return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
+    }
     hipLaunchKernelGGL((k_small<KT, RT>), dim3(1), dim3(1024), 0, st, (const Raw*)keys,
                        (const R*)rids, (uint32_t)n, (uint32_t)k_eff, dmask, out_keys, out_rids);
     return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;

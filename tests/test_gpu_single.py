@@ -273,3 +273,34 @@ def test_repeated_rowids_identical_pairs():
                 assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"k={k} mode={mode} {order}")
             finally:
                 tk.set_tuning(tail_mode=1)
+
+
+def test_small_query_paths():
+    """Queries within one LDS tile are ranked across workgroups over the input
+    (path 7); tail_mode=2 keeps them in one workgroup; both equal the oracle,
+    including ties and the smallest sizes."""
+    import torch
+    rng = np.random.default_rng(77)
+    cases = [("float32", 5000, 1000, "desc"), ("int32", 16384, 2048, "asc"), ("int64", 8192, 300, "desc"),
+             ("float32", 3, 2, "asc"), ("int32", 1000, 1000, "desc"), ("int64", 100, 1, "asc")]
+    for dtype, n, k, order in cases:
+        keys = inputgen.generate(KINDS[dtype], 90 + n, n)
+        if dtype == "int32":
+            keys = (keys % 97).astype(np.int32)  # heavy ties
+        kd = to_dev(keys)
+        rdt = np.uint64 if dtype == "int64" else np.uint32
+        rids = rng.permutation(n).astype(rdt)
+        exp = oracle.topk(keys, rids, k, order_code(order))
+        for mode in (1, 2):
+            try:
+                tk.set_tuning(tail_mode=mode)
+                ws = tk.new_workspace(n, k, tk.key_code(keys.dtype), tk.rid_code(np.dtype(rdt)))
+                ok, orr = tk.topk(kd, k, rowids=to_dev(rids), order=order, workspace=ws)
+                torch.cuda.synchronize()
+                info = tk.query_info(ws)
+                say(f"{dtype} n={n} k={k} {order} tail_mode={mode}: {info}")
+                if mode == 1:
+                    assert info["path"] == 7
+                assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"{dtype} n={n} k={k} mode={mode}")
+            finally:
+                tk.set_tuning(tail_mode=1)
