@@ -135,6 +135,7 @@ __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, u
 // survivors number thousands.  A stage that fills up sends the rest straight
 // to the buffer (one atomic per wave).
 constexpr uint32_t FILT_STAGE = 1024;
+static_assert(FILT_STAGE % FILT_NT == 0, "the final append covers the stage in whole rounds");
 
 template <typename U, typename R>
 struct SurvStage {
@@ -147,7 +148,7 @@ struct SurvStage {
 
 template <typename U, typename R>
 __device__ __forceinline__ void stage_survivor(bool pass, U kk, R ff, SurvStage<U, R>& st, QHead* h,
-                                               U* sk, R* sf, uint64_t cap) {
+                                               U* sk, R* sf, uint64_t cap, const R* drids) {
   const uint64_t m = ballot(pass);
   if (m == 0) return;
   const uint32_t leader = (uint32_t)__builtin_ctzll(m);
@@ -170,7 +171,7 @@ __device__ __forceinline__ void stage_survivor(bool pass, U kk, R ff, SurvStage<
     const uint64_t pos = g + lanes_below(ms);
     if (pos < cap) {
       sk[pos] = kk;
-      sf[pos] = ff;
+      sf[pos] = drids ? (R)~drids[ff] : ff;
     }
   }
 }
@@ -276,7 +277,7 @@ __device__ __forceinline__ void load_rowids(const R* p, bool aligned16, R (&out)
 template <typename U, typename R, int VEC>
 __device__ __forceinline__ void stage_vector(const bool (&pass)[VEC], const U (&kk)[VEC],
                                              const R (&ff)[VEC], SurvStage<U, R>& st, QHead* h,
-                                             U* sk, R* sf, uint64_t cap) {
+                                             U* sk, R* sf, uint64_t cap, const R* drids) {
   uint64_t m[VEC];
   uint32_t pre[VEC], tot = 0;
 #pragma unroll
@@ -307,7 +308,7 @@ __device__ __forceinline__ void stage_vector(const bool (&pass)[VEC], const U (&
       const uint64_t pos = g + (p - sb);
       if (pos < cap) {
         sk[pos] = kk[e];
-        sf[pos] = ff[e];
+        sf[pos] = drids ? (R)~drids[ff[e]] : ff[e];
       }
     }
   }
@@ -328,6 +329,12 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
   const R Tf = (R)h->thr_f;
   const R* rids = static_cast<const R*>(a.rids);
   const bool tie_rows = rids != nullptr && h->tie_heavy != 0;
+  // Otherwise, explicit row-ids are looked up once per workgroup at the final
+  // append: the stage holds the survivor's index, so a wave that reaches the
+  // threshold does not wait on a scattered row-id load (needs indices that
+  // fit a row-id)
+  const R* drids = rids != nullptr && !tie_rows && (sizeof(R) == 8 || a.n <= (1ull << 32))
+                       ? rids : nullptr;
   const Raw* keys = static_cast<const Raw*>(a.keys);
   const InputSrc<KT, RT> src{keys, (const R*)a.rids, (U)a.dmask};
   const U dmask = (U)a.dmask;
@@ -394,9 +401,12 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
       } else if (ballot(tie)) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) ff[e] = src.flip(i0 + e);
-      } else {
+      } else if (!drids) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) ff[e] = kk[e] > Tk ? src.flip(i0 + e) : (R)0;
+      } else {  // no key of the wave ties: the key alone decides
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) ff[e] = (R)0;
       }
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
@@ -404,7 +414,11 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
         pv |= pass[e];
       }
       if (ballot(pv) == 0) continue;
-      stage_vector<U, R, VEC>(pass, kk, ff, st, h, sk, sf, a.cap);
+      if (drids) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) ff[e] = (R)(i0 + e);
+      }
+      stage_vector<U, R, VEC>(pass, kk, ff, st, h, sk, sf, a.cap, drids);
     }
   }
   // the head and the remainder (fewer than VEC + TILE keys), one per thread:
@@ -425,19 +439,29 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
         ff = src.flip(i);
         pass = pass || ff >= Tf;
       }
+      if (drids) ff = (R)i;
     }
-    stage_survivor<U, R>(pass, kk, ff, st, h, sk, sf, a.cap);
+    stage_survivor<U, R>(pass, kk, ff, st, h, sk, sf, a.cap, drids);
   }
   // append the stage to the query's survivor buffer
   __syncthreads();
   const uint32_t c = st.cnt < FILT_STAGE ? st.cnt : FILT_STAGE;
   if (threadIdx.x == 0) st.base = c ? atomicAdd(&h->surv_count, (unsigned long long)c) : 0ull;
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < c; j += NT) {
+  constexpr int FL = FILT_STAGE / NT;  // the whole stage's row-id loads in flight at once
+  R fv[FL];
+#pragma unroll
+  for (int q = 0; q < FL; ++q) {
+    const uint32_t j = (uint32_t)q * NT + threadIdx.x;
+    if (j < c) fv[q] = drids ? (R)~drids[st.f[j]] : st.f[j];
+  }
+#pragma unroll
+  for (int q = 0; q < FL; ++q) {
+    const uint32_t j = (uint32_t)q * NT + threadIdx.x;
     const uint64_t pos = st.base + j;
-    if (pos < a.cap) {
+    if (j < c && pos < a.cap) {
       sk[pos] = st.k[j];
-      sf[pos] = st.f[j];
+      sf[pos] = fv[q];
     }
   }
 }
