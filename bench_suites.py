@@ -6,6 +6,8 @@
     python bench_suites.py c4                key-only vs full-row transfer with late materialization
     python bench_suites.py c5                served form: Poisson arrivals, gate on vs always-GPU
     python bench_suites.py crossover         CPU vs GPU time over N (host- and device-resident keys)
+    python bench_suites.py gate              cost-model fit, predicted vs measured break-even N,
+                                             margin sweep of the gate on the serving mixture
     python bench_suites.py e2e               headline query with pinned H2D and D2H included
 
 Each suite prints one JSON object per measurement on stdout.  Every input is
@@ -376,10 +378,10 @@ def suite_c5(a):
     n, k, off = req["n"], req["k"], req["offset"]
     cost = json.loads(a.cost) if a.cost else None
 
-    def run(gate, rate, max_batch, slots, window_us):
+    def run(gate, rate, max_batch, slots, window_us, margin_us=0.0):
         srv = Server(arena_bytes=a.arena_mb << 20, max_batch=max_batch, slots=slots,
-                     window_us=window_us, gate=gate, margin_ms=0.0, cpu_threads=a.cpu_threads,
-                     cost=cost)
+                     window_us=window_us, gate=gate, margin_ms=margin_us * 1e-3,
+                     cpu_threads=a.cpu_threads, cost=cost)
         ids = [srv.add_column(d, h) for d, h in cols]
         # Poisson arrivals: exponential gaps from the recipe's uniforms
         gaps = -np.log1p(-req["u_arr"]) / rate
@@ -413,14 +415,15 @@ def suite_c5(a):
         if a.modes and name not in a.modes:
             continue
         for lam in a.rates:
-            lat, routes, st, bad, span = run(gate, lam, mb, sl, win)
-            emit({"suite": "c5", "mode": name, "rate_qps": lam, "requests": cnt,
-                  "columns": a.columns, "col_rows": col_len,
-                  "achieved_qps": cnt / span, "makespan_s": span,
-                  "lat_p50_ms": pct(lat, 50) * 1e3, "lat_p95_ms": pct(lat, 95) * 1e3,
-                  "lat_p99_ms": pct(lat, 99) * 1e3, "cpu_routed": float(np.mean(routes == 1)),
-                  "stats": st, "oracle_checked": (cnt + a.check_every - 1) // a.check_every,
-                  "oracle_mismatches": bad})
+            for m in (a.margins_us if gate == GATE_COST else [0.0]):
+                lat, routes, st, bad, span = run(gate, lam, mb, sl, win, m)
+                emit({"suite": "c5", "mode": name, "rate_qps": lam, "margin_us": m, "requests": cnt,
+                      "columns": a.columns, "col_rows": col_len,
+                      "achieved_qps": cnt / span, "makespan_s": span,
+                      "lat_p50_ms": pct(lat, 50) * 1e3, "lat_p95_ms": pct(lat, 95) * 1e3,
+                      "lat_p99_ms": pct(lat, 99) * 1e3, "cpu_routed": float(np.mean(routes == 1)),
+                      "stats": st, "oracle_checked": (cnt + a.check_every - 1) // a.check_every,
+                      "oracle_mismatches": bad})
 
 
 # ---- crossover ---------------------------------------------------------------------------------
@@ -452,67 +455,79 @@ def crossover_n(rows, key):
     return best
 
 
-def suite_crossover(a):
-    torch = _torch()
-    import inputgen
-    import oracle
-    import paper_2601_19911_amd as tk
-    from inputgen import native as gen
+class _Point:
+    """CPU and GPU times of one Top-K (N, K) over the first N keys of a seeded
+    column of one dtype: GPU with keys resident in HBM and with keys copied from
+    pinned host memory (launch to results on the host), CPU route on every core
+    of the affinity mask; both results checked against the oracle."""
 
-    dev = torch.device("cuda:0")
-    cores = len(os.sched_getaffinity(0))
-    kinds = {"int32": (inputgen.KIND_U_I32, torch.int32), "int64": (inputgen.KIND_U_I64, torch.int64),
-             "float32": (inputgen.KIND_U_F32, torch.float32)}
-    s = torch.cuda.current_stream()
-    for dt in a.dtypes:
+    def __init__(self, dt, nmax, ks):
+        torch = _torch()
+        import inputgen
+        import paper_2601_19911_amd as tk
+        from inputgen import native as gen
+        kinds = {"int32": (inputgen.KIND_U_I32, torch.int32), "int64": (inputgen.KIND_U_I64, torch.int64),
+                 "float32": (inputgen.KIND_U_F32, torch.float32)}
         kind, tdt = kinds[dt]
-        nmax = 1 << a.max_log2
-        hk = gen.host_fill(kind, inputgen.config_seed(6), nmax)
-        pk = _pinned_copy(hk)
-        dk = torch.empty(nmax, dtype=tdt, device=dev)
-        dk.copy_(pk)
+        self.dt, self.tdt, self.torch, self.tk = dt, tdt, torch, tk
+        self.dev = torch.device("cuda:0")
+        self.cores = len(os.sched_getaffinity(0))
+        self.hk = gen.host_fill(kind, inputgen.config_seed(6), nmax)
+        self.pk = _pinned_copy(self.hk)
+        self.dk = torch.empty(nmax, dtype=tdt, device=self.dev)
+        self.dk.copy_(self.pk)
+        kmax = max(ks)
+        self.ws = tk.new_workspace(nmax, kmax, tk.key_code(tdt), tk.TK_RID_U32, device=self.dev)
+        self.ok = torch.empty(kmax, dtype=tdt, device=self.dev)
+        self.orr = torch.empty(kmax, dtype=torch.uint32, device=self.dev)
+        self.hok = torch.empty(kmax, dtype=tdt, pin_memory=True)
+        self.hor = torch.empty(kmax, dtype=torch.int32, pin_memory=True)
+        self.s = torch.cuda.current_stream()
+
+    def __call__(self, N, K):
+        import oracle
+        torch, tk = self.torch, self.tk
+        ke = min(K, N)
+        reps = 31 if N <= (1 << 22) else 5
+
+        def gpu(resident):
+            ts = []
+            for r in range(reps + 2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if not resident:
+                    self.dk[:N].copy_(self.pk[:N], non_blocking=True)
+                tk.topk(self.dk[:N], K, out_keys=self.ok[:ke], out_rowids=self.orr[:ke],
+                        workspace=self.ws, stream=self.s)
+                self.hok[:ke].copy_(self.ok[:ke], non_blocking=True)
+                self.hor[:ke].copy_(self.orr[:ke].view(torch.int32), non_blocking=True)
+                torch.cuda.synchronize()
+                if r >= 2:
+                    ts.append(time.perf_counter() - t0)
+            return float(np.median(ts))
+
+        g_res, g_host = gpu(True), gpu(False)
+        ek, er = oracle.topk(self.hk[:N], None, K, oracle.DESC, rid_dtype=np.uint32)
+        match = same(self.hok[:ke].numpy(), self.hor[:ke].numpy().view(np.uint32), ek, er)
+        cts = []
+        for r in range(reps + 1):
+            t0 = time.perf_counter()
+            ck, cr = tk.cpu_topk(self.hk[:N], K, nthreads=self.cores)
+            if r:
+                cts.append(time.perf_counter() - t0)
+        cpu_match = same(ck, cr, ek, er)
+        return {"dtype": self.dt, "k": K, "n": N, "gpu_resident_s": g_res, "gpu_host_keys_s": g_host,
+                "cpu_all_cores_s": float(np.median(cts)), "cpu_threads": self.cores, "reps": reps,
+                "oracle_match": bool(match), "cpu_match": bool(cpu_match)}
+
+
+def suite_crossover(a):
+    for dt in a.dtypes:
+        pt = _Point(dt, 1 << a.max_log2, a.ks)
         rows = []
         for K in a.ks:
-            ws = tk.new_workspace(nmax, K, tk.key_code(tdt), tk.TK_RID_U32, device=dev)
-            ok = torch.empty(K, dtype=tdt, device=dev)
-            orr = torch.empty(K, dtype=torch.uint32, device=dev)
-            hok = torch.empty(K, dtype=tdt, pin_memory=True)
-            hor = torch.empty(K, dtype=torch.int32, pin_memory=True)
             for lg in range(a.min_log2, a.max_log2 + 1):
-                N = 1 << lg
-                ke = min(K, N)
-                reps = 31 if N <= (1 << 22) else 5
-
-                def gpu(resident):
-                    ts = []
-                    for r in range(reps + 2):
-                        torch.cuda.synchronize()
-                        t0 = time.perf_counter()
-                        if not resident:
-                            dk[:N].copy_(pk[:N], non_blocking=True)
-                        tk.topk(dk[:N], K, out_keys=ok[:ke], out_rowids=orr[:ke], workspace=ws,
-                                stream=s)
-                        hok[:ke].copy_(ok[:ke], non_blocking=True)
-                        hor[:ke].copy_(orr[:ke].view(torch.int32), non_blocking=True)
-                        torch.cuda.synchronize()
-                        if r >= 2:
-                            ts.append(time.perf_counter() - t0)
-                    return float(np.median(ts))
-
-                g_res, g_host = gpu(True), gpu(False)
-                ek, er = oracle.topk(hk[:N], None, K, oracle.DESC, rid_dtype=np.uint32)
-                match = same(hok[:ke].numpy(), hor[:ke].numpy().view(np.uint32), ek, er)
-                cts = []
-                for r in range(reps + 1):
-                    t0 = time.perf_counter()
-                    ck, cr = tk.cpu_topk(hk[:N], K, nthreads=cores)
-                    if r:
-                        cts.append(time.perf_counter() - t0)
-                cpu_match = same(ck, cr, ek, er)
-                row = {"suite": "crossover", "dtype": dt, "k": K, "n": N, "gpu_resident_s": g_res,
-                       "gpu_host_keys_s": g_host, "cpu_all_cores_s": float(np.median(cts)),
-                       "cpu_threads": cores, "reps": reps, "oracle_match": bool(match),
-                       "cpu_match": bool(cpu_match)}
+                row = dict(suite="crossover", **pt(1 << lg, K))
                 rows.append(row)
                 emit(row)
             ks_rows = [r for r in rows if r["k"] == K]
@@ -520,11 +535,98 @@ def suite_crossover(a):
                   "crossover_n_resident": crossover_n(ks_rows, "gpu_resident_s"),
                   "crossover_n_host_keys": crossover_n(ks_rows, "gpu_host_keys_s")})
         emit({"suite": "crossover", "dtype": dt, "fit": fit_costs(rows)})
+        del pt
+
+
+# ---- gate: break-even prediction and margin sensitivity -------------------------------------
+
+def predicted_break_even(cost, k, margin_s=0.0):
+    """N at which the gate's estimated saving, C_cpu - C_gpu, reaches the margin
+    (the cost models are linear in N): the smallest offloaded N."""
+    slope = cost["cpu_a"] - cost["gpu_a"]
+    if slope <= 0:
+        return None
+    rest = (cost["gpu_b"] * k + cost["gpu_c"]) - (cost["cpu_b"] * k * np.log2(k + 1.0) + cost["cpu_c"])
+    return max((margin_s + rest) / slope, 1.0)
+
+
+def gate_route_gpu(cost, n, k, margin_s=0.0):
+    """The gate's decision for requests (n, k): True where offloaded."""
+    n = np.asarray(n, dtype=np.float64)
+    k = np.minimum(np.asarray(k, dtype=np.float64), n)
+    c_cpu = cost["cpu_a"] * n + cost["cpu_b"] * k * np.log2(k + 1.0) + cost["cpu_c"]
+    c_gpu = cost["gpu_a"] * n + cost["gpu_b"] * k + cost["gpu_c"]
+    return c_cpu - c_gpu > margin_s
+
+
+def measured_break_even(pt, k, rows, steps):
+    """Smallest N from which the resident GPU route beats the CPU route: the
+    bracketing pair of the power-of-two sweep, then `steps` bisections in log N
+    (each midpoint measured like the sweep)."""
+    rows = sorted(rows, key=lambda r: r["n"])
+    hi = crossover_n(rows, "gpu_resident_s")
+    if hi is None or hi == rows[0]["n"]:
+        return hi, []
+    lo = hi // 2
+    extra = []
+    for _ in range(steps):
+        mid = int(round(np.sqrt(float(lo) * float(hi))))
+        if mid <= lo or mid >= hi:
+            break
+        r = pt(mid, k)
+        extra.append(r)
+        if r["gpu_resident_s"] < r["cpu_all_cores_s"]:
+            hi = mid
+        else:
+            lo = mid
+    return float(np.sqrt(float(lo) * float(hi))), extra
+
+
+def suite_gate(a):
+    """Break-even validation: fit the gate's cost models on the power-of-two
+    sweep of every dtype and K (N <= 2^fit_log2), predict each break-even N,
+    measure it by bisection, and report the relative error.  Then the margin
+    sweep: the serving mixture at one arrival rate under the fitted gate, one
+    run per margin (offload share predicted from the model and observed,
+    latency, throughput)."""
+    fit_rows, be = [], []
+    for dt in a.dtypes:
+        pt = _Point(dt, 1 << a.max_log2, a.ks)
+        for K in a.ks:
+            rows = []
+            for lg in range(a.min_log2, a.max_log2 + 1):
+                row = dict(suite="gate", **pt(1 << lg, K))
+                rows.append(row)
+                emit(row)
+            meas, extra = measured_break_even(pt, K, rows, a.bisect)
+            for r in extra:
+                emit(dict(suite="gate", bisect=True, **r))
+            fit_rows += [r for r in rows if r["n"] <= (1 << a.fit_log2)]
+            be.append({"dtype": dt, "k": K, "measured": meas})
+        del pt
+    cost = fit_costs(fit_rows)
+    emit({"suite": "gate", "fit": cost, "fit_points": len(fit_rows)})
+    for b in be:
+        pred = predicted_break_even(cost, b["k"])
+        err = None if (pred is None or b["measured"] is None) else abs(pred - b["measured"]) / b["measured"]
+        emit({"suite": "gate", "dtype": b["dtype"], "k": b["k"], "break_even_measured": b["measured"],
+              "break_even_predicted": pred, "rel_error": err})
+    # margin sweep on the serving mixture, under the fitted gate
+    import inputgen
+    req = inputgen.serving_requests(a.requests, col_len=1 << a.col_log2)
+    for m in a.margins_us:
+        emit({"suite": "gate", "margin_us": m,
+              "predicted_gpu_share": float(np.mean(gate_route_gpu(cost, req["n"], req["k"], m * 1e-6))),
+              "break_even_by_k": {str(k): predicted_break_even(cost, k, m * 1e-6)
+                                  for k in (10, 100, 1000, 10000)}})
+    a.cost = json.dumps(cost)
+    a.modes = ["cost_gate"]
+    suite_c5(a)
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("suite", choices=["c2", "c3", "c4", "c5", "crossover", "e2e"])
+    ap.add_argument("suite", choices=["c2", "c3", "c4", "c5", "crossover", "gate", "e2e"])
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--q", type=int, default=4096)
     ap.add_argument("--n-hi-log2", type=float, default=24.0)
@@ -548,9 +650,13 @@ def main():
     ap.add_argument("--ks", type=int, nargs="+", default=[10, 100, 1000])
     ap.add_argument("--min-log2", type=int, default=8)
     ap.add_argument("--max-log2", type=int, default=26)
+    ap.add_argument("--margins-us", type=float, nargs="+", default=[0.0],
+                    help="c5, gate: margins of the cost gate, microseconds")
+    ap.add_argument("--bisect", type=int, default=4, help="gate: bisections of each break-even")
+    ap.add_argument("--fit-log2", type=int, default=22, help="gate: largest N of the model fit")
     a = ap.parse_args()
     {"c2": suite_c2, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5, "crossover": suite_crossover,
-     "e2e": suite_e2e}[a.suite](a)
+     "gate": suite_gate, "e2e": suite_e2e}[a.suite](a)
 
 
 if __name__ == "__main__":

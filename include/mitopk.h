@@ -193,7 +193,7 @@ typedef struct {
   int32_t gate;         /* 0 always GPU, 1 cost gate, 2 always CPU */
   double margin_ms;     /* gate margin */
   int32_t cpu_threads;  /* CPU-route workers; 0: 4 */
-  /* cost model, seconds: C_cpu = cpu_a*N + cpu_b*K*log2(K+1) + cpu_c,
+  /* cost model, seconds, K = min(k, N): C_cpu = cpu_a*N + cpu_b*K*log2(K+1) + cpu_c,
    * C_gpu = gpu_a*N + gpu_b*K + gpu_c.  All six 0: a fit measured on MI355X
    * with 16 host threads (cpu 1.79e-10, 1.26e-8, 4.36e-5; gpu 0, 1.48e-8,
    * 5.30e-5), which sends device-resident requests below N ~ 16K to the CPU */

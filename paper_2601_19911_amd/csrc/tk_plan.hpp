@@ -17,6 +17,10 @@ constexpr uint32_t SAMPLE_CHUNK = 16;        // contiguous keys per sample chunk
 constexpr uint32_t SAMPLE_PER_BLOCK = 2048;  // sample keys per local-select block
 constexpr uint32_t SAMPLE_FINAL_MAX = 2048;  // candidates of the final select (registers of a
                                              // filter workgroup)
+// Largest N sampled with K > N / 16: the survivors (up to ~N / 2) then stay
+// below 2^20, so that no bucket of the large-K tail (128 or 256 per octave)
+// outgrows one LDS tile
+constexpr uint64_t SAMPLE_WIDE_K_MAX_N = 1ull << 20;
 
 struct SamplePlan {
   bool fast = false;     // sample -> filter -> tail; else exact radix select
@@ -45,15 +49,18 @@ struct Tuning {
 // as large as allowed while the final select still fits one workgroup.
 inline SamplePlan plan_sample(uint64_t n, uint64_t k_eff, const Tuning& t) {
   SamplePlan p;
-  if (t.force_exact || k_eff == 0 || n < (1ull << t.min_sample_log2) * 16 || k_eff * 16 > n)
-    return p;
+  if (t.force_exact || k_eff == 0 || n < (1ull << t.min_sample_log2) * 16) return p;
+  // K beyond N / 16: a sample still bounds the survivors to ~K when N is
+  // moderate; past SAMPLE_WIDE_K_MAX_N (or K beyond N / 2) the exact select
+  // over the input is used instead
+  if (k_eff * 16 > n && (n > SAMPLE_WIDE_K_MAX_N || k_eff * 2 > n)) return p;
   for (int lg = (int)t.max_sample_log2; lg >= (int)t.min_sample_log2; --lg) {
     const uint64_t S = 1ull << lg;
     if (S * 16 > n) continue;
     const double m = (double)k_eff * (double)S / (double)n;
     const uint64_t r1 = (uint64_t)ceil(m + t.sample_sigma * sqrt(m) + 3.0);
     const uint64_t blocks = S / SAMPLE_PER_BLOCK;
-    if (r1 > 256 || r1 * blocks > SAMPLE_FINAL_MAX) continue;
+    if (r1 > SAMPLE_PER_BLOCK || r1 * blocks > SAMPLE_FINAL_MAX) continue;
     p.fast = true;
     p.S = (uint32_t)S;
     p.blocks = (uint32_t)blocks;

@@ -442,7 +442,8 @@ extern "C" int tk_server_submit(tk_server* s, uint32_t col, uint64_t offset, uin
   int route = 0;
   if (s->cfg.gate == 2) route = 1;
   else if (s->cfg.gate == 1 && c.h_keys) {
-    const double saving = cpu_cost(s->cfg, n, k) - gpu_cost(s->cfg, n, k);
+    const uint32_t ke = (uint64_t)k < n ? k : (uint32_t)n;  // the work is min(k, n) results
+    const double saving = cpu_cost(s->cfg, n, ke) - gpu_cost(s->cfg, n, ke);
     route = saving > s->cfg.margin_ms * 1e-3 ? 0 : 1;
   }
   if (route == 1 && !c.h_keys) route = 0;

@@ -1,9 +1,9 @@
 // Single-query entry point of key-only Top-K (ordering primitive, paper
 // sec. III-A) and the two paths that do not go through the engine:
-//   - queries that fit one LDS tile: ranked across workgroups over the whole
-//     input (k_rsmall, tk_rank.hpp), or, as a tuning choice, by one
-//     workgroup (k_small): the keys are loaded once, the best K found by
-//     radix select and bitonic-sorted in LDS;
+//   - queries that fit one LDS tile: for K up to 2048 ranked across
+//     workgroups over the whole input (k_rsmall, tk_rank.hpp); for larger K,
+//     or as a tuning choice, by one workgroup (k_small): the keys are loaded
+//     once, the best K found by radix select and bitonic-sorted in LDS;
 //   - queries whose K is a large share of N (or forced, for tests): an exact
 //     radix select over the whole input by a cooperative grid (k_tail with
 //     exact_only): 8-bit digits of the key image from the top, then of the
@@ -478,7 +478,7 @@ int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, i
   const U dmask = order == TK_ASC ? (U)~(U)0 : (U)0;
   constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
   if (n <= CAP && !tun.force_exact) {
-    if (tun.rank_tail && n <= RANK_CMAX) {
+    if (tun.rank_tail && n <= RANK_CMAX && !bucket_tail_for(k_eff)) {
       // ranked over the input by several workgroups; the header reports the path
       // when the caller passed a workspace
       QHead* h = ws && ws_bytes >= HEADER_BYTES && !((uintptr_t)ws & 255u)
@@ -510,7 +510,12 @@ int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, i
   TailArgs a{keys, rids, n, (uint64_t)dmask, h, cand_k, cand_f, tmp_k, tmp_f, k_eff, out_keys,
              out_rids, 1};
   void* args[] = {&a};
-  const int grid = coop_grid_tail<KT, RT>(dev);
+  // one workgroup per 16 Ki keys, up to what the device holds at once: every
+  // digit round ends in a grid barrier whose cost grows with the grid, so a
+  // small input is not spread over the whole device
+  const uint64_t want = (n + 16383) / 16384;
+  const int full = coop_grid_tail<KT, RT>(dev);
+  const int grid = want < (uint64_t)full ? (int)want : full;
   if (hipLaunchCooperativeKernel((const void*)k_tail<KT, RT>, dim3(grid), dim3(1024), args, 0, st) !=
       hipSuccess)
     return TK_EHIP;

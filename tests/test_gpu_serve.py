@@ -124,3 +124,38 @@ def _alone_and_in_mix(seed):
     assert_same(a[0], a[1], ek, er, what="alone")
     assert srv.stats()["batches"] >= 2
     srv.close()
+
+
+@pytest.mark.parametrize("margin_us", [0.0, 40.0])
+def test_gate_routes_follow_cost_model(margin_us):
+    """The gate offloads exactly the requests whose modelled saving,
+    C_cpu - C_gpu at K = min(k, N), exceeds the margin (paper sec. II-B), and
+    either route returns the oracle's result."""
+    import torch
+    from bench_suites import gate_route_gpu
+    ncol = 1 << 20
+    cols = _columns(ncol)
+    host = [h for _, h in cols]
+    cost = {"cpu_a": 1.8e-10, "cpu_b": 1.3e-8, "cpu_c": 4.4e-5, "gpu_a": 0.0, "gpu_b": 1.5e-8,
+            "gpu_c": 5.3e-5}
+    srv = Server(arena_bytes=256 << 20, max_batch=32, slots=2, gate=GATE_COST, margin_ms=margin_us * 1e-3,
+                 cost=cost)
+    ids = [srv.add_column(d, h) for d, h in cols]
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11 + int(margin_us))
+    reqs = []
+    for _ in range(160):
+        n = int(2 ** rng.uniform(8, 20))
+        reqs.append((int(rng.integers(0, 3)), int(rng.integers(0, ncol - n + 1)), n,
+                     int(rng.choice([1, 10, 100, 1000, 10000])), int(rng.integers(0, 2))))
+    want_gpu = gate_route_gpu(cost, [r[2] for r in reqs], [r[3] for r in reqs], margin_us * 1e-6)
+    say(f"gate margin {margin_us} us: {int(want_gpu.sum())} of {len(reqs)} requests modelled to offload")
+    rid = [srv.submit(ids[c], off, n, k, o) for (c, off, n, k, o) in reqs]
+    srv.drain()
+    for i, ((c, off, n, k, o), r) in enumerate(zip(reqs, rid)):
+        ok, orr, info = srv.result(r, c, min(k, n))
+        assert info.route == (0 if want_gpu[i] else 1), f"request n={n} k={k} routed {info.route}"
+        ek, er = _expect(host, c, off, n, k, o)
+        assert_same(ok, orr, ek, er, what=f"gated n={n} k={k} o={o} route={info.route}")
+    assert 0 < int(want_gpu.sum()) < len(reqs)
+    srv.close()

@@ -282,7 +282,9 @@ def test_small_query_paths():
     import torch
     rng = np.random.default_rng(77)
     cases = [("float32", 5000, 1000, "desc"), ("int32", 16384, 2048, "asc"), ("int64", 8192, 300, "desc"),
-             ("float32", 3, 2, "asc"), ("int32", 1000, 1000, "desc"), ("int64", 100, 1, "asc")]
+             ("float32", 3, 2, "asc"), ("int32", 1000, 1000, "desc"), ("int64", 100, 1, "asc"),
+             # K past the ranked form's reach: one workgroup in either mode
+             ("int32", 8192, 10000, "desc"), ("float32", 16384, 2049, "asc"), ("int64", 8192, 5000, "desc")]
     for dtype, n, k, order in cases:
         keys = inputgen.generate(KINDS[dtype], 90 + n, n)
         if dtype == "int32":
@@ -299,8 +301,44 @@ def test_small_query_paths():
                 torch.cuda.synchronize()
                 info = tk.query_info(ws)
                 say(f"{dtype} n={n} k={k} {order} tail_mode={mode}: {info}")
-                if mode == 1:
+                if mode == 1 and min(k, n) <= 2048:
                     assert info["path"] == 7
                 assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"{dtype} n={n} k={k} mode={mode}")
             finally:
                 tk.set_tuning(tail_mode=1)
+
+
+def _run_path_cases(cases, want_path, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    for dtype, n, k, order in cases:
+        keys = inputgen.generate(KINDS[dtype], seed + n, n)
+        if dtype == "int32" and order == "desc":
+            keys = (keys % 1009).astype(np.int32)  # ties across the boundary
+        rdt = np.uint64 if dtype == "int64" else np.uint32
+        rids = rng.permutation(n).astype(rdt)
+        exp = oracle.topk(keys, rids, k, order_code(order))
+        ws = tk.new_workspace(n, k, tk.key_code(keys.dtype), tk.rid_code(np.dtype(rdt)))
+        ok, orr = tk.topk(to_dev(keys), k, rowids=to_dev(rids), order=order, workspace=ws)
+        torch.cuda.synchronize()
+        info = tk.query_info(ws)
+        say(f"{dtype} n={n} k={k} {order}: {info}")
+        assert info["path"] == want_path and info["status"] == 0
+        assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"{dtype} n={n} k={k} {order}")
+
+
+def test_exact_path_small_grids():
+    """Inputs past one LDS tile that the sample cannot serve (N below 16 sample
+    chunks of 2048 keys, K above N / 2, or K above N / 16 at N past 2^20) take
+    the exact radix select over the input on a grid sized by N (path 5)."""
+    _run_path_cases([("int32", 23170, 10, "desc"), ("float32", 30048, 1000, "asc"),
+                     ("int64", 20000, 3000, "asc"), ("int32", 65536, 40000, "desc"),
+                     ("float32", 1 << 22, 1 << 19, "desc"), ("int64", 1 << 21, 1 << 20, "asc")], 5, seed=300)
+
+
+def test_wide_k_sampled():
+    """K between N / 16 and N / 2 at N up to 2^20: the sampled path with the
+    bucketed tail (path 6), equal to the oracle."""
+    _run_path_cases([("int32", 65536, 10000, "desc"), ("float32", 131072, 10000, "asc"),
+                     ("int64", 100000, 7000, "desc"), ("float32", 1 << 20, 1 << 17, "desc"),
+                     ("int64", 1 << 20, 1 << 19, "asc")], 6, seed=400)
