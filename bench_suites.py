@@ -428,17 +428,21 @@ def suite_c5(a):
 
 # ---- crossover ---------------------------------------------------------------------------------
 
-def fit_costs(rows):
+def fit_costs(rows, relative=False):
     """Least-squares cost models of the gate (reading: C_cpu = a N + b K log2(K+1) + c,
-    C_gpu = a N + b K + c), from crossover rows of one dtype."""
+    C_gpu = a N + b K + c), from crossover rows.  relative: residuals taken
+    relative to the measured time, so that the small-N points near the
+    break-even weigh as much as the large ones."""
     N = np.array([r["n"] for r in rows], dtype=np.float64)
     K = np.array([min(r["k"], r["n"]) for r in rows], dtype=np.float64)
     cpu = np.array([r["cpu_all_cores_s"] for r in rows])
     gpu = np.array([r["gpu_resident_s"] for r in rows])
+    wc = 1.0 / cpu if relative else np.ones_like(cpu)
+    wg = 1.0 / gpu if relative else np.ones_like(gpu)
     A = np.stack([N, K * np.log2(K + 1), np.ones_like(N)], 1)
-    ca = np.linalg.lstsq(A, cpu, rcond=None)[0]
+    ca = np.linalg.lstsq(A * wc[:, None], cpu * wc, rcond=None)[0]
     B = np.stack([N, K, np.ones_like(N)], 1)
-    ga = np.linalg.lstsq(B, gpu, rcond=None)[0]
+    ga = np.linalg.lstsq(B * wg[:, None], gpu * wg, rcond=None)[0]
     return {"cpu_a": float(ca[0]), "cpu_b": float(ca[1]), "cpu_c": float(ca[2]),
             "gpu_a": float(ga[0]), "gpu_b": float(ga[1]), "gpu_c": float(ga[2])}
 
@@ -584,8 +588,9 @@ def measured_break_even(pt, k, rows, steps):
 
 def suite_gate(a):
     """Break-even validation: fit the gate's cost models on the power-of-two
-    sweep of every dtype and K (N <= 2^fit_log2), predict each break-even N,
-    measure it by bisection, and report the relative error.  Then the margin
+    sweep of every dtype and K (2^fit_lo_log2 <= N <= 2^fit_log2, relative
+    residuals), predict each break-even N, measure it by bisection, and report
+    the relative error.  Then the margin
     sweep: the serving mixture at one arrival rate under the fitted gate, one
     run per margin (offload share predicted from the model and observed,
     latency, throughput)."""
@@ -601,10 +606,10 @@ def suite_gate(a):
             meas, extra = measured_break_even(pt, K, rows, a.bisect)
             for r in extra:
                 emit(dict(suite="gate", bisect=True, **r))
-            fit_rows += [r for r in rows if r["n"] <= (1 << a.fit_log2)]
+            fit_rows += [r for r in rows if (1 << a.fit_lo_log2) <= r["n"] <= (1 << a.fit_log2)]
             be.append({"dtype": dt, "k": K, "measured": meas})
         del pt
-    cost = fit_costs(fit_rows)
+    cost = fit_costs(fit_rows, relative=True)
     emit({"suite": "gate", "fit": cost, "fit_points": len(fit_rows)})
     for b in be:
         pred = predicted_break_even(cost, b["k"])
@@ -653,7 +658,8 @@ def main():
     ap.add_argument("--margins-us", type=float, nargs="+", default=[0.0],
                     help="c5, gate: margins of the cost gate, microseconds")
     ap.add_argument("--bisect", type=int, default=4, help="gate: bisections of each break-even")
-    ap.add_argument("--fit-log2", type=int, default=22, help="gate: largest N of the model fit")
+    ap.add_argument("--fit-log2", type=int, default=20, help="gate: largest N of the model fit")
+    ap.add_argument("--fit-lo-log2", type=int, default=10, help="gate: smallest N of the model fit")
     a = ap.parse_args()
     {"c2": suite_c2, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5, "crossover": suite_crossover,
      "gate": suite_gate, "e2e": suite_e2e}[a.suite](a)

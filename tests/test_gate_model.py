@@ -73,3 +73,10 @@ def test_bisection_brackets_the_true_crossover():
     assert len(extra) == len(calls) == 6
     # six halvings of one octave in log N: within 2^(1/128) of the truth
     assert abs(np.log2(meas) - np.log2(n_true)) <= 1.0 / 64
+
+
+def test_relative_fit_recovers_noise_free_models():
+    rows = [_row(1 << lg, k) for k in (10, 100, 1000, 10000) for lg in range(10, 21)]
+    got = fit_costs(rows, relative=True)
+    for key, v in TRUE.items():
+        assert got[key] == pytest.approx(v, rel=1e-6, abs=1e-15), key
