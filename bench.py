@@ -27,7 +27,7 @@ def parse(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--k", type=int, default=1000)
-    ap.add_argument("--dtype", choices=["float32", "int32", "int64"], default="float32")
+    ap.add_argument("--dtype", choices=["float32", "int32", "int64", "float64"], default="float32")
     ap.add_argument("--dist", choices=["uniform", "zipf", "sorted"], default="uniform")
     ap.add_argument("--order", choices=["desc", "asc"], default="desc")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -82,12 +82,14 @@ def measure(args) -> dict:
     torch.cuda.set_device(dev)
     n = 1 << args.log2n
     k = args.k
-    dt = {"float32": torch.float32, "int32": torch.int32, "int64": torch.int64}[args.dtype]
+    dt = {"float32": torch.float32, "int32": torch.int32, "int64": torch.int64,
+          "float64": torch.float64}[args.dtype]
     kind = {("float32", "uniform"): inputgen.KIND_U_F32, ("int32", "uniform"): inputgen.KIND_U_I32,
             ("int64", "uniform"): inputgen.KIND_U_I64, ("float32", "zipf"): inputgen.KIND_ZIPF_F32,
             ("int64", "zipf"): inputgen.KIND_ZIPF_I64, ("int32", "zipf"): inputgen.KIND_ZIPF_I32,
             ("float32", "sorted"): inputgen.KIND_SORTED_F32,
-            ("int64", "sorted"): inputgen.KIND_SORTED_I64}[(args.dtype, args.dist)]
+            ("int64", "sorted"): inputgen.KIND_SORTED_I64,
+            ("float64", "uniform"): inputgen.KIND_U_F64}[(args.dtype, args.dist)]
     seed = inputgen.config_seed(2)
     stream = torch.cuda.current_stream()
     keys = torch.empty(n, dtype=dt, device=dev)
@@ -194,7 +196,7 @@ def measure(args) -> dict:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"float32": "f32", "int32": "i32", "int64": "i64"}[args.dtype],
+        "dtype": {"float32": "f32", "int32": "i32", "int64": "i64", "float64": "f64"}[args.dtype],
         "data": "synthetic",
         "config": {"workload": f"single Top-K query, N=2^{args.log2n} {args.dtype} keys "
                                f"({args.dist}) + {'uint64' if rid_t == torch.uint64 else 'uint32'} "

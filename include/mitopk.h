@@ -13,7 +13,8 @@
  *     TK_DESC: key_a > key_b, or key_a == key_b and rowid_a < rowid_b
  *     TK_ASC:  key_a < key_b, or key_a == key_b and rowid_a < rowid_b
  *   with numeric order for int32/int64 keys and IEEE 754-2019 totalOrder
- *   (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN) for float32 keys.
+ *   (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN) for float32 and
+ *   float64 keys (float64 is the key type of the paper's workload, sec. V-A).
  *   The output is the first K_eff = min(k, n) pairs in that order, best
  *   first: out_keys[j] holds the original key bits, out_rowids[j] its row-id.
  *
@@ -42,7 +43,7 @@
 extern "C" {
 #endif
 
-typedef enum { TK_KEY_I32 = 0, TK_KEY_I64 = 1, TK_KEY_F32 = 2 } tk_key_t;
+typedef enum { TK_KEY_I32 = 0, TK_KEY_I64 = 1, TK_KEY_F32 = 2, TK_KEY_F64 = 3 } tk_key_t;
 typedef enum { TK_RID_U32 = 0, TK_RID_U64 = 1 } tk_rid_t;
 typedef enum { TK_DESC = 0, TK_ASC = 1 } tk_order_t;
 
@@ -63,7 +64,7 @@ size_t tk_workspace_size(uint64_t n, uint64_t k, int key_type, int rid_type);
 
 /* One Top-K query (paper sec. III-A): selects the best min(k, n) (key,
  * row-id) pairs and writes them best first.
- *   keys        device array of n keys (int32, int64 or float32 bits)
+ *   keys        device array of n keys (int32, int64, float32 or float64 bits)
  *   rowids      device array of n row-ids of rid_type, or NULL (row-id = index)
  *   out_keys    device array of >= min(k, n) keys, or NULL (row-ids only)
  *   out_rowids  device array of >= min(k, n) row-ids of rid_type, or NULL

@@ -52,6 +52,7 @@ KIND_IOTA_U32 = 7
 KIND_IOTA_U64 = 8
 KIND_PAYLOAD_F64 = 9
 KIND_ZIPF_I32 = 10
+KIND_U_F64 = KIND_PAYLOAD_F64  # uniform float64 keys in [0, 1): the same 2^-53 grid
 
 KIND_DTYPE = {
     KIND_U_I32: np.int32,

@@ -9,7 +9,7 @@ and the library never imports it.
   template of sec. V-B): sort the (key, row-id) pairs by key (descending or
   ascending), ties by ascending row-id, keep the first min(K, N).
 * :func:`brute_topk` is a pure-Python ``sorted`` of the same definition for
-  tiny inputs; it orders float32 keys through the classic sign-flip map of the
+  tiny inputs; it orders float keys through the classic sign-flip map of the
   bit pattern, an independent formulation of IEEE 754 totalOrder.
 * :func:`check_invariants` tests the properties every correct result has at
   any size.
@@ -28,7 +28,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.cpp")
 LIB = os.path.join(HERE, "liboracle.so")
 
-KEY_CODE = {np.dtype(np.int32): 0, np.dtype(np.int64): 1, np.dtype(np.float32): 2}
+KEY_CODE = {np.dtype(np.int32): 0, np.dtype(np.int64): 1, np.dtype(np.float32): 2,
+            np.dtype(np.float64): 3}
 RID_CODE = {np.dtype(np.uint32): 0, np.dtype(np.uint64): 1}
 DESC, ASC = 0, 1
 
@@ -123,6 +124,11 @@ def _f32_total_rank(bits: int) -> int:
     return (bits ^ 0xFFFFFFFF) if bits & 0x80000000 else (bits | 0x80000000)
 
 
+def _f64_total_rank(bits: int) -> int:
+    """Integer whose natural order is IEEE totalOrder on a float64 bit pattern."""
+    return (bits ^ 0xFFFFFFFFFFFFFFFF) if bits >> 63 else (bits | (1 << 63))
+
+
 def brute_topk(keys, rowids, k, order=DESC):
     """sorted() of all pairs by the definition, first min(k, n) kept."""
     keys = np.asarray(keys)
@@ -130,6 +136,8 @@ def brute_topk(keys, rowids, k, order=DESC):
     rids = list(range(n)) if rowids is None else [int(r) for r in rowids]
     if keys.dtype == np.float32:
         ranks = [_f32_total_rank(int(b)) for b in keys.view(np.uint32)]
+    elif keys.dtype == np.float64:
+        ranks = [_f64_total_rank(int(b)) for b in keys.view(np.uint64)]
     else:
         ranks = [int(x) for x in keys]
     sign = -1 if order == DESC else 1
@@ -157,6 +165,11 @@ def order_rank(keys: np.ndarray, order: int) -> np.ndarray:
         neg = (b >> np.uint64(31)) == 1
         u = np.where(neg, b ^ np.uint64(0xFFFFFFFF), b | np.uint64(0x80000000))
         top = np.uint64((1 << 32) - 1)
+    elif keys.dtype == np.float64:
+        b = keys.view(np.uint64)
+        neg = (b >> np.uint64(63)) == 1
+        u = np.where(neg, ~b, b | np.uint64(1 << 63))
+        top = np.uint64((1 << 64) - 1)
     else:
         raise TypeError(keys.dtype)
     return (top - u) if order == DESC else u

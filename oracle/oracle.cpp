@@ -13,7 +13,7 @@
 //     descending: key_a > key_b, or key_a = key_b and rowid_a < rowid_b
 //     ascending:  key_a < key_b, or key_a = key_b and rowid_a < rowid_b
 //   where < is numeric order for int32/int64 and the IEEE 754-2019 totalOrder
-//   predicate (clause 5.10) for float32.  The result is the first
+//   predicate (clause 5.10) for float32 and float64.  The result is the first
 //   K_eff = min(K, N) pairs of the input sorted by that relation, best first:
 //   the original key bits and the paired row-id.
 //
@@ -28,7 +28,7 @@
 
 namespace {
 
-enum { KEY_I32 = 0, KEY_I64 = 1, KEY_F32 = 2 };
+enum { KEY_I32 = 0, KEY_I64 = 1, KEY_F32 = 2, KEY_F64 = 3 };
 enum { RID_U32 = 0, RID_U64 = 1 };
 enum { ORDER_DESC = 0, ORDER_ASC = 1 };
 
@@ -63,6 +63,30 @@ int cmp_f32(float a, float b) {
   return sb ? 1 : -1;
 }
 
+// The same clauses for float64 (binary64 significand field: 52 bits).
+int cmp_f64(double a, double b) {
+  const bool an = std::isnan(a), bn = std::isnan(b);
+  const bool sa = std::signbit(a), sb = std::signbit(b);
+  if (!an && !bn) {
+    if (a < b) return -1;
+    if (a > b) return 1;
+    if (sa == sb) return 0;
+    return sa ? -1 : 1;
+  }
+  if (an && bn) {
+    if (sa != sb) return sa ? -1 : 1;
+    uint64_t ba, bb;
+    std::memcpy(&ba, &a, 8);
+    std::memcpy(&bb, &b, 8);
+    const uint64_t fa = ba & 0xFFFFFFFFFFFFFull, fb = bb & 0xFFFFFFFFFFFFFull;
+    if (fa == fb) return 0;
+    const int c = fa < fb ? -1 : 1;
+    return sa ? -c : c;
+  }
+  if (an) return sa ? -1 : 1;
+  return sb ? 1 : -1;
+}
+
 template <typename K>
 int cmp_int(K a, K b) { return a < b ? -1 : (a > b ? 1 : 0); }
 
@@ -78,6 +102,12 @@ struct Before {
       std::memcpy(&a, &keys[i], 4);
       std::memcpy(&b, &keys[j], 4);
       return cmp_f32(a, b);
+    }
+    if (key_type == KEY_F64) {
+      double a, b;
+      std::memcpy(&a, &keys[i], 8);
+      std::memcpy(&b, &keys[j], 8);
+      return cmp_f64(a, b);
     }
     return cmp_int(keys[i], keys[j]);
   }
@@ -114,14 +144,14 @@ void dispatch_rid(int rid_type, const void* keys, const void* rids, uint64_t n, 
 
 extern "C" {
 
-// One query.  keys: n keys of key_type (0 int32, 1 int64, 2 float32).  rowids:
+// One query.  keys: n keys of key_type (0 int32, 1 int64, 2 float32, 3 float64).  rowids:
 // n row-ids of rid_type (0 uint32, 1 uint64), or null for row-id = index.
 // order: 0 descending, 1 ascending.  Writes K_eff = min(k, n) results to
 // out_keys (key bits, may be null) and out_rowids (rid_type, may be null) and
 // K_eff to *out_count.  Returns 0, or -1 on a bad argument.
 int oracle_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int key_type,
                 int rid_type, int order, void* out_keys, void* out_rowids, uint64_t* out_count) {
-  if (key_type < 0 || key_type > 2 || rid_type < 0 || rid_type > 1 || order < 0 || order > 1)
+  if (key_type < 0 || key_type > 3 || rid_type < 0 || rid_type > 1 || order < 0 || order > 1)
     return -1;
   if (n > 0 && !keys) return -1;
   const uint64_t k_eff = k < n ? k : n;
@@ -143,7 +173,7 @@ int oracle_topk_batched(const void* keys, const void* rowids, const uint64_t* of
                         const uint32_t* ks, const uint8_t* orders, uint32_t q, int key_type,
                         int rid_type, void* out_keys, void* out_rowids) {
   if (!offsets || !ks || !orders) return -1;
-  const size_t kb = key_type == KEY_I64 ? 8 : 4, rb = rid_type == RID_U64 ? 8 : 4;
+  const size_t kb = key_type == KEY_I64 || key_type == KEY_F64 ? 8 : 4, rb = rid_type == RID_U64 ? 8 : 4;
   uint64_t out_pos = 0;
   for (uint32_t i = 0; i < q; ++i) {
     const uint64_t lo = offsets[i], n = offsets[i + 1] - offsets[i];

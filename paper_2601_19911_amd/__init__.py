@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmitopk.so")
 
-TK_KEY_I32, TK_KEY_I64, TK_KEY_F32 = 0, 1, 2
+TK_KEY_I32, TK_KEY_I64, TK_KEY_F32, TK_KEY_F64 = 0, 1, 2, 3
 TK_RID_U32, TK_RID_U64 = 0, 1
 TK_DESC, TK_ASC = 0, 1
 
@@ -83,8 +83,8 @@ def check(rc: int, what: str = "call"):
 def key_code(dtype) -> int:
     import torch
     m = {torch.int32: TK_KEY_I32, torch.int64: TK_KEY_I64, torch.float32: TK_KEY_F32,
-         np.dtype(np.int32): TK_KEY_I32, np.dtype(np.int64): TK_KEY_I64,
-         np.dtype(np.float32): TK_KEY_F32}
+         torch.float64: TK_KEY_F64, np.dtype(np.int32): TK_KEY_I32, np.dtype(np.int64): TK_KEY_I64,
+         np.dtype(np.float32): TK_KEY_F32, np.dtype(np.float64): TK_KEY_F64}
     if dtype not in m:
         raise TypeError(f"unsupported key dtype {dtype}")
     return m[dtype]
@@ -134,7 +134,7 @@ def new_workspace(n: int, k: int, key_type: int, rid_type: int, device="cuda"):
 
 def topk(keys, k: int, rowids=None, order="desc", out_keys=None, out_rowids=None,
          rid_dtype=None, workspace=None, stream=None, want_keys: bool = True):
-    """Top-K of device tensor ``keys`` (int32, int64 or float32), best first.
+    """Top-K of device tensor ``keys`` (int32, int64, float32 or float64), best first.
 
     ``rowids``: device tensor of uint32/uint64 row-ids, or None for the index.
     Returns ``(out_keys, out_rowids)``; tensors are allocated when not given.

@@ -60,7 +60,7 @@ Tuning plan_tuning(const tk_plan_params* p) {
 bool valid_inputs(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders, uint32_t q,
                   int key_type, int rid_type, const tk_plan_params* params) {
   if (!offsets || !ks || !orders || q == 0) return false;
-  if (key_type < 0 || key_type > 2 || rid_type < 0 || rid_type > 1) return false;
+  if (key_type < 0 || key_type > 3 || rid_type < 0 || rid_type > 1) return false;
   if (params && ((params->tile_keys && params->tile_keys < 4096) ||
                  params->min_sample_log2 > 24 || params->max_sample_log2 > 24))
     return false;
@@ -99,7 +99,7 @@ size_t build(tk_plan& P, const uint64_t* offsets, const uint32_t* ks, const uint
 
 int upload(tk_plan& P, const void* keys, const void* rowids, void* out_keys, void* out_rowids,
            hipStream_t st) {
-  const uint32_t kb = P.key_type == TK_KEY_I64 ? 8 : 4, rb = P.rid_type == TK_RID_U64 ? 8 : 4;
+  const uint32_t kb = key_bytes(P.key_type), rb = P.rid_type == TK_RID_U64 ? 8 : 4;
   std::vector<MQuery> qs(P.q);
   for (uint32_t i = 0; i < P.q; ++i) {
     MQuery& m = qs[i];

@@ -30,12 +30,18 @@ inline uint32_t img(uint32_t bits, int kt) {
   if (kt == TK_KEY_F32) return bits ^ ((uint32_t)((int32_t)bits >> 31) | 0x80000000u);
   return bits ^ 0x80000000u;
 }
-inline uint64_t img(uint64_t bits, int) { return bits ^ 0x8000000000000000ull; }
+inline uint64_t img(uint64_t bits, int kt) {
+  if (kt == TK_KEY_F64) return bits ^ ((uint64_t)((int64_t)bits >> 63) | 0x8000000000000000ull);
+  return bits ^ 0x8000000000000000ull;
+}
 inline uint32_t unimg(uint32_t u, int kt) {
   if (kt == TK_KEY_F32) return u ^ (((u >> 31) - 1u) | 0x80000000u);
   return u ^ 0x80000000u;
 }
-inline uint64_t unimg(uint64_t u, int) { return u ^ 0x8000000000000000ull; }
+inline uint64_t unimg(uint64_t u, int kt) {
+  if (kt == TK_KEY_F64) return u ^ (((u >> 63) - 1ull) | 0x8000000000000000ull);
+  return u ^ 0x8000000000000000ull;
+}
 
 template <typename U, typename R>
 void keep_best(std::vector<Comp<U, R>>& v, size_t k) {
@@ -103,7 +109,7 @@ int run(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, int kt, 
 extern "C" int tk_cpu_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k,
                            int key_type, int rid_type, int order, void* out_keys,
                            void* out_rowids, uint64_t* out_count, int nthreads) {
-  if (key_type < 0 || key_type > 2 || rid_type < 0 || rid_type > 1 || order < 0 || order > 1)
+  if (key_type < 0 || key_type > 3 || rid_type < 0 || rid_type > 1 || order < 0 || order > 1)
     return TK_EINVAL;
   if (n > 0 && !keys) return TK_EINVAL;
   const uint64_t k_eff = k < n ? k : n;
@@ -115,7 +121,7 @@ extern "C" int tk_cpu_topk(const void* keys, const void* rowids, uint64_t n, uin
     if (nthreads < 1) nthreads = 1;
   }
   try {
-    if (key_type == TK_KEY_I64) {
+    if (key_type == TK_KEY_I64 || key_type == TK_KEY_F64) {
       if (rid_type == TK_RID_U32)
         return run<uint64_t, uint32_t>(keys, rowids, n, k_eff, key_type, order, out_keys, out_rowids, nthreads);
       return run<uint64_t, uint64_t>(keys, rowids, n, k_eff, key_type, order, out_keys, out_rowids, nthreads);

@@ -15,7 +15,9 @@
 
 namespace tk {
 
-constexpr int KEY_I32 = 0, KEY_I64 = 1, KEY_F32 = 2;
+constexpr int KEY_I32 = 0, KEY_I64 = 1, KEY_F32 = 2, KEY_F64 = 3;
+// bytes of a key of each type
+__host__ __device__ constexpr uint32_t key_bytes(int kt) { return kt == KEY_I64 || kt == KEY_F64 ? 8u : 4u; }
 constexpr int RID_U32 = 0, RID_U64 = 1;
 
 template <int KT> struct Key;
@@ -40,6 +42,18 @@ template <> struct Key<KEY_I64> {
   using U = uint64_t;
   static __host__ __device__ __forceinline__ U enc(Raw x) { return x ^ 0x8000000000000000ull; }
   static __host__ __device__ __forceinline__ Raw dec(U u) { return u ^ 0x8000000000000000ull; }
+};
+// float64: as float32, on 64-bit patterns (negative: all bits flipped;
+// non-negative: sign bit set), so that unsigned order is totalOrder
+template <> struct Key<KEY_F64> {
+  using Raw = uint64_t;
+  using U = uint64_t;
+  static __host__ __device__ __forceinline__ U enc(Raw x) {
+    return x ^ ((uint64_t)((int64_t)x >> 63) | 0x8000000000000000ull);
+  }
+  static __host__ __device__ __forceinline__ Raw dec(U u) {
+    return u ^ (((u >> 63) - 1ull) | 0x8000000000000000ull);
+  }
 };
 
 template <int RT> struct Rid;

@@ -93,7 +93,7 @@ Regions regions_of(uint64_t k_eff, uint32_t kb, uint32_t rb, const SamplePlan& p
 
 uint64_t multi_layout(const std::vector<uint64_t>& n, const std::vector<uint64_t>& k, int key_type,
                       int rid_type, const Tuning& tun, uint32_t slice_keys, MLayout& L) {
-  const uint32_t kb = key_type == TK_KEY_I64 ? 8 : 4, rb = rid_type == TK_RID_U64 ? 8 : 4;
+  const uint32_t kb = key_bytes(key_type), rb = rid_type == TK_RID_U64 ? 8 : 4;
   const size_t q = n.size();
   const uint64_t slice = slice_keys ? slice_keys : DEFAULT_SLICE;
   L = MLayout{};
@@ -131,7 +131,7 @@ uint64_t multi_layout(const std::vector<uint64_t>& n, const std::vector<uint64_t
 
 void multi_records(const std::vector<MQuery>& q, const MLayout& L, int key_type, int rid_type,
                    char* ws, MRecords& r) {
-  const uint32_t kb = key_type == TK_KEY_I64 ? 8 : 4, rb = rid_type == TK_RID_U64 ? 8 : 4;
+  const uint32_t kb = key_bytes(key_type), rb = rid_type == TK_RID_U64 ? 8 : 4;
   r.sa.clear();
   r.smap.clear();
   r.fa.clear();
@@ -234,6 +234,7 @@ void multi_enqueue(const MLaunch& m, int key_type, int rid_type, hipStream_t st)
   switch (key_type) {
     case TK_KEY_I32: enqueue_rid<KEY_I32>(m, rid_type, st); break;
     case TK_KEY_F32: enqueue_rid<KEY_F32>(m, rid_type, st); break;
+    case TK_KEY_F64: enqueue_rid<KEY_F64>(m, rid_type, st); break;
     default: enqueue_rid<KEY_I64>(m, rid_type, st); break;
   }
 }

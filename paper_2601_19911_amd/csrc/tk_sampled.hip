@@ -170,6 +170,8 @@ TK_INST(KEY_F32, RID_U32)
 TK_INST(KEY_F32, RID_U64)
 TK_INST(KEY_I64, RID_U32)
 TK_INST(KEY_I64, RID_U64)
+TK_INST(KEY_F64, RID_U32)
+TK_INST(KEY_F64, RID_U64)
 #undef TK_INST
 #endif  // TK_EMU
 

@@ -85,7 +85,7 @@ struct tk_server {
   std::deque<Req> reqs;  // stable addresses; index = request id
   std::mutex mu;
   std::condition_variable cv_batch, cv_cpu, cv_done, cv_slot;
-  std::deque<uint64_t> gpu_q[3];  // per key type
+  std::deque<uint64_t> gpu_q[4];  // per key type
   std::deque<uint64_t> cpu_q;
   std::vector<Slot> slots;
   std::deque<int> inflight;  // slot indices in launch order
@@ -131,7 +131,7 @@ void cpu_worker(tk_server* s) {
     }
     Req& r = *rp;
     r.t_start = now_ns();
-    const uint32_t kb = c.key_type == TK_KEY_I64 ? 8 : 4;
+    const uint32_t kb = key_bytes(c.key_type);
     const uint64_t ke = std::min<uint64_t>(r.k, r.n);
     r.out_keys.resize(ke * kb);
     r.out_rids.resize(ke);
@@ -165,7 +165,7 @@ struct BatchBuild {
 // Lays out a micro-batch for `arena`; returns false if it does not fit.
 bool build_batch(const std::vector<Taken>& ids, int key_type, char* arena, size_t arena_bytes,
                  BatchBuild& b, size_t* needed) {
-  const uint32_t kb = key_type == TK_KEY_I64 ? 8 : 4, rb = 8;
+  const uint32_t kb = key_bytes(key_type), rb = 8;
   const size_t q = ids.size();
   Tuning t = current_tuning();
   t.force_exact = 0;
@@ -222,7 +222,8 @@ void batcher_loop(tk_server* s) {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_batch.wait(lk, [&] {
         if (s->stop) return true;
-        bool any = !s->gpu_q[0].empty() || !s->gpu_q[1].empty() || !s->gpu_q[2].empty();
+        bool any = false;
+        for (const auto& q : s->gpu_q) any = any || !q.empty();
         if (!any) return false;
         for (auto& sl : s->slots)
           if (!sl.busy) return true;
@@ -231,7 +232,7 @@ void batcher_loop(tk_server* s) {
       if (s->stop) return;
       // the key type whose oldest request waited longest
       uint64_t best = UINT64_MAX;
-      for (int t = 0; t < 3; ++t)
+      for (int t = 0; t < 4; ++t)
         if (!s->gpu_q[t].empty() && s->reqs[s->gpu_q[t].front()].t_submit < best) {
           best = s->reqs[s->gpu_q[t].front()].t_submit;
           kt = t;
@@ -337,7 +338,7 @@ void completer_loop(tk_server* s) {
     }
     Slot& sl = s->slots[slot];
     const hipError_t e = hipEventSynchronize(sl.done);
-    const uint32_t kb = sl.key_type == TK_KEY_I64 ? 8 : 4;
+    const uint32_t kb = key_bytes(sl.key_type);
     const uint64_t tdone = now_ns();
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -414,7 +415,7 @@ extern "C" int tk_server_create(const tk_server_cfg* cfg, void* arena, size_t ar
 
 extern "C" int tk_server_add_column(tk_server* s, const void* d_keys, const void* h_keys,
                                     uint64_t n, int key_type, uint32_t* col) {
-  if (!s || !col || key_type < 0 || key_type > 2 || (n && !d_keys)) return TK_EINVAL;
+  if (!s || !col || key_type < 0 || key_type > 3 || (n && !d_keys)) return TK_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
   s->cols.push_back(Column{d_keys, h_keys, n, key_type});
   *col = (uint32_t)(s->cols.size() - 1);

@@ -528,6 +528,8 @@ template int run_single<KEY_F32, RID_U32>(const void*, const void*, uint64_t, ui
 template int run_single<KEY_F32, RID_U64>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
 template int run_single<KEY_I64, RID_U32>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
 template int run_single<KEY_I64, RID_U64>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
+template int run_single<KEY_F64, RID_U32>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
+template int run_single<KEY_F64, RID_U64>(const void*, const void*, uint64_t, uint64_t, int, void*, void*, void*, size_t, hipStream_t, const Tuning&);
 
 }  // namespace tk
 
@@ -537,14 +539,14 @@ using namespace tk;
 
 extern "C" size_t tk_workspace_size(uint64_t n, uint64_t k, int key_type, int rid_type) {
   const uint64_t k_eff = k < n ? k : n;
-  const uint32_t kb = key_type == TK_KEY_I64 ? 8 : 4, rb = rid_type == TK_RID_U64 ? 8 : 4;
+  const uint32_t kb = key_bytes(key_type), rb = rid_type == TK_RID_U64 ? 8 : 4;
   return single_ws_bytes(n, k_eff, kb, rb, current_tuning());
 }
 
 extern "C" int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int key_type,
                        int rid_type, int order, void* out_keys, void* out_rowids,
                        uint64_t* out_count, void* workspace, size_t workspace_bytes, void* stream) {
-  if (key_type < 0 || key_type > 2 || rid_type < 0 || rid_type > 1 || order < 0 || order > 1)
+  if (key_type < 0 || key_type > 3 || rid_type < 0 || rid_type > 1 || order < 0 || order > 1)
     return TK_EINVAL;
   const uint64_t k_eff = k < n ? k : n;
   if (n > 0 && !keys) return TK_EINVAL;
@@ -558,6 +560,7 @@ extern "C" int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_
   return run_single<KT, RT>(keys, rowids, n, k_eff, order, out_keys, out_rowids, workspace, workspace_bytes, st, t)
   if (key_type == TK_KEY_I32) { if (rid_type == TK_RID_U32) TK_RUN(KEY_I32, RID_U32); TK_RUN(KEY_I32, RID_U64); }
   if (key_type == TK_KEY_F32) { if (rid_type == TK_RID_U32) TK_RUN(KEY_F32, RID_U32); TK_RUN(KEY_F32, RID_U64); }
+  if (key_type == TK_KEY_F64) { if (rid_type == TK_RID_U32) TK_RUN(KEY_F64, RID_U32); TK_RUN(KEY_F64, RID_U64); }
   if (rid_type == TK_RID_U32) TK_RUN(KEY_I64, RID_U32);
   TK_RUN(KEY_I64, RID_U64);
 #undef TK_RUN

@@ -8,7 +8,7 @@ import ctypes
 
 import numpy as np
 
-from . import TK_KEY_F32, TK_KEY_I32, TK_KEY_I64, TopKError, check, key_code, lib
+from . import TK_KEY_F32, TK_KEY_F64, TK_KEY_I32, TK_KEY_I64, TopKError, check, key_code, lib
 
 GATE_GPU, GATE_COST, GATE_CPU = 0, 1, 2
 
@@ -118,7 +118,8 @@ class Server:
         check(_bind().tk_server_drain(self._h), "tk_server_drain")
 
     def result(self, req, col, k_eff):
-        kdt = {TK_KEY_I32: np.int32, TK_KEY_I64: np.int64, TK_KEY_F32: np.float32}[self.cols[col][2]]
+        kdt = {TK_KEY_I32: np.int32, TK_KEY_I64: np.int64, TK_KEY_F32: np.float32,
+               TK_KEY_F64: np.float64}[self.cols[col][2]]
         ok = np.empty(k_eff, dtype=kdt)
         orr = np.empty(k_eff, dtype=np.uint64)
         info = tk_req_info()

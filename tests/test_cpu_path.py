@@ -13,7 +13,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("kind", [inputgen.KIND_U_I32, inputgen.KIND_U_F32, inputgen.KIND_U_I64,
-                                  inputgen.KIND_ZIPF_F32, inputgen.KIND_SORTED_F32])
+                                  inputgen.KIND_ZIPF_F32, inputgen.KIND_SORTED_F32, inputgen.KIND_U_F64])
 @pytest.mark.parametrize("n,k", [(1, 1), (1000, 0), (1000, 999), (1000, 5000), (70001, 100),
                                  (300000, 1000), (300000, 40000)])
 @pytest.mark.parametrize("order", ["desc", "asc"])
@@ -34,6 +34,15 @@ def test_cpu_u64_rowids_and_specials():
     rids = np.arange(len(keys), dtype=np.uint64)[::-1].copy()
     for order, o in (("desc", oracle.DESC), ("asc", oracle.ASC)):
         _same(tk.cpu_topk(keys, 12345, rowids=rids, order=order), oracle.topk(keys, rids, 12345, o))
+
+
+def test_cpu_float64_specials():
+    bits = np.array([0xFFF8000000000000, 0xFFF0000000000000, 0x8000000000000000, 0, 0x0000000000000001,
+                     0x3FF0000000000000, 0x7FF0000000000000, 0x7FF8000000000000] * 4000, dtype=np.uint64)
+    keys = bits.view(np.float64)
+    rids = np.arange(len(keys), dtype=np.uint64)[::-1].copy()
+    for order, o in (("desc", oracle.DESC), ("asc", oracle.ASC)):
+        _same(tk.cpu_topk(keys, 9999, rowids=rids, order=order), oracle.topk(keys, rids, 9999, o))
 
 
 def test_gather_rows_host_is_numpy_take():

@@ -21,14 +21,15 @@ N = 1 << 28
 
 KIND = {("float32", "uniform"): inputgen.KIND_U_F32, ("int64", "uniform"): inputgen.KIND_U_I64,
         ("float32", "zipf"): inputgen.KIND_ZIPF_F32, ("int64", "zipf"): inputgen.KIND_ZIPF_I64,
-        ("float32", "sorted"): inputgen.KIND_SORTED_F32, ("int64", "sorted"): inputgen.KIND_SORTED_I64}
+        ("float32", "sorted"): inputgen.KIND_SORTED_F32, ("int64", "sorted"): inputgen.KIND_SORTED_I64,
+        ("float64", "uniform"): inputgen.KIND_U_F64}
 
 
 def device_input(dtype: str, dist: str):
     """(device keys, device iota row-ids, host keys) of the N = 2^28 workload."""
     import torch
     dev = torch.device("cuda:0")
-    tdt = {"float32": torch.float32, "int64": torch.int64}[dtype]
+    tdt = {"float32": torch.float32, "int64": torch.int64, "float64": torch.float64}[dtype]
     keys = torch.empty(N, dtype=tdt, device=dev)
     cdf = cdf_dev = None
     if dist == "zipf":
@@ -82,6 +83,7 @@ CASES = [
     ("int64", "uniform", 1000, "desc"),
     ("int64", "zipf", 1000, "asc"),
     ("int64", "sorted", 100_000, "desc"),
+    ("float64", "uniform", 1000, "desc"),
 ]
 
 

@@ -110,3 +110,7 @@ def test_multi_plan_argument_errors():
     orders = np.array([0, 1], dtype=np.uint8)
     with pytest.raises(tk.TopKError):
         Plan(off, ks, orders, key_dtype=torch.int64, rid_dtype=torch.uint32, tile_keys=100)
+
+
+def test_multi_float64_given_rowids():
+    _plan_run(inputgen.KIND_U_F64, 64, 8, 21, 5000, seed=49, with_rids=True, launches=2)

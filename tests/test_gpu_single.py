@@ -342,3 +342,44 @@ def test_wide_k_sampled():
     _run_path_cases([("int32", 65536, 10000, "desc"), ("float32", 131072, 10000, "asc"),
                      ("int64", 100000, 7000, "desc"), ("float32", 1 << 20, 1 << 17, "desc"),
                      ("int64", 1 << 20, 1 << 19, "asc")], 6, seed=400)
+
+
+def _f64_keys(n, seed):
+    """float64 keys of mixed sign and magnitude with IEEE specials and ties:
+    +-0, +-inf, NaNs of both signs, subnormals and repeated values."""
+    rng = np.random.default_rng(seed)
+    keys = rng.standard_normal(n) * 10.0 ** rng.integers(-30, 30, n)
+    specials = np.array([0x0000000000000000, 0x8000000000000000, 0x7FF0000000000000, 0xFFF0000000000000,
+                         0x7FF8000000000000, 0xFFF8000000000001, 0x0000000000000001, 0x800000000000000F],
+                        dtype=np.uint64).view(np.float64)
+    m = max(n // 50, 1)
+    keys[rng.integers(0, n, m)] = specials[rng.integers(0, len(specials), m)]
+    keys[rng.integers(0, n, m)] = keys[rng.integers(0, n, m)]  # repeats
+    return keys
+
+
+@pytest.mark.parametrize("n,k", [(1, 1), (3000, 1000), (16384, 5000), (23170, 300), (1 << 20, 100),
+                                 (1 << 20, 10000), (1 << 20, 300000)])
+def test_float64_keys(n, k):
+    """float64 keys (the paper's key type) through every route: ranked and
+    one-workgroup small paths, the exact select, the sampled ranked and
+    bucketed tails; totalOrder on the specials; both orders, row-ids given and
+    implicit (u64 and u32)."""
+    import torch
+    keys = _f64_keys(n, seed=n + k)
+    kd = to_dev(keys)
+    rng = np.random.default_rng(k)
+    for order in ("desc", "asc"):
+        for rdt in (None, np.uint64, np.uint32):
+            rids = None if rdt is None else rng.permutation(n).astype(rdt)
+            exp = oracle.topk(keys, rids, k, order_code(order),
+                              rid_dtype=np.uint32 if rdt is None else rdt)
+            rc = tk.TK_RID_U32 if rdt in (None, np.uint32) else tk.TK_RID_U64
+            ws = tk.new_workspace(n, k, tk.TK_KEY_F64, rc)
+            ok, orr = tk.topk(kd, k, rowids=None if rids is None else to_dev(rids), order=order,
+                              workspace=ws, rid_dtype=torch.uint32 if rdt is None else None)
+            torch.cuda.synchronize()
+            info = tk.query_info(ws)
+            say(f"float64 n={n} k={k} {order} rids={rdt}: {info}")
+            assert info["status"] == 0
+            assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"float64 n={n} k={k} {order} {rdt}")

@@ -87,6 +87,15 @@ def test_exhaustive_float32_specials():
     assert _exhaustive(F32_ALPHABET, 3) > 1000
 
 
+F64_ALPHABET = np.array([0xFFF8000000000000, 0xFFF0000000000000, 0x8000000000000000, 0x0000000000000000,
+                         0x3FF0000000000000, 0x7FF0000000000000, 0x7FF8000000000000],
+                        dtype=np.uint64).view(np.float64)
+
+
+def test_exhaustive_float64_specials():
+    assert _exhaustive(F64_ALPHABET, 3) > 1000
+
+
 def test_exhaustive_int64_alphabet():
     assert _exhaustive(np.array([-(2 ** 63), -5, 0, 2 ** 63 - 1], dtype=np.int64), 4) > 1000
 
@@ -128,20 +137,67 @@ def test_total_order_ladder():
         assert np.array_equal(keys.view(np.uint32)[orr.astype(np.int64)], ok.view(np.uint32))
 
 
+LADDER64 = np.array([
+    0xFFFFFFFFFFFFFFFF,  # -NaN, largest significand: lowest of all
+    0xFFF8000000000001,  # -NaN (quiet)
+    0xFFF0000000000001,  # -NaN (signalling)
+    0xFFF0000000000000,  # -inf
+    0xFFEFFFFFFFFFFFFF,  # -max finite
+    0xBFF0000000000000,  # -1
+    0x8010000000000000,  # -min normal
+    0x8000000000000001,  # -min subnormal
+    0x8000000000000000,  # -0
+    0x0000000000000000,  # +0
+    0x0000000000000001,  # +min subnormal
+    0x0010000000000000,  # +min normal
+    0x3FF0000000000000,  # +1
+    0x7FEFFFFFFFFFFFFF,  # +max finite
+    0x7FF0000000000000,  # +inf
+    0x7FF0000000000001,  # +NaN (signalling)
+    0x7FF8000000000000,  # +NaN (quiet)
+    0x7FFFFFFFFFFFFFFF,  # +NaN, largest significand: highest of all
+], dtype=np.uint64)
+
+
+def test_total_order_ladder_float64():
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        p = rng.permutation(len(LADDER64))
+        keys = LADDER64[p].view(np.float64)
+        ok, orr = oracle.topk(keys, None, len(LADDER64), ASC)
+        assert np.array_equal(ok.view(np.uint64), LADDER64)
+        ok, orr = oracle.topk(keys, None, len(LADDER64), DESC)
+        assert np.array_equal(ok.view(np.uint64), LADDER64[::-1])
+        assert np.array_equal(keys.view(np.uint64)[orr.astype(np.int64)], ok.view(np.uint64))
+
+
+def test_float64_finite_order_is_numeric():
+    # away from zeros and NaNs, totalOrder is the numeric order: numpy's sort
+    rng = np.random.default_rng(4)
+    keys = rng.standard_normal(5000) * 10.0 ** rng.integers(-300, 300, 5000)
+    keys[keys == 0] = 1.0
+    for k in (1, 17, 5000):
+        ok, _ = oracle.topk(keys, None, k, DESC)
+        assert np.array_equal(ok, np.sort(keys)[::-1][:k])
+        ok, _ = oracle.topk(keys, None, k, ASC)
+        assert np.array_equal(ok, np.sort(keys)[:k])
+
+
 # ---- library special cases ---------------------------------------------------------------
 
 @pytest.mark.parametrize("n", [1, 7, 1000, 1 << 16])
-@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32", "float64"])
 def test_k_equals_n_is_lexsort(n, dtype):
     rng = np.random.default_rng(n)
-    if dtype == "float32":
-        keys = (rng.integers(0, 50, n).astype(np.float32) * np.float32(0.25)) - np.float32(3.0)
-        keys[keys == 0] = np.float32(0.5)  # keep -0/+0 out: numpy sorts them as equal
+    if dtype in ("float32", "float64"):
+        keys = (rng.integers(0, 50, n).astype(dtype) * 0.25) - 3.0
+        keys = keys.astype(dtype)
+        keys[keys == 0] = 0.5  # keep -0/+0 out: numpy sorts them as equal
     else:
         keys = rng.integers(-40, 40, n).astype(dtype)
     rids = rng.permutation(n).astype(np.uint32)
     ok, orr = oracle.topk(keys, rids, n, DESC)
-    neg = -keys if dtype == "float32" else ~keys
+    neg = -keys if dtype in ("float32", "float64") else ~keys
     o = np.lexsort((rids, neg))
     assert np.array_equal(_bits(ok), _bits(keys[o])) and np.array_equal(orr, rids[o])
     ok, orr = oracle.topk(keys, rids, n, ASC)
@@ -149,7 +205,7 @@ def test_k_equals_n_is_lexsort(n, dtype):
     assert np.array_equal(_bits(ok), _bits(keys[o])) and np.array_equal(orr, rids[o])
 
 
-@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32", "float64"])
 def test_k1_is_first_argmax(dtype):
     rng = np.random.default_rng(7)
     for _ in range(50):
@@ -161,7 +217,8 @@ def test_k1_is_first_argmax(dtype):
         assert int(orr[0]) == int(np.argmin(keys))
 
 
-@pytest.mark.parametrize("kind", [inputgen.KIND_U_I32, inputgen.KIND_U_F32, inputgen.KIND_U_I64])
+@pytest.mark.parametrize("kind", [inputgen.KIND_U_I32, inputgen.KIND_U_F32, inputgen.KIND_U_I64,
+                                  inputgen.KIND_PAYLOAD_F64])
 def test_key_multiset_is_numpy_sort(kind):
     keys = inputgen.generate(kind, 11, 1 << 18)
     for k in (1, 100, 5000):
