@@ -210,9 +210,24 @@ __device__ __forceinline__ void bscatter_body(const BTailArgs& b, uint32_t* loff
     if (bk >= bstar) atomicAdd(&lcnt[bk], 1u);
   });
   __syncthreads();
-  for (uint32_t i = bstar + t; i < NB; i += BT_NT) {
-    const uint32_t c = lcnt[i];
-    if (c) lcnt[i] = loff[i] + atomicAdd(&b.cur[i], c);
+  // reserve room in each hot bucket: BT_BATCH atomics in flight per thread
+  for (uint32_t i0 = bstar + t; i0 < NB; i0 += BT_BATCH * BT_NT) {
+    uint32_t c[BT_BATCH], r[BT_BATCH];
+#pragma unroll
+    for (int q = 0; q < BT_BATCH; ++q) {
+      const uint32_t i = i0 + (uint32_t)q * BT_NT;
+      c[q] = i < NB ? lcnt[i] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < BT_BATCH; ++q) {
+      const uint32_t i = i0 + (uint32_t)q * BT_NT;
+      r[q] = c[q] ? atomicAdd(&b.cur[i], c[q]) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < BT_BATCH; ++q) {
+      const uint32_t i = i0 + (uint32_t)q * BT_NT;
+      if (c[q]) lcnt[i] = loff[i] + r[q];
+    }
   }
   __syncthreads();
   U* hk = static_cast<U*>(b.hk);
