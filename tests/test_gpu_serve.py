@@ -159,3 +159,30 @@ def test_gate_routes_follow_cost_model(margin_us):
         assert_same(ok, orr, ek, er, what=f"gated n={n} k={k} o={o} route={info.route}")
     assert 0 < int(want_gpu.sum()) < len(reqs)
     srv.close()
+
+
+@pytest.mark.parametrize("gate", [GATE_GPU, GATE_CPU])
+def test_served_float64_column(gate):
+    """A float64 column (the paper's key type) through either route of the
+    served form; every request equals the oracle on its rows."""
+    import torch
+    ncol = 1 << 20
+    h = inputgen.generate(inputgen.KIND_U_F64, 21, ncol)
+    h[::997] = -h[::997]  # both signs
+    srv = Server(arena_bytes=256 << 20, max_batch=32, slots=2, gate=gate)
+    cid = srv.add_column(to_dev(h), h)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(23)
+    reqs = []
+    for _ in range(60):
+        n = int(2 ** rng.uniform(8, 20))
+        reqs.append((int(rng.integers(0, ncol - n + 1)), n, int(rng.choice([1, 10, 100, 1000, 10000])),
+                     int(rng.integers(0, 2))))
+    rid = [srv.submit(cid, off, n, k, o) for (off, n, k, o) in reqs]
+    srv.drain()
+    for (off, n, k, o), r in zip(reqs, rid):
+        ok, orr, info = srv.result(r, 0, min(k, n))
+        assert info.route == (0 if gate == GATE_GPU else 1)
+        ek, er = oracle.topk(h[off:off + n], None, k, o, rid_dtype=np.uint64)
+        assert_same(ok, orr, ek, er + np.uint64(off), what=f"float64 served n={n} k={k} o={o}")
+    srv.close()
