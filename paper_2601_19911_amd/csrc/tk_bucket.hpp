@@ -113,17 +113,17 @@ __device__ __forceinline__ void bscatter_body(const BTailArgs& b, uint32_t* loff
     if (blockIdx.x == 0 && t == 0) b.meta->fallback = 1u;
     return;
   }
-  // the histogram into LDS, BT_BATCH loads in flight per thread
-  for (uint32_t i0 = t; i0 < NB; i0 += BT_BATCH * BT_NT) {
-    uint32_t c[BT_BATCH];
+  // the histogram into LDS: every load of the thread in flight at once
+  {
+    uint32_t c[BPT];
 #pragma unroll
-    for (int q = 0; q < BT_BATCH; ++q) {
-      const uint32_t i = i0 + (uint32_t)q * BT_NT;
+    for (uint32_t q = 0; q < BPT; ++q) {
+      const uint32_t i = q * BT_NT + t;
       c[q] = i < NB ? b.gh[i] : 0u;
     }
 #pragma unroll
-    for (int q = 0; q < BT_BATCH; ++q) {
-      const uint32_t i = i0 + (uint32_t)q * BT_NT;
+    for (uint32_t q = 0; q < BPT; ++q) {
+      const uint32_t i = q * BT_NT + t;
       if (i < NB) {
         loff[i] = c[q];
         lcnt[i] = 0;
