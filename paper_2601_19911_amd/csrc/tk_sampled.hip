@@ -151,7 +151,7 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
                        wsp<BMeta>(ws, L.btail + (size_t)3 * nb * 4), wsp<char>(ws, L.btail + hot),
                        wsp<char>(ws, L.btail + hot + align_up((size_t)p.cap * sizeof(U), 256))};
     hipLaunchKernelGGL((k_bhist<KT, RT>), dim3(BT_SLICES), dim3(BT_NT), 0, st, bt);
-    hipLaunchKernelGGL((k_bscatter<KT, RT>), dim3(BT_SLICES), dim3(BT_NT), 0, st, bt);
+    hipLaunchKernelGGL((k_bscatter<KT, RT>), dim3(BT_SCATTER), dim3(BT_NT), 0, st, bt);
     hipLaunchKernelGGL((k_bsort<KT, RT>), dim3(BT_GRID), dim3(TAIL_NT), 0, st, bt);
   } else if (tun.rank_tail)
     hipLaunchKernelGGL((k_rtail<KT, RT>), dim3(rank_grid(k_eff)), dim3(RANK_NT), 0, st, ta);
