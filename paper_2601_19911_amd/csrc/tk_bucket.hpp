@@ -29,7 +29,7 @@
 namespace tk {
 
 constexpr int BT_NT = 256;           // k_bhist, k_bscatter
-constexpr uint32_t BT_SLICES = 64;   // workgroups of k_bhist
+constexpr uint32_t BT_SLICES = 128;  // workgroups of k_bhist
 constexpr uint32_t BT_SCATTER = 256; // workgroups of k_bscatter
 constexpr uint32_t BT_GRID = 256;    // workgroups of k_bsort
 
