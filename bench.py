@@ -36,6 +36,8 @@ def parse(argv=None):
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the result")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--read-ceiling", action="store_true",
+                    help="only measure the read ceiling: tk_read_probe over 1 GiB")
     return ap.parse_args(argv)
 
 
@@ -67,6 +69,34 @@ def calibrate_copy():
     torch.cuda.synchronize()
     print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": n,
                       "bytes_written_per_copy": n, "copies": 5}), flush=True)
+
+
+def read_ceiling():
+    """The HBM read ceiling the streaming pass is compared against: the read
+    probe of the library over 1 GiB, 20 timed passes per launch shape (event
+    pairs on the launch stream), median and best in GB/s."""
+    import numpy as np
+    import torch
+    import paper_2601_19911_amd as tk
+    n = 1 << 30
+    buf = torch.full((n // 4,), 0x11111111, dtype=torch.int32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    rows = []
+    for wg in (2, 3, 4, 8):
+        for _ in range(3):
+            tk.read_probe(buf, wg, sink, stream=s)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+        for a, b in ev:
+            a.record(s)
+            tk.read_probe(buf, wg, sink, stream=s)
+            b.record(s)
+        torch.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        rows.append({"wg_per_cu": wg, "median_gbs": n / (np.median(ms) * 1e-3) / 1e9,
+                     "best_gbs": n / (ms.min() * 1e-3) / 1e9})
+    assert int(sink.item()) == 0
+    print(json.dumps({"read_ceiling": rows, "bytes": n, "peak_gbs": HBM_PEAK_GBS}), flush=True)
 
 
 def measure(args) -> dict:
@@ -228,6 +258,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.read_ceiling:
+        read_ceiling()
         return
     print(json.dumps(measure(args)), flush=True)
 

@@ -265,6 +265,17 @@ int tk_gather_f64_device(const double* cols, uint32_t ncols, uint64_t n, const v
 int tk_profile_begin(uint32_t max_launches);
 int tk_profile_end(double* total_ms, uint64_t* launches);
 
+/* Read-ceiling probe: the bandwidth the streaming pass (the HBM-bound step of
+ * the selection, sec. III-A) is compared against.  Enqueues one read-only pass
+ * over `buf` with 16-byte nontemporal loads and one compare per 4-byte word,
+ * on wg_per_cu workgroups of 256 threads per CU striding over 16 KiB tiles;
+ * each workgroup adds its count of words above 0xFFFFFFFF (always 0) to the
+ * device word `sink`, so no other byte is written.  Reads the whole tiles of
+ * `bytes` (rounded down to 16 KiB).  buf: device memory, 16-byte aligned;
+ * sink: device uint32; 1 <= wg_per_cu <= 32.  Stream-ordered and
+ * asynchronous; time it with events on `stream`.  TK_EINVAL on a bad argument. */
+int tk_read_probe(const void* buf, uint64_t bytes, uint32_t wg_per_cu, void* sink, void* stream);
+
 /* Human-readable name of a tk_status_t value. */
 const char* tk_status_string(int status);
 

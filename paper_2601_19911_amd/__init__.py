@@ -66,6 +66,8 @@ def lib():
         L.tk_profile_begin.restype = i32
         L.tk_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]
         L.tk_profile_end.restype = i32
+        L.tk_read_probe.argtypes = [vp, u64, ctypes.c_uint32, vp, vp]
+        L.tk_read_probe.restype = i32
         L.tk_status_string.argtypes = [i32]
         L.tk_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -199,6 +201,13 @@ def profile_end():
     n = ctypes.c_uint64(0)
     check(lib().tk_profile_end(ctypes.byref(ms), ctypes.byref(n)), "tk_profile_end")
     return ms.value, n.value
+
+
+def read_probe(buf, wg_per_cu: int, sink, stream=None):
+    """Enqueues one read-only pass over device tensor ``buf`` (tk_read_probe);
+    ``sink`` is a device int32/uint32 tensor of at least one element."""
+    check(lib().tk_read_probe(_ptr(buf), buf.numel() * buf.element_size(), int(wg_per_cu), _ptr(sink),
+                              _stream_handle(stream)), "tk_read_probe")
 
 
 # ---- CPU route ------------------------------------------------------------------------------

@@ -314,6 +314,27 @@ __device__ __forceinline__ void stage_vector(const bool (&pass)[VEC], const U (&
   }
 }
 
+// One tile of the streaming pass: UNR 16-byte nontemporal loads per thread
+// (or one key per thread for VEC = 1), NT threads apart.
+template <typename Raw, int VEC, int UNR, int NT>
+__device__ __forceinline__ void load_key_tile(const Raw* keys, uint64_t base, Raw (&v)[UNR][VEC]) {
+#pragma unroll
+  for (int u = 0; u < UNR; ++u) {
+    const uint64_t i0 = base + ((uint64_t)u * NT + threadIdx.x) * VEC;
+    if constexpr (VEC * sizeof(Raw) == 16) {
+      const u32x4s q = __builtin_nontemporal_load(reinterpret_cast<const u32x4s*>(keys + i0));
+      if constexpr (sizeof(Raw) == 4) {
+        v[u][0] = q.x; v[u][1] = q.y; v[u][2] = q.z; v[u][3] = q.w;
+      } else {
+        v[u][0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+        v[u][1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
+      }
+    } else {
+      v[u][0] = keys[i0];
+    }
+  }
+}
+
 template <int KT, int RT, int VEC, int UNR>
 __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
                                             SurvStage<typename Key<KT>::U, typename Rid<RT>::R>& st) {
@@ -346,80 +367,86 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
   // every lane's row-id vector starts head + a multiple of VEC rows in
   const bool ralign = rids != nullptr && (((uintptr_t)(rids + head)) & 15u) == 0;
   const uint64_t ntiles = (a.n - head) / TILE;
+  // tile t + nblk is loaded while tile t is checked: twice the bytes in
+  // flight per wave at the same occupancy
+  // (and, when row-ids go with the keys, its row-ids likewise)
+  Raw v[UNR][VEC];
+  R rv[UNR][VEC];
+  auto load_rows = [=](uint64_t b, R (&r)[UNR][VEC]) {
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+      load_rowids<R, VEC>(rids + b + ((uint64_t)u * NT + threadIdx.x) * VEC, ralign, r[u]);
+  };
+  if (blk < ntiles) {
+    load_key_tile<Raw, VEC, UNR, NT>(keys, head + blk * TILE, v);
+    if (tie_rows) load_rows(head + blk * TILE, rv);
+  }
   for (uint64_t t = blk; t < ntiles; t += a.nblk) {
     const uint64_t base = head + t * TILE;
-    Raw v[UNR][VEC];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const uint64_t i0 = base + ((uint64_t)u * NT + threadIdx.x) * VEC;
-      if constexpr (VEC * sizeof(Raw) == 16) {
-        const u32x4s q = __builtin_nontemporal_load(reinterpret_cast<const u32x4s*>(keys + i0));
-        if constexpr (sizeof(Raw) == 4) {
-          v[u][0] = q.x; v[u][1] = q.y; v[u][2] = q.z; v[u][3] = q.w;
-        } else {
-          v[u][0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
-          v[u][1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
-        }
-      } else {
-        v[u][0] = keys[i0];
-      }
-    }
-    R rv[UNR][VEC];
-    if (tie_rows) {  // with the keys, so both loads are in flight together
-#pragma unroll
-      for (int u = 0; u < UNR; ++u)
-        load_rowids<R, VEC>(rids + base + ((uint64_t)u * NT + threadIdx.x) * VEC, ralign, rv[u]);
+    Raw nv[UNR][VEC];
+    R nrv[UNR][VEC];
+    if (t + a.nblk < ntiles) {
+      load_key_tile<Raw, VEC, UNR, NT>(keys, base + a.nblk * TILE, nv);
+      if (tie_rows) load_rows(base + a.nblk * TILE, nrv);
     }
     bool any = false;
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
 #pragma unroll
       for (int e = 0; e < VEC; ++e) any |= (Key<KT>::enc(v[u][e]) ^ dmask) >= Tk;
-    if (ballot(any) == 0) continue;
-    // A vector some lane of the wave reaches the threshold with.  When a key
-    // of the wave ties with the threshold (common in skewed columns) the
-    // row-ids of the whole vector are read at once, coalesced; otherwise only
-    // the lanes above the threshold read theirs.  Then survivors are staged.
+    if (ballot(any) != 0) {
+      // A vector some lane of the wave reaches the threshold with.  When a key
+      // of the wave ties with the threshold (common in skewed columns) the
+      // row-ids of the whole vector are read at once, coalesced; otherwise only
+      // the lanes above the threshold read theirs.  Then survivors are staged.
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      U kk[VEC];
-      bool hit = false, tie = false;
+      for (int u = 0; u < UNR; ++u) {
+        U kk[VEC];
+        bool hit = false, tie = false;
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        kk[e] = Key<KT>::enc(v[u][e]) ^ dmask;
-        hit |= kk[e] >= Tk;
-        tie |= kk[e] == Tk;
+        for (int e = 0; e < VEC; ++e) {
+          kk[e] = Key<KT>::enc(v[u][e]) ^ dmask;
+          hit |= kk[e] >= Tk;
+          tie |= kk[e] == Tk;
+        }
+        if (ballot(hit) == 0) continue;
+        const uint64_t i0 = base + ((uint64_t)u * NT + threadIdx.x) * VEC;
+        R ff[VEC];
+        bool pass[VEC];
+        bool pv = false;
+        if (tie_rows) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) ff[e] = ~rv[u][e];
+        } else if (ballot(tie)) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) ff[e] = src.flip(i0 + e);
+        } else if (!drids) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) ff[e] = kk[e] > Tk ? src.flip(i0 + e) : (R)0;
+        } else {  // no key of the wave ties: the key alone decides
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) ff[e] = (R)0;
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          pass[e] = kk[e] > Tk || (kk[e] == Tk && ff[e] >= Tf);
+          pv |= pass[e];
+        }
+        if (ballot(pv) == 0) continue;
+        if (drids) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) ff[e] = (R)(i0 + e);
+        }
+        stage_vector<U, R, VEC>(pass, kk, ff, st, h, sk, sf, a.cap, drids);
       }
-      if (ballot(hit) == 0) continue;
-      const uint64_t i0 = base + ((uint64_t)u * NT + threadIdx.x) * VEC;
-      R ff[VEC];
-      bool pass[VEC];
-      bool pv = false;
-      if (tie_rows) {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) ff[e] = ~rv[u][e];
-      } else if (ballot(tie)) {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) ff[e] = src.flip(i0 + e);
-      } else if (!drids) {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) ff[e] = kk[e] > Tk ? src.flip(i0 + e) : (R)0;
-      } else {  // no key of the wave ties: the key alone decides
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) ff[e] = (R)0;
-      }
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        pass[e] = kk[e] > Tk || (kk[e] == Tk && ff[e] >= Tf);
-        pv |= pass[e];
-      }
-      if (ballot(pv) == 0) continue;
-      if (drids) {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) ff[e] = (R)(i0 + e);
-      }
-      stage_vector<U, R, VEC>(pass, kk, ff, st, h, sk, sf, a.cap, drids);
     }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        v[u][e] = nv[u][e];
+        if (tie_rows) rv[u][e] = nrv[u][e];
+      }
   }
   // the head and the remainder (fewer than VEC + TILE keys), one per thread:
   // position p < head is key p, the others follow the last whole tile

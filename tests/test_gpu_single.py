@@ -383,3 +383,18 @@ def test_float64_keys(n, k):
             say(f"float64 n={n} k={k} {order} rids={rdt}: {info}")
             assert info["status"] == 0
             assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"float64 n={n} k={k} {order} {rdt}")
+
+
+def test_read_probe():
+    """The read-ceiling probe writes nothing but its zero count and rejects bad
+    arguments before launching."""
+    import torch
+    buf = torch.full((1 << 20,), -1, dtype=torch.int32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tk.read_probe(buf, 3, sink)
+    torch.cuda.synchronize()
+    assert int(sink.item()) == 0 and bool((buf == -1).all().item())
+    L = tk.lib()
+    assert L.tk_read_probe(buf.data_ptr() + 4, 1 << 20, 3, sink.data_ptr(), None) == -1  # TK_EINVAL
+    assert L.tk_read_probe(buf.data_ptr(), 1 << 20, 0, sink.data_ptr(), None) == -1  # TK_EINVAL
+    assert L.tk_read_probe(buf.data_ptr(), 1 << 20, 3, None, None) == -1  # TK_EINVAL
