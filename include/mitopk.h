@@ -90,10 +90,12 @@ typedef struct {
                            workgroups over the whole input;
                            4 sampled, but the sample misjudged: exact select
                            over the input; 5 exact radix select over the input
-                           (K a large share of N); 0 after a one-workgroup query */
+                           (no usable sample: N below 2^15, K above N / 2, or K
+                           above N / 16 with N above 2^20); 0 after a
+                           one-workgroup query (N within one LDS tile, K > 2048) */
   uint32_t status;      /* 0, or device failure bits (1: a grid barrier timed out,
                            2: a wait between engine items timed out) */
-  uint64_t survivors;   /* keys that passed the sampled threshold (paths 2-4) */
+  uint64_t survivors;   /* keys that passed the sampled threshold (paths 2-4, 6) */
   uint64_t threshold_key;  /* sampled threshold, order-preserving key image */
 } tk_info;
 int tk_query_info(const void* workspace, tk_info* info);
