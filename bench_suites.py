@@ -27,6 +27,9 @@ import time
 
 import numpy as np
 
+from paper_2601_19911_amd.gate import (break_even, crossover_n, fit_costs, measured_break_even,
+                                       route_gpu)
+
 HBM_PEAK_GBS = 8000.0
 
 
@@ -428,37 +431,6 @@ def suite_c5(a):
 
 # ---- crossover ---------------------------------------------------------------------------------
 
-def fit_costs(rows, relative=False):
-    """Least-squares cost models of the gate (reading: C_cpu = a N + b K log2(K+1) + c,
-    C_gpu = a N + b K + c), from crossover rows.  relative: residuals taken
-    relative to the measured time, so that the small-N points near the
-    break-even weigh as much as the large ones."""
-    N = np.array([r["n"] for r in rows], dtype=np.float64)
-    K = np.array([min(r["k"], r["n"]) for r in rows], dtype=np.float64)
-    cpu = np.array([r["cpu_all_cores_s"] for r in rows])
-    gpu = np.array([r["gpu_resident_s"] for r in rows])
-    wc = 1.0 / cpu if relative else np.ones_like(cpu)
-    wg = 1.0 / gpu if relative else np.ones_like(gpu)
-    A = np.stack([N, K * np.log2(K + 1), np.ones_like(N)], 1)
-    ca = np.linalg.lstsq(A * wc[:, None], cpu * wc, rcond=None)[0]
-    B = np.stack([N, K, np.ones_like(N)], 1)
-    ga = np.linalg.lstsq(B * wg[:, None], gpu * wg, rcond=None)[0]
-    return {"cpu_a": float(ca[0]), "cpu_b": float(ca[1]), "cpu_c": float(ca[2]),
-            "gpu_a": float(ga[0]), "gpu_b": float(ga[1]), "gpu_c": float(ga[2])}
-
-
-def crossover_n(rows, key):
-    """Smallest N from which the GPU time stays below the CPU time."""
-    rows = sorted(rows, key=lambda r: r["n"])
-    best = None
-    for r in reversed(rows):
-        if r[key] < r["cpu_all_cores_s"]:
-            best = r["n"]
-        else:
-            break
-    return best
-
-
 class _Point:
     """CPU and GPU times of one Top-K (N, K) over the first N keys of a seeded
     column of one dtype: GPU with keys resident in HBM and with keys copied from
@@ -544,59 +516,19 @@ def suite_crossover(a):
 
 # ---- gate: break-even prediction and margin sensitivity -------------------------------------
 
-def predicted_break_even(cost, k, margin_s=0.0):
-    """N at which the gate's estimated saving, C_cpu - C_gpu, reaches the margin
-    (the cost models are linear in N): the smallest offloaded N."""
-    slope = cost["cpu_a"] - cost["gpu_a"]
-    if slope <= 0:
-        return None
-    rest = (cost["gpu_b"] * k + cost["gpu_c"]) - (cost["cpu_b"] * k * np.log2(k + 1.0) + cost["cpu_c"])
-    return max((margin_s + rest) / slope, 1.0)
-
-
-def gate_route_gpu(cost, n, k, margin_s=0.0):
-    """The gate's decision for requests (n, k): True where offloaded."""
-    n = np.asarray(n, dtype=np.float64)
-    k = np.minimum(np.asarray(k, dtype=np.float64), n)
-    c_cpu = cost["cpu_a"] * n + cost["cpu_b"] * k * np.log2(k + 1.0) + cost["cpu_c"]
-    c_gpu = cost["gpu_a"] * n + cost["gpu_b"] * k + cost["gpu_c"]
-    return c_cpu - c_gpu > margin_s
-
-
-def measured_break_even(pt, k, rows, steps):
-    """Smallest N from which the resident GPU route beats the CPU route: the
-    bracketing pair of the power-of-two sweep, then `steps` bisections in log N
-    (each midpoint measured like the sweep)."""
-    rows = sorted(rows, key=lambda r: r["n"])
-    hi = crossover_n(rows, "gpu_resident_s")
-    if hi is None or hi == rows[0]["n"]:
-        return hi, []
-    lo = hi // 2
-    extra = []
-    for _ in range(steps):
-        mid = int(round(np.sqrt(float(lo) * float(hi))))
-        if mid <= lo or mid >= hi:
-            break
-        r = pt(mid, k)
-        extra.append(r)
-        if r["gpu_resident_s"] < r["cpu_all_cores_s"]:
-            hi = mid
-        else:
-            lo = mid
-    return float(np.sqrt(float(lo) * float(hi))), extra
-
-
 def suite_gate(a):
-    """Break-even validation: fit the gate's cost models on the power-of-two
-    sweep of every dtype and K (2^fit_lo_log2 <= N <= 2^fit_log2, relative
-    residuals), predict each break-even N, measure it by bisection, and report
-    the relative error.  Then the margin
-    sweep: the serving mixture at one arrival rate under the fitted gate, one
-    run per margin (offload share predicted from the model and observed,
-    latency, throughput)."""
-    fit_rows, be = [], []
+    """Break-even validation (paper sec. V-D, in kind): fit the gate's cost
+    models per key type on the power-of-two sweep of every K
+    (2^fit_lo_log2 <= N <= 2^fit_log2, relative residuals), predict each
+    break-even N from that key type's models, measure it by bisection, and
+    report the relative error.  Then the margin sweep: the serving mixture at
+    one arrival rate under the fitted per-type gate, one run per margin
+    (offload share predicted from the models and observed, latency,
+    throughput)."""
+    be, costs = [], {}
     for dt in a.dtypes:
         pt = _Point(dt, 1 << a.max_log2, a.ks)
+        fit_rows = []
         for K in a.ks:
             rows = []
             for lg in range(a.min_log2, a.max_log2 + 1):
@@ -609,22 +541,29 @@ def suite_gate(a):
             fit_rows += [r for r in rows if (1 << a.fit_lo_log2) <= r["n"] <= (1 << a.fit_log2)]
             be.append({"dtype": dt, "k": K, "measured": meas})
         del pt
-    cost = fit_costs(fit_rows, relative=True)
-    emit({"suite": "gate", "fit": cost, "fit_points": len(fit_rows)})
+        costs[dt] = fit_costs(fit_rows, relative=True)
+        emit({"suite": "gate", "dtype": dt, "fit": costs[dt], "fit_points": len(fit_rows)})
     for b in be:
-        pred = predicted_break_even(cost, b["k"])
+        pred = break_even(costs[b["dtype"]], b["k"])
         err = None if (pred is None or b["measured"] is None) else abs(pred - b["measured"]) / b["measured"]
         emit({"suite": "gate", "dtype": b["dtype"], "k": b["k"], "break_even_measured": b["measured"],
               "break_even_predicted": pred, "rel_error": err})
-    # margin sweep on the serving mixture, under the fitted gate
+    # margin sweep on the serving mixture, under the fitted per-type gate
     import inputgen
     req = inputgen.serving_requests(a.requests, col_len=1 << a.col_log2)
+    types = ["int32", "int64", "float32"]
+    col_type = np.array([types[c % 3] for c in range(a.columns)])
+    req_type = col_type[np.minimum((req["u_col"] * a.columns).astype(np.int64), a.columns - 1)]
     for m in a.margins_us:
-        emit({"suite": "gate", "margin_us": m,
-              "predicted_gpu_share": float(np.mean(gate_route_gpu(cost, req["n"], req["k"], m * 1e-6))),
-              "break_even_by_k": {str(k): predicted_break_even(cost, k, m * 1e-6)
-                                  for k in (10, 100, 1000, 10000)}})
-    a.cost = json.dumps(cost)
+        share = np.zeros(len(req["n"]), dtype=bool)
+        for t in types:
+            sel = req_type == t
+            if t in costs and sel.any():
+                share[sel] = route_gpu(costs[t], req["n"][sel], req["k"][sel], m * 1e-6)
+        emit({"suite": "gate", "margin_us": m, "predicted_gpu_share": float(np.mean(share)),
+              "break_even_by_k": {t: {str(k): break_even(costs[t], k, m * 1e-6)
+                                      for k in (10, 100, 1000, 10000)} for t in costs}})
+    a.cost = json.dumps(costs)
     a.modes = ["cost_gate"]
     suite_c5(a)
 

@@ -178,17 +178,26 @@ int tk_plan_stats(const tk_plan* plan, uint32_t* fallbacks, uint32_t* unfinished
 void tk_plan_destroy(tk_plan* plan);
 
 /* ---- Served form -----------------------------------------------------------------------------
- * Continuous batching of Top-K requests over device-resident key columns
- * with the cost gate of the paper (sec. II-B): a request is offloaded only
- * when the estimated CPU cost exceeds the estimated GPU cost (transfer +
- * kernel + result return) by more than a margin; otherwise it runs on the
- * host CPU path over the column's host mirror.  A batcher thread forms
- * micro-batches of one key type whenever one of `slots` stream slots is free,
- * admitting requests while the slot's share of the arena has room; batches
- * on different slots overlap on the device.  Row-ids are the global row
- * index in the column (uint64).  Every result equals tk_topk on the same
- * keys, whichever route and batch it took. */
+ * Continuous batching of Top-K requests over key columns with the cost gate
+ * of the paper (sec. II-B): a request is offloaded only when the estimated
+ * CPU cost exceeds the estimated GPU cost (transfer + kernel + result return)
+ * by more than a margin; otherwise it runs on the host CPU path over the
+ * column's host copy.  The gate's signals are the paper's: N (rows), K (the
+ * limit, capped at N), the bytes B a GPU route must move over the host link
+ * (N x key bytes for a host-resident column, 0 for a device-resident one) and
+ * the estimated CPU cost.  A batcher thread forms micro-batches of one key
+ * type whenever one of `slots` stream slots is free, admitting requests while
+ * the slot's arena, staging and result buffers have room; batches on
+ * different slots overlap on the device.  Row-ids are the global row index
+ * in the column (uint64).  Every result equals tk_topk on the same keys,
+ * whichever route and batch it took. */
 typedef struct tk_server tk_server;
+/* Cost model of one key type, seconds, K = min(k, N):
+ *   C_cpu = cpu_a*N + cpu_b*K*log2(K+1) + cpu_c
+ *   C_gpu = gpu_a*N + gpu_b*K + gpu_c  (+ B / h2d_bytes_per_s for a host-resident column) */
+typedef struct {
+  double cpu_a, cpu_b, cpu_c, gpu_a, gpu_b, gpu_c;
+} tk_cost_model;
 typedef struct {
   uint32_t max_batch;   /* requests per micro-batch; 0: 256 */
   uint32_t slots;       /* micro-batches in flight; 0: 2 */
@@ -196,33 +205,43 @@ typedef struct {
   int32_t gate;         /* 0 always GPU, 1 cost gate, 2 always CPU */
   double margin_ms;     /* gate margin */
   int32_t cpu_threads;  /* CPU-route workers; 0: 4 */
-  /* cost model, seconds, K = min(k, N): C_cpu = cpu_a*N + cpu_b*K*log2(K+1) + cpu_c,
-   * C_gpu = gpu_a*N + gpu_b*K + gpu_c.  All six 0: a fit measured on MI355X
-   * with 16 host threads (cpu 1.79e-10, 1.26e-8, 4.36e-5; gpu 0, 1.48e-8,
-   * 5.30e-5), which sends device-resident requests below N ~ 16K to the CPU */
-  double cpu_a, cpu_b, cpu_c, gpu_a, gpu_b, gpu_c;
+  /* per key type, indexed by tk_key_t; an all-zero entry takes the library's
+   * default for that type (a fit measured on MI355X, device-resident keys,
+   * against the CPU route on 16 host threads) */
+  tk_cost_model cost[4];
+  double h2d_bytes_per_s;  /* host-to-device rate for host-resident columns; 0: 5.0e10 */
 } tk_server_cfg;
 typedef struct {
   uint64_t t_submit_ns, t_start_ns, t_done_ns;  /* host steady clock */
   int32_t route;   /* 0 GPU, 1 CPU */
-  int32_t status;
+  int32_t status;  /* TK_OK, or the request's error (TK_ENOMEM: larger than a slot
+                      and no host copy to run it on the CPU) */
   uint64_t count;  /* results written */
 } tk_req_info;
 typedef struct {
   uint64_t submitted, completed, routed_gpu, routed_cpu, batches, batched_requests;
+  uint64_t live;          /* requests the server still holds: queued, running, or
+                             finished and not yet taken by tk_server_result */
+  uint64_t failed;        /* requests finished with an error status */
 } tk_server_counters;
 
 /* arena: caller-owned device buffer (256-byte aligned) split among the
  * slots; it bounds how much one micro-batch may hold. */
 int tk_server_create(const tk_server_cfg* cfg, void* arena, size_t arena_bytes, tk_server** server);
-/* d_keys: device column of n keys; h_keys: its host mirror (NULL: GPU only). */
+/* A column of n keys.  d_keys: device copy (NULL: host-resident only, the GPU
+ * route then copies each request's rows into the slot's arena, and the gate
+ * counts those bytes); h_keys: host copy for the CPU route (NULL: GPU only;
+ * pinned memory from hipHostMalloc keeps a host-resident column's copies
+ * asynchronous).  At least one of the two is required.  The caller keeps both
+ * alive until tk_server_destroy. */
 int tk_server_add_column(tk_server* server, const void* d_keys, const void* h_keys, uint64_t n,
                          int key_type, uint32_t* col_id);
 /* Top-K of rows [offset, offset + n) of a column; returns at once. */
 int tk_server_submit(tk_server* server, uint32_t col, uint64_t offset, uint64_t n, uint32_t k,
                      int order, uint64_t* req_id);
-/* Copies a finished request's keys and row-ids to host memory; TK_EAGAIN
- * while it runs. */
+/* Copies a finished request's keys and row-ids to host memory and releases
+ * the request (its id is then unknown: TK_EINVAL); TK_EAGAIN while it runs.
+ * Returns the request's own status. */
 int tk_server_result(tk_server* server, uint64_t req_id, void* h_keys, uint64_t* h_rowids,
                      tk_req_info* info);
 /* Submits `count` requests at t_arrival_s[i] seconds after the call (an

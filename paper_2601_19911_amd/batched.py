@@ -113,6 +113,11 @@ class Plan:
             self._h = None
 
     def __del__(self):
+        # no HIP calls while the interpreter shuts down: the runtime (or a
+        # profiler attached to it) may already be finalized; close() explicitly
+        import sys
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

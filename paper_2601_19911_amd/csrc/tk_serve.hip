@@ -1,7 +1,8 @@
-// Served form: continuous batching of Top-K requests over device-resident key
-// columns, with the cost-accounted gate of the paper (sec. II-B, the "Risky
-// Gate"): a request goes to the GPU only when the estimated CPU cost exceeds
-// the estimated offload cost by more than a margin; otherwise it runs on the
+// Served form: continuous batching of Top-K requests over key columns, with
+// the cost-accounted gate of the paper (sec. II-B, the "Risky Gate"): a
+// request goes to the GPU only when the estimated CPU cost exceeds the
+// estimated offload cost (host-link transfer of a host-resident column's rows,
+// kernels, result return) by more than a margin; otherwise it runs on the
 // host with the multithreaded CPU path.  Host code only.
 //
 // Threads: the caller submits; a batcher thread forms micro-batches of one key
@@ -23,7 +24,9 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <memory>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "mitopk.h"
@@ -42,8 +45,8 @@ uint64_t now_ns() {
 }
 
 struct Column {
-  const void* d_keys;
-  const void* h_keys;
+  const void* d_keys;  // nullptr: host-resident, the GPU route copies the rows it needs
+  const void* h_keys;  // nullptr: no host copy, GPU route only
   uint64_t n;
   int key_type;
 };
@@ -55,7 +58,7 @@ struct Req {
   uint32_t k;
   int order;
   int route;  // 0 GPU, 1 CPU
-  std::atomic<int> state{0};  // 0 queued, 1 running, 2 done, 3 taken
+  std::atomic<int> state{0};  // 0 queued, 1 running, 2 done (released when taken)
   int status = 0;
   uint64_t t_submit = 0, t_start = 0, t_done = 0;
   std::vector<uint8_t> out_keys;
@@ -82,7 +85,10 @@ struct Slot {
 struct tk_server {
   tk_server_cfg cfg{};
   std::vector<Column> cols;
-  std::deque<Req> reqs;  // stable addresses; index = request id
+  // live requests by id (stable addresses); a request is released once its
+  // result is taken, so the server holds only queued, running and untaken ones
+  std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
+  uint64_t next_id = 0;
   std::mutex mu;
   std::condition_variable cv_batch, cv_cpu, cv_done, cv_slot;
   std::deque<uint64_t> gpu_q[4];  // per key type
@@ -93,23 +99,44 @@ struct tk_server {
   std::thread batcher, completer;
   bool stop = false;
   uint64_t submitted = 0, completed = 0, n_gpu = 0, n_cpu = 0, n_batches = 0, n_batched = 0;
+  uint64_t n_failed = 0;
   int dev = 0;
+  Req& req(uint64_t id) { return *reqs.at(id); }
 };
 
 namespace {
 
-double cpu_cost(const tk_server_cfg& c, uint64_t n, uint32_t k) {
+double cpu_cost(const tk_cost_model& c, uint64_t n, uint32_t k) {
   return c.cpu_a * (double)n + c.cpu_b * (double)k * std::log2((double)k + 1.0) + c.cpu_c;
 }
-double gpu_cost(const tk_server_cfg& c, uint64_t n, uint32_t k) {
-  return c.gpu_a * (double)n + c.gpu_b * (double)k + c.gpu_c;
+// offload cost: kernels and result return, plus the host-link transfer of the
+// request's key bytes when the column has no device copy (the gate's B)
+double gpu_cost(const tk_cost_model& c, uint64_t n, uint32_t k, double bytes, double h2d) {
+  return c.gpu_a * (double)n + c.gpu_b * (double)k + c.gpu_c + bytes / h2d;
 }
+
+bool all_zero(const tk_cost_model& c) {
+  return c.cpu_a == 0 && c.cpu_b == 0 && c.cpu_c == 0 && c.gpu_a == 0 && c.gpu_b == 0 && c.gpu_c == 0;
+}
+
+// Default cost models per key type (tk_key_t order): least-squares fits of
+// measured request times on an MI355X (device-resident keys, launch to
+// results on the host) and of the CPU route on 16 host threads.
+constexpr tk_cost_model DEFAULT_COST[4] = {
+    {1.79e-10, 1.26e-8, 4.36e-5, 0.0, 1.48e-8, 5.30e-5},  // int32
+    {1.79e-10, 1.26e-8, 4.36e-5, 0.0, 1.48e-8, 5.30e-5},  // int64
+    {1.79e-10, 1.26e-8, 4.36e-5, 0.0, 1.48e-8, 5.30e-5},  // float32
+    {1.79e-10, 1.26e-8, 4.36e-5, 0.0, 1.48e-8, 5.30e-5},  // float64
+};
+constexpr double DEFAULT_H2D = 5.0e10;
 
 void finish(tk_server* s, uint64_t id) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    s->reqs[id].t_done = now_ns();
-    s->reqs[id].state.store(2);
+    Req& r = s->req(id);
+    r.t_done = now_ns();
+    r.state.store(2);
+    if (r.status != TK_OK) ++s->n_failed;
     ++s->completed;
   }
   s->cv_done.notify_all();
@@ -126,7 +153,7 @@ void cpu_worker(tk_server* s) {
       if (s->stop && s->cpu_q.empty()) return;
       id = s->cpu_q.front();
       s->cpu_q.pop_front();
-      rp = &s->reqs[id];
+      rp = &s->req(id);
       c = s->cols[rp->col];
     }
     Req& r = *rp;
@@ -146,7 +173,8 @@ void cpu_worker(tk_server* s) {
 
 struct Taken {
   Req* r;
-  const void* d_keys;
+  const void* d_keys;  // column's device keys, or nullptr (host-resident: staged in the arena)
+  const void* h_keys;  // column's host keys
   uint64_t offset, n;
   uint32_t k;
   int order;
@@ -154,17 +182,19 @@ struct Taken {
 
 // A micro-batch laid out in a slot's arena:
 //   [batch workspace: query states, then each query's regions][argument
-//   records][result keys][result row-ids]
+//   records][result keys][result row-ids][rows of host-resident requests]
 struct BatchBuild {
   MLayout L;
   MRecords rec;
   std::vector<uint64_t> out_off;
-  uint64_t off_rec = 0, rec_bytes = 0, off_out_k = 0, off_out_r = 0, end = 0;
+  std::vector<uint64_t> stage_off;  // arena offset of each host-resident request's rows
+  uint64_t off_rec = 0, rec_bytes = 0, off_out_k = 0, off_out_r = 0, off_rows = 0, end = 0;
+  size_t stage_need = 0, out_need = 0;  // pinned staging and result bytes the batch needs
 };
 
-// Lays out a micro-batch for `arena`; returns false if it does not fit.
-bool build_batch(const std::vector<Taken>& ids, int key_type, char* arena, size_t arena_bytes,
-                 BatchBuild& b, size_t* needed) {
+// Lays out a micro-batch for a slot; returns false if it does not fit the
+// slot's arena, its pinned staging or its pinned result buffer.
+bool build_batch(const std::vector<Taken>& ids, int key_type, const Slot& sl, BatchBuild& b) {
   const uint32_t kb = key_bytes(key_type), rb = 8;
   const size_t q = ids.size();
   Tuning t = current_tuning();
@@ -193,21 +223,30 @@ bool build_batch(const std::vector<Taken>& ids, int key_type, char* arena, size_
   off = align_up(off + b.out_off[q] * kb, 256);
   b.off_out_r = off;
   off = align_up(off + b.out_off[q] * rb, 256);
+  b.off_rows = off;
+  b.stage_off.assign(q, 0);
+  for (size_t i = 0; i < q; ++i)
+    if (!ids[i].d_keys) {
+      b.stage_off[i] = off;
+      off = align_up(off + ids[i].n * kb, 256);
+    }
   b.end = off;
-  if (needed) *needed = off;
-  if (off > arena_bytes) return false;
+  b.stage_need = b.L.heads_bytes + b.rec_bytes;
+  b.out_need = b.off_rows - b.off_out_k;
+  if (off > sl.arena_bytes || b.stage_need > sl.stage_bytes || b.out_need > sl.out_bytes) return false;
   std::vector<MQuery> qs(q);
   for (size_t i = 0; i < q; ++i) {
     MQuery& m = qs[i];
-    m.keys = static_cast<const char*>(ids[i].d_keys) + ids[i].offset * kb;
+    m.keys = ids[i].d_keys ? static_cast<const char*>(ids[i].d_keys) + ids[i].offset * kb
+                           : static_cast<const char*>(sl.arena + b.stage_off[i]);
     m.rids = nullptr;  // local index; the column offset is added on the host
     m.n = ids[i].n;
     m.k = ids[i].k;
     m.order = ids[i].order;
-    m.out_keys = arena + b.off_out_k + b.out_off[i] * kb;
-    m.out_rids = arena + b.off_out_r + b.out_off[i] * rb;
+    m.out_keys = sl.arena + b.off_out_k + b.out_off[i] * kb;
+    m.out_rids = sl.arena + b.off_out_r + b.out_off[i] * rb;
   }
-  multi_records(qs, b.L, key_type, TK_RID_U64, arena, b.rec);
+  multi_records(qs, b.L, key_type, TK_RID_U64, sl.arena, b.rec);
   return true;
 }
 
@@ -233,8 +272,8 @@ void batcher_loop(tk_server* s) {
       // the key type whose oldest request waited longest
       uint64_t best = UINT64_MAX;
       for (int t = 0; t < 4; ++t)
-        if (!s->gpu_q[t].empty() && s->reqs[s->gpu_q[t].front()].t_submit < best) {
-          best = s->reqs[s->gpu_q[t].front()].t_submit;
+        if (!s->gpu_q[t].empty() && s->req(s->gpu_q[t].front()).t_submit < best) {
+          best = s->req(s->gpu_q[t].front()).t_submit;
           kt = t;
         }
       // a short window lets a batch fill when it would otherwise be tiny
@@ -256,41 +295,64 @@ void batcher_loop(tk_server* s) {
       if (slot < 0) continue;
       auto& q = s->gpu_q[kt];
       while (!q.empty() && take.size() < s->cfg.max_batch) {
-        Req& r = s->reqs[q.front()];
-        take.push_back(Taken{&r, s->cols[r.col].d_keys, r.offset, r.n, r.k, r.order});
+        Req& r = s->req(q.front());
+        const Column& c = s->cols[r.col];
+        take.push_back(Taken{&r, c.d_keys, c.h_keys, r.offset, r.n, r.k, r.order});
         q.pop_front();
       }
       s->slots[slot].busy = true;
     }
     Slot& sl = s->slots[slot];
-    // admission by memory: shrink the batch until it fits the slot's arena
+    // admission by memory: shrink the batch until it fits the slot's arena,
+    // staging and result buffers
     BatchBuild b;
-    size_t need = 0;
-    while (!take.empty() && !build_batch(take, kt, sl.arena, sl.arena_bytes, b, &need)) {
+    bool fits = false;
+    while (!take.empty() && !(fits = build_batch(take, kt, sl, b))) {
       if (take.size() == 1) break;
       std::lock_guard<std::mutex> lk(s->mu);
       s->gpu_q[kt].push_front(take.back().r->id);
       take.pop_back();
     }
-    const size_t stage = b.L.heads_bytes + b.rec_bytes;
-    const size_t outb = b.end - b.off_out_k;
-    if (take.empty() || need > sl.arena_bytes || stage > sl.stage_bytes || outb > sl.out_bytes) {
-      // a single request larger than a slot: it goes to the CPU path instead
-      std::lock_guard<std::mutex> lk(s->mu);
-      for (const Taken& t : take) {
-        t.r->route = 1;
-        s->cpu_q.push_back(t.r->id);
+    if (!fits) {
+      // a single request larger than a slot: the CPU route takes it when its
+      // column has a host copy; otherwise it fails (no valid host address)
+      bool any_cpu = false;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (const Taken& t : take) {
+          if (t.h_keys) {
+            t.r->route = 1;
+            ++s->n_cpu;
+            --s->n_gpu;
+            s->cpu_q.push_back(t.r->id);
+            any_cpu = true;
+          } else {
+            t.r->status = TK_ENOMEM;
+            t.r->t_start = t.r->t_done = now_ns();
+            t.r->state.store(2);
+            ++s->n_failed;
+            ++s->completed;
+          }
+        }
+        sl.busy = false;
       }
-      sl.busy = false;
-      s->cv_cpu.notify_all();
+      if (any_cpu) s->cv_cpu.notify_all();
+      s->cv_done.notify_all();
+      s->cv_batch.notify_all();
       continue;
     }
     const uint64_t t0 = now_ns();
+    const uint32_t kb = key_bytes(kt);
     // staging: zeroed query states, then the argument records
     std::memset(sl.h_stage, 0, b.L.heads_bytes);
     const MLaunch m = multi_pack(b.rec, sl.h_stage + b.L.heads_bytes, sl.arena + b.off_rec);
     int rc = TK_OK;
-    if (b.L.heads_bytes &&
+    for (size_t i = 0; rc == TK_OK && i < take.size(); ++i)
+      if (!take[i].d_keys &&
+          hipMemcpyAsync(sl.arena + b.stage_off[i], static_cast<const char*>(take[i].h_keys) + take[i].offset * kb,
+                         take[i].n * kb, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+        rc = TK_EHIP;
+    if (rc == TK_OK && b.L.heads_bytes &&
         hipMemcpyAsync(sl.arena, sl.h_stage, b.L.heads_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
       rc = TK_EHIP;
     if (rc == TK_OK && b.rec_bytes &&
@@ -302,8 +364,8 @@ void batcher_loop(tk_server* s) {
       if (hipGetLastError() != hipSuccess) rc = TK_EHIP;
     }
     if (rc == TK_OK)
-      rc = hipMemcpyAsync(sl.h_out, sl.arena + b.off_out_k, outb, hipMemcpyDeviceToHost, sl.stream) ==
-                   hipSuccess ? TK_OK : TK_EHIP;
+      rc = hipMemcpyAsync(sl.h_out, sl.arena + b.off_out_k, b.out_need, hipMemcpyDeviceToHost,
+                          sl.stream) == hipSuccess ? TK_OK : TK_EHIP;
     if (rc == TK_OK) rc = hipEventRecord(sl.done, sl.stream) == hipSuccess ? TK_OK : TK_EHIP;
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -343,13 +405,14 @@ void completer_loop(tk_server* s) {
     {
       std::lock_guard<std::mutex> lk(s->mu);
       for (size_t i = 0; i < sl.reqs.size(); ++i) {
-        Req& r = s->reqs[sl.reqs[i]];
+        Req& r = s->req(sl.reqs[i]);
         const uint64_t a = sl.out_off[i], c = sl.out_off[i + 1] - a;
         r.out_keys.assign(sl.h_out + a * kb, sl.h_out + (a + c) * kb);
         r.out_rids.resize(c);
         std::memcpy(r.out_rids.data(), sl.h_out + sl.out_rid_base + a * 8, c * 8);
         for (auto& x : r.out_rids) x += r.offset;  // local index -> column row
         if (e != hipSuccess) r.status = TK_EHIP;
+        if (r.status != TK_OK) ++s->n_failed;
         r.t_done = tdone;
         r.state.store(2);
         ++s->completed;
@@ -370,19 +433,9 @@ extern "C" int tk_server_create(const tk_server_cfg* cfg, void* arena, size_t ar
   tk_server* s = new (std::nothrow) tk_server;
   if (!s) return TK_ENOMEM;
   s->cfg = *cfg;
-  const tk_server_cfg& c = s->cfg;
-  if (c.cpu_a == 0 && c.cpu_b == 0 && c.cpu_c == 0 && c.gpu_a == 0 && c.gpu_b == 0 && c.gpu_c == 0) {
-    // no cost model given: least-squares fit of measured request times for
-    // N = 2^8 .. 2^22, K in {10, 100, 1000}, int32/int64/float32 keys, on an
-    // MI355X (device-resident keys, launch to results on the host) against the
-    // CPU route on 16 host threads
-    s->cfg.cpu_a = 1.79e-10;
-    s->cfg.cpu_b = 1.26e-8;
-    s->cfg.cpu_c = 4.36e-5;
-    s->cfg.gpu_a = 0.0;
-    s->cfg.gpu_b = 1.48e-8;
-    s->cfg.gpu_c = 5.30e-5;
-  }
+  for (int t = 0; t < 4; ++t)
+    if (all_zero(s->cfg.cost[t])) s->cfg.cost[t] = DEFAULT_COST[t];
+  if (!(s->cfg.h2d_bytes_per_s > 0)) s->cfg.h2d_bytes_per_s = DEFAULT_H2D;
   if (s->cfg.max_batch == 0) s->cfg.max_batch = 256;
   if (s->cfg.slots == 0) s->cfg.slots = 2;
   if (s->cfg.cpu_threads <= 0) s->cfg.cpu_threads = 4;
@@ -415,7 +468,7 @@ extern "C" int tk_server_create(const tk_server_cfg* cfg, void* arena, size_t ar
 
 extern "C" int tk_server_add_column(tk_server* s, const void* d_keys, const void* h_keys,
                                     uint64_t n, int key_type, uint32_t* col) {
-  if (!s || !col || key_type < 0 || key_type > 3 || (n && !d_keys)) return TK_EINVAL;
+  if (!s || !col || key_type < 0 || key_type > 3 || (n && !d_keys && !h_keys)) return TK_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
   s->cols.push_back(Column{d_keys, h_keys, n, key_type});
   *col = (uint32_t)(s->cols.size() - 1);
@@ -427,11 +480,12 @@ extern "C" int tk_server_submit(tk_server* s, uint32_t col, uint64_t offset, uin
   if (!s || !req_id || order < 0 || order > 1) return TK_EINVAL;
   const uint64_t t = now_ns();
   std::lock_guard<std::mutex> lk(s->mu);
-  if (col >= s->cols.size() || offset + n > s->cols[col].n) return TK_EINVAL;
+  if (col >= s->cols.size() || offset > s->cols[col].n || n > s->cols[col].n - offset) return TK_EINVAL;
   const Column& c = s->cols[col];
-  s->reqs.emplace_back();
-  const uint64_t id = s->reqs.size() - 1;
-  Req& r = s->reqs.back();
+  std::unique_ptr<Req> rp(new (std::nothrow) Req);
+  if (!rp) return TK_ENOMEM;
+  const uint64_t id = s->next_id++;
+  Req& r = *rp;
   r.id = id;
   r.col = col;
   r.offset = offset;
@@ -439,16 +493,20 @@ extern "C" int tk_server_submit(tk_server* s, uint32_t col, uint64_t offset, uin
   r.k = k;
   r.order = order;
   r.t_submit = t;
-  // the gate: CPU unless offloading saves more than the margin
+  // the gate: CPU unless offloading saves more than the margin; a column with
+  // no device copy pays the transfer of the request's rows on the GPU route
   int route = 0;
   if (s->cfg.gate == 2) route = 1;
   else if (s->cfg.gate == 1 && c.h_keys) {
     const uint32_t ke = (uint64_t)k < n ? k : (uint32_t)n;  // the work is min(k, n) results
-    const double saving = cpu_cost(s->cfg, n, ke) - gpu_cost(s->cfg, n, ke);
+    const tk_cost_model& m = s->cfg.cost[c.key_type];
+    const double bytes = c.d_keys ? 0.0 : (double)n * key_bytes(c.key_type);
+    const double saving = cpu_cost(m, n, ke) - gpu_cost(m, n, ke, bytes, s->cfg.h2d_bytes_per_s);
     route = saving > s->cfg.margin_ms * 1e-3 ? 0 : 1;
   }
   if (route == 1 && !c.h_keys) route = 0;
   r.route = route;
+  s->reqs.emplace(id, std::move(rp));
   ++s->submitted;
   if (route == 1) {
     ++s->n_cpu;
@@ -467,11 +525,12 @@ extern "C" int tk_server_result(tk_server* s, uint64_t id, void* h_keys, uint64_
                                 tk_req_info* info) {
   if (!s) return TK_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
-  if (id >= s->reqs.size()) return TK_EINVAL;
-  Req& r = s->reqs[id];
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return TK_EINVAL;
+  Req& r = *it->second;
   if (r.state.load() < 2) return TK_EAGAIN;
-  if (h_keys) std::memcpy(h_keys, r.out_keys.data(), r.out_keys.size());
-  if (h_rowids) std::memcpy(h_rowids, r.out_rids.data(), r.out_rids.size() * 8);
+  if (h_keys && !r.out_keys.empty()) std::memcpy(h_keys, r.out_keys.data(), r.out_keys.size());
+  if (h_rowids && !r.out_rids.empty()) std::memcpy(h_rowids, r.out_rids.data(), r.out_rids.size() * 8);
   if (info) {
     info->t_submit_ns = r.t_submit;
     info->t_start_ns = r.t_start;
@@ -480,7 +539,9 @@ extern "C" int tk_server_result(tk_server* s, uint64_t id, void* h_keys, uint64_
     info->status = r.status;
     info->count = r.out_rids.size();
   }
-  return r.status;
+  const int st = r.status;
+  s->reqs.erase(it);  // taken: the request and its results are released
+  return st;
 }
 
 extern "C" int tk_server_drain(tk_server* s) {
@@ -499,6 +560,8 @@ extern "C" int tk_server_stats(tk_server* s, tk_server_counters* st) {
   st->routed_cpu = s->n_cpu;
   st->batches = s->n_batches;
   st->batched_requests = s->n_batched;
+  st->live = s->reqs.size();
+  st->failed = s->n_failed;
   return TK_OK;
 }
 

@@ -417,28 +417,44 @@ void profile_mark(hipStream_t st, bool begin) {
 
 int profile_begin(uint32_t max_launches) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
-  for (auto e : g_prof.ev) (void)hipEventDestroy(e);
+  for (auto e : g_prof.ev)
+    if (e) (void)hipEventDestroy(e);
   g_prof.ev.assign(2 * (size_t)max_launches, nullptr);
   for (auto& e : g_prof.ev)
-    if (hipEventCreate(&e) != hipSuccess) return TK_EHIP;
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& x : g_prof.ev)
+        if (x) (void)hipEventDestroy(x);
+      g_prof.ev.clear();
+      return TK_EHIP;
+    }
   g_prof.used = 0;
   g_prof.max = max_launches;
   g_prof.on = true;
   return TK_OK;
 }
 
+// Reads the recorded pairs and releases the events, so that no HIP object of
+// the library outlives the measurement (nothing is left for process teardown).
 int profile_end(double* total_ms, uint64_t* launches) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.on = false;
   double tot = 0;
-  for (uint32_t i = 0; i + 1 < g_prof.used; i += 2) {
-    if (hipEventSynchronize(g_prof.ev[i + 1]) != hipSuccess) return TK_EHIP;
+  int rc = TK_OK;
+  for (uint32_t i = 0; i + 1 < g_prof.used && rc == TK_OK; i += 2) {
     float ms = 0;
-    if (hipEventElapsedTime(&ms, g_prof.ev[i], g_prof.ev[i + 1]) != hipSuccess) return TK_EHIP;
+    if (hipEventSynchronize(g_prof.ev[i + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, g_prof.ev[i], g_prof.ev[i + 1]) != hipSuccess)
+      rc = TK_EHIP;
     tot += ms;
   }
+  const uint64_t n = g_prof.used / 2;
+  for (auto e : g_prof.ev)
+    if (e) (void)hipEventDestroy(e);
+  g_prof.ev.clear();
+  g_prof.used = 0;
+  if (rc != TK_OK) return rc;
   if (total_ms) *total_ms = tot;
-  if (launches) *launches = g_prof.used / 2;
+  if (launches) *launches = n;
   return TK_OK;
 }
 

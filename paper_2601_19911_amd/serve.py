@@ -13,12 +13,19 @@ from . import TK_KEY_F32, TK_KEY_F64, TK_KEY_I32, TK_KEY_I64, TopKError, check, 
 GATE_GPU, GATE_COST, GATE_CPU = 0, 1, 2
 
 
+COST_FIELDS = ("cpu_a", "cpu_b", "cpu_c", "gpu_a", "gpu_b", "gpu_c")
+KEY_NAMES = {TK_KEY_I32: "int32", TK_KEY_I64: "int64", TK_KEY_F32: "float32", TK_KEY_F64: "float64"}
+
+
+class tk_cost_model(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in COST_FIELDS]
+
+
 class tk_server_cfg(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_uint32), ("slots", ctypes.c_uint32),
                 ("window_us", ctypes.c_double), ("gate", ctypes.c_int32),
                 ("margin_ms", ctypes.c_double), ("cpu_threads", ctypes.c_int32),
-                ("cpu_a", ctypes.c_double), ("cpu_b", ctypes.c_double), ("cpu_c", ctypes.c_double),
-                ("gpu_a", ctypes.c_double), ("gpu_b", ctypes.c_double), ("gpu_c", ctypes.c_double)]
+                ("cost", tk_cost_model * 4), ("h2d_bytes_per_s", ctypes.c_double)]
 
 
 class tk_req_info(ctypes.Structure):
@@ -29,7 +36,24 @@ class tk_req_info(ctypes.Structure):
 
 class tk_server_counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "routed_gpu",
-                                               "routed_cpu", "batches", "batched_requests")]
+                                               "routed_cpu", "batches", "batched_requests",
+                                               "live", "failed")]
+
+
+def cost_models(cost):
+    """The four per-key-type models of tk_server_cfg from ``cost``: None (the
+    library's defaults), one dict of the six coefficients (every key type), or
+    a dict from key-type name ("int32", "int64", "float32", "float64") to such
+    a dict (missing types take the default)."""
+    arr = (tk_cost_model * 4)()
+    if not cost:
+        return arr
+    per_type = all(isinstance(v, dict) for v in cost.values())
+    for code, name in KEY_NAMES.items():
+        c = cost.get(name) if per_type else cost
+        if c:
+            arr[code] = tk_cost_model(*[float(c.get(f, 0.0)) for f in COST_FIELDS])
+    return arr
 
 
 _bound = False
@@ -67,14 +91,11 @@ class Server:
     optional host mirrors (numpy arrays) for the CPU route."""
 
     def __init__(self, arena_bytes=1 << 30, max_batch=256, slots=2, window_us=0.0, gate=GATE_GPU,
-                 margin_ms=0.0, cpu_threads=4, cost=None, device="cuda"):
+                 margin_ms=0.0, cpu_threads=4, cost=None, h2d_bytes_per_s=0.0, device="cuda"):
         import torch
         L = _bind()
-        cost = cost or {}
         self.cfg = tk_server_cfg(max_batch, slots, window_us, gate, margin_ms, cpu_threads,
-                                 cost.get("cpu_a", 0.0), cost.get("cpu_b", 0.0),
-                                 cost.get("cpu_c", 0.0), cost.get("gpu_a", 0.0),
-                                 cost.get("gpu_b", 0.0), cost.get("gpu_c", 0.0))
+                                 cost_models(cost), h2d_bytes_per_s)
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
         h = ctypes.c_void_p()
         check(L.tk_server_create(ctypes.byref(self.cfg), self.arena.data_ptr(), arena_bytes,
@@ -82,16 +103,27 @@ class Server:
         self._h = h
         self.cols = []
 
-    def add_column(self, d_keys, h_keys=None):
+    def add_column(self, d_keys=None, h_keys=None):
+        """A column from a device tensor and/or a host array (numpy, or a
+        pinned torch CPU tensor); either may be None, not both."""
         c = ctypes.c_uint32()
-        kc = key_code(d_keys.dtype)
+        if d_keys is None and h_keys is None:
+            raise ValueError("a column needs a device or a host copy")
         hptr = None
         if h_keys is not None:
-            h_keys = np.ascontiguousarray(h_keys)
-            assert key_code(h_keys.dtype) == kc and len(h_keys) == d_keys.shape[0]
-            hptr = h_keys.ctypes.data
-        check(_bind().tk_server_add_column(self._h, d_keys.data_ptr(), hptr, d_keys.shape[0], kc,
-                                           ctypes.byref(c)), "tk_server_add_column")
+            if not isinstance(h_keys, np.ndarray):  # a torch CPU tensor (pinned for async copies)
+                hptr = h_keys.data_ptr()
+                kc, n = key_code(h_keys.dtype), h_keys.shape[0]
+            else:
+                h_keys = np.ascontiguousarray(h_keys)
+                hptr = h_keys.ctypes.data
+                kc, n = key_code(h_keys.dtype), len(h_keys)
+        if d_keys is not None:
+            kc, n = key_code(d_keys.dtype), d_keys.shape[0]
+            if h_keys is not None:
+                assert key_code(h_keys.dtype) == kc and h_keys.shape[0] == n
+        check(_bind().tk_server_add_column(self._h, None if d_keys is None else d_keys.data_ptr(),
+                                           hptr, n, kc, ctypes.byref(c)), "tk_server_add_column")
         self.cols.append((d_keys, h_keys, kc))
         return c.value
 
@@ -130,6 +162,20 @@ class Server:
         check(rc, "tk_server_result")
         return ok[:info.count], orr[:info.count], info
 
+    def result_status(self, req, col, k_eff):
+        """(status, info) of a finished request without raising on its error
+        status; None while it runs.  Takes (releases) the request."""
+        kdt = {TK_KEY_I32: np.int32, TK_KEY_I64: np.int64, TK_KEY_F32: np.float32,
+               TK_KEY_F64: np.float64}[self.cols[col][2]]
+        ok = np.empty(max(k_eff, 1), dtype=kdt)
+        orr = np.empty(max(k_eff, 1), dtype=np.uint64)
+        info = tk_req_info()
+        rc = _bind().tk_server_result(self._h, req, ok.ctypes.data, orr.ctypes.data,
+                                      ctypes.byref(info))
+        if rc == 1:
+            return None
+        return rc, info
+
     def stats(self):
         st = tk_server_counters()
         check(_bind().tk_server_stats(self._h, ctypes.byref(st)))
@@ -141,6 +187,11 @@ class Server:
             self._h = None
 
     def __del__(self):
+        # no HIP calls while the interpreter shuts down: the runtime (or a
+        # profiler attached to it) may already be finalized; close() explicitly
+        import sys
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -5,7 +5,9 @@ with a known answer."""
 import numpy as np
 import pytest
 
-from bench_suites import crossover_n, fit_costs, gate_route_gpu, measured_break_even, predicted_break_even
+from paper_2601_19911_amd.gate import break_even as predicted_break_even
+from paper_2601_19911_amd.gate import crossover_n, fit_costs, measured_break_even
+from paper_2601_19911_amd.gate import route_gpu as gate_route_gpu
 
 TRUE = {"cpu_a": 2.0e-10, "cpu_b": 1.0e-8, "cpu_c": 4.0e-5, "gpu_a": 1.0e-12, "gpu_b": 2.0e-8,
         "gpu_c": 6.0e-5}
@@ -30,15 +32,44 @@ def test_fit_recovers_noise_free_models():
         assert got[key] == pytest.approx(v, rel=1e-6, abs=1e-15), key
 
 
-@pytest.mark.parametrize("k", [1, 10, 100, 1000, 10000])
+@pytest.mark.parametrize("k", [1, 10, 100, 1000, 10000, 100000])
 @pytest.mark.parametrize("margin", [0.0, 2e-5])
 def test_break_even_is_where_saving_meets_margin(k, margin):
+    """On either side of N = k (the model's K is min(k, N)): the saving equals
+    the margin at the predicted N*, and the gate switches there."""
     n_star = predicted_break_even(TRUE, k, margin)
-    if n_star > k:  # K = min(k, N) is constant above k: the saving is linear there
-        cpu, gpu = _times(n_star, k)
+    assert n_star is not None and n_star >= 1.0
+    cpu, gpu = _times(n_star, k)
+    if n_star > 1.0:
         assert cpu - gpu == pytest.approx(margin, abs=1e-12)
-        assert gate_route_gpu(TRUE, [n_star * 1.01], [k], margin)[0]
         assert not gate_route_gpu(TRUE, [n_star * 0.99], [k], margin)[0]
+    assert gate_route_gpu(TRUE, [n_star * 1.01], [k], margin)[0]
+    # offloaded everywhere above N*
+    grid = np.geomspace(n_star * 1.01, 1 << 30, 200)
+    assert gate_route_gpu(TRUE, grid, np.full(grid.shape, k), margin).all()
+
+
+def test_break_even_below_k():
+    """A model whose crossing lies below k: before the fix the predictor
+    clamped it to 1 (it held K = k below N = k)."""
+    c = dict(TRUE, cpu_b=4.0e-8, gpu_b=1.0e-8)   # large K strongly favours the GPU
+    k = 10000
+    n_star = predicted_break_even(c, k)
+    assert 1.0 < n_star < k
+    n = np.array([n_star * 0.999, n_star * 1.001])
+    cpu, gpu = [np.array(x) for x in zip(*[_times(v, k, c) for v in n])]
+    assert cpu[0] - gpu[0] < 0 < cpu[1] - gpu[1]
+
+
+def test_break_even_with_transfer_term():
+    """A host-resident column pays B = N x key bytes over the host link: the
+    break-even moves up, and vanishes when the link is slower per key than the
+    CPU's scan."""
+    k = 100
+    base = predicted_break_even(TRUE, k)
+    with_b = predicted_break_even(TRUE, k, bytes_per_key=4.0, h2d_bytes_per_s=5.0e10)
+    assert with_b > base
+    assert predicted_break_even(TRUE, k, bytes_per_key=8.0, h2d_bytes_per_s=1.0e10) is None
 
 
 def test_route_caps_k_at_n():

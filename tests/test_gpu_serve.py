@@ -132,7 +132,7 @@ def test_gate_routes_follow_cost_model(margin_us):
     C_cpu - C_gpu at K = min(k, N), exceeds the margin (paper sec. II-B), and
     either route returns the oracle's result."""
     import torch
-    from bench_suites import gate_route_gpu
+    from paper_2601_19911_amd.gate import route_gpu as gate_route_gpu
     ncol = 1 << 20
     cols = _columns(ncol)
     host = [h for _, h in cols]
@@ -186,3 +186,74 @@ def test_served_float64_column(gate):
         ek, er = oracle.topk(h[off:off + n], None, k, o, rid_dtype=np.uint64)
         assert_same(ok, orr, ek, er + np.uint64(off), what=f"float64 served n={n} k={k} o={o}")
     srv.close()
+
+
+def test_oversize_request_on_gpu_only_column_fails_cleanly():
+    """A request larger than a slot, on a column with no host copy and at an
+    offset > 0 (where a CPU route would read an invalid host address), comes
+    back with TK_ENOMEM and no results; the requests around it are served and
+    equal the oracle; every request is released once taken."""
+    import torch
+    ncol = 1 << 22
+    h = inputgen.generate(inputgen.KIND_U_I32, 5, ncol)
+    srv = Server(arena_bytes=8 << 20, max_batch=8, slots=2, gate=GATE_GPU)  # 4 MiB per slot
+    cid = srv.add_column(to_dev(h))  # device copy only
+    torch.cuda.synchronize()
+    # K = 10^6 of 3 * 2^20 rows: 12 MB of results alone, past the slot's 4 MiB
+    big = (12345, 3 << 20, 1_000_000, 0)
+    small = [(int(o), 1 << 16, 10, int(o) & 1) for o in np.linspace(7, ncol - (1 << 16), 12)]
+    ids = [srv.submit(cid, *small[i]) for i in range(6)]
+    bid = srv.submit(cid, *big)
+    ids += [srv.submit(cid, *small[i]) for i in range(6, 12)]
+    srv.drain()
+    st = srv.stats()
+    say(f"oversize: {st}")
+    assert st["failed"] == 1 and st["completed"] == 13 and st["live"] == 13
+    rc, info = srv.result_status(bid, cid, big[2])
+    assert rc == tk.TK_ENOMEM and info.status == tk.TK_ENOMEM and info.count == 0
+    for (off, n, k, o), r in zip(small, ids):
+        ok, orr, info = srv.result(r, cid, min(k, n))
+        assert info.route == 0
+        ek, er = oracle.topk(h[off:off + n], None, k, o, rid_dtype=np.uint64)
+        assert_same(ok, orr, ek, er + np.uint64(off), what=f"small off={off} n={n} k={k} o={o}")
+    assert srv.stats()["live"] == 0
+    srv.close()
+
+
+def test_served_host_resident_column_and_transfer_gate():
+    """A column held only in pinned host memory: the GPU route copies each
+    request's rows into the slot's arena.  With the cost gate the routing
+    follows the models with the transfer term B = N x key bytes (paper
+    sec. II-B); either route equals the oracle."""
+    import torch
+    from paper_2601_19911_amd.gate import route_gpu
+    ncol = 1 << 22
+    h = inputgen.generate(inputgen.KIND_U_I64, 31, ncol)
+    pinned = torch.from_numpy(h).pin_memory()
+    cost = {"cpu_a": 1.0e-9, "cpu_b": 1.3e-8, "cpu_c": 4.4e-5, "gpu_a": 0.0, "gpu_b": 1.5e-8,
+            "gpu_c": 5.3e-5}
+    h2d = 2.0e10
+    rng = np.random.default_rng(41)
+    reqs = []
+    for _ in range(80):
+        n = int(2 ** rng.uniform(10, 21))
+        reqs.append((int(rng.integers(0, ncol - n + 1)), n, int(rng.choice([10, 100, 1000])),
+                     int(rng.integers(0, 2))))
+    for gate in (GATE_GPU, GATE_COST):
+        srv = Server(arena_bytes=256 << 20, max_batch=16, slots=2, gate=gate, cost=cost,
+                     h2d_bytes_per_s=h2d)
+        cid = srv.add_column(None, pinned)  # host-resident: no device copy
+        rid = [srv.submit(cid, *r) for r in reqs]
+        srv.drain()
+        want = route_gpu(cost, [r[1] for r in reqs], [r[2] for r in reqs], 0.0,
+                         bytes_per_key=8.0, h2d_bytes_per_s=h2d)
+        if gate == GATE_COST:
+            say(f"host-resident column: {int(want.sum())} of {len(reqs)} modelled to offload")
+            assert 0 < int(want.sum()) < len(reqs)
+        for i, ((off, n, k, o), r) in enumerate(zip(reqs, rid)):
+            ok, orr, info = srv.result(r, cid, min(k, n))
+            assert info.route == (0 if (gate == GATE_GPU or want[i]) else 1)
+            ek, er = oracle.topk(h[off:off + n], None, k, o, rid_dtype=np.uint64)
+            assert_same(ok, orr, ek, er + np.uint64(off), what=f"host column n={n} k={k} o={o} gate={gate}")
+        assert srv.stats()["live"] == 0
+        srv.close()
