@@ -13,6 +13,10 @@ and the library never imports it.
   bit pattern, an independent formulation of IEEE 754 totalOrder.
 * :func:`check_invariants` tests the properties every correct result has at
   any size.
+* :func:`join` calls ``oracle_join`` (join.cpp), the plain definition of the
+  matching primitive (paper sec. III-B): every (probe row-id, build row-id)
+  pair whose keys are equal, sorted by (probe row-id, build row-id);
+  :func:`brute_join` is the nested loop over all pairs, for tiny inputs.
 """
 
 from __future__ import annotations
@@ -21,11 +25,13 @@ import ctypes
 import os
 import struct
 import subprocess
+import threading
 
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.cpp")
+SRCS = [SRC, os.path.join(HERE, "join.cpp")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 KEY_CODE = {np.dtype(np.int32): 0, np.dtype(np.int64): 1, np.dtype(np.float32): 2,
@@ -37,7 +43,7 @@ _lib = None
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", SRC, "-o", LIB + ".tmp"]
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", *SRCS, "-o", LIB + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("building liboracle.so failed:\n" + r.stderr)
@@ -50,7 +56,7 @@ def build(verbose: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(f) for f in SRCS):
             build()
         L = ctypes.CDLL(LIB)
         vp, u64 = ctypes.c_void_p, ctypes.c_uint64
@@ -60,6 +66,10 @@ def _load():
         L.oracle_topk_batched.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint32, ctypes.c_int,
                                           ctypes.c_int, vp, vp]
         L.oracle_topk_batched.restype = ctypes.c_int
+        L.oracle_join.argtypes = [vp, vp, u64, ctypes.c_int, vp, vp, u64, ctypes.c_int, ctypes.c_int]
+        L.oracle_join.restype = ctypes.c_int64
+        L.oracle_join_fetch.argtypes = [vp, vp]
+        L.oracle_join_fetch.restype = None
         _lib = L
     return _lib
 
@@ -115,6 +125,48 @@ def topk_batched(keys: np.ndarray, rowids: np.ndarray | None, offsets: np.ndarra
     if rc != 0:
         raise ValueError("oracle_topk_batched rejected its arguments")
     return ok, orr
+
+
+JOIN_KEY_CODE = {np.dtype(np.int32): 0, np.dtype(np.int64): 1}
+_join_lock = threading.Lock()
+
+
+def join(build_keys: np.ndarray, build_rowids: np.ndarray | None, probe_keys: np.ndarray,
+         probe_rowids: np.ndarray | None):
+    """Inner equi-join matches: (probe_rowids, build_rowids), both uint64,
+    sorted by (probe row-id, build row-id).  ``None`` row-ids mean position."""
+    bk = np.ascontiguousarray(build_keys)
+    pk = np.ascontiguousarray(probe_keys)
+    assert bk.dtype == pk.dtype
+    kc = JOIN_KEY_CODE[bk.dtype]
+    br = None if build_rowids is None else np.ascontiguousarray(build_rowids)
+    pr = None if probe_rowids is None else np.ascontiguousarray(probe_rowids)
+    brc = 0 if br is None else RID_CODE[br.dtype]
+    prc = 0 if pr is None else RID_CODE[pr.dtype]
+    L = _load()
+    with _join_lock:
+        m = L.oracle_join(_ptr(bk), _ptr(br), bk.shape[0], brc, _ptr(pk), _ptr(pr), pk.shape[0],
+                          prc, kc)
+        if m < 0:
+            raise ValueError("oracle_join rejected its arguments")
+        op = np.empty(m, dtype=np.uint64)
+        ob = np.empty(m, dtype=np.uint64)
+        L.oracle_join_fetch(op.ctypes.data, ob.ctypes.data)
+    return op, ob
+
+
+def brute_join(build_keys, build_rowids, probe_keys, probe_rowids):
+    """Nested loop over every (probe, build) pair: the definition itself."""
+    nb, np_ = len(build_keys), len(probe_keys)
+    brid = list(range(nb)) if build_rowids is None else [int(r) for r in build_rowids]
+    prid = list(range(np_)) if probe_rowids is None else [int(r) for r in probe_rowids]
+    out = []
+    for j in range(np_):
+        for i in range(nb):
+            if int(probe_keys[j]) == int(build_keys[i]):
+                out.append((prid[j], brid[i]))
+    out.sort()
+    return [p for p, _ in out], [b for _, b in out]
 
 
 # ---- pure-Python brute force (tiny inputs) --------------------------------------------------
