@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmitopk.so")
 TK_KEY_I32, TK_KEY_I64, TK_KEY_F32, TK_KEY_F64 = 0, 1, 2, 3
 TK_RID_U32, TK_RID_U64 = 0, 1
 TK_DESC, TK_ASC = 0, 1
+TK_OK, TK_EINVAL, TK_ENOMEM, TK_EHIP, TK_EUNSUPPORTED, TK_EDEVICE, TK_EAGAIN = 0, -1, -2, -3, -4, -5, 1
 
 _lib = None
 
@@ -68,6 +69,10 @@ def lib():
         L.tk_profile_end.restype = i32
         L.tk_read_probe.argtypes = [vp, u64, ctypes.c_uint32, vp, vp]
         L.tk_read_probe.restype = i32
+        L.tk_sort_workspace_size.argtypes = [u64, i32, i32]
+        L.tk_sort_workspace_size.restype = ctypes.c_size_t
+        L.tk_sort.argtypes = [vp, vp, u64, i32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tk_sort.restype = i32
         L.tk_status_string.argtypes = [i32]
         L.tk_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -170,6 +175,38 @@ def topk(keys, k: int, rowids=None, order="desc", out_keys=None, out_rowids=None
                        _ptr(out_keys), _ptr(out_rowids), ctypes.byref(cnt),
                        workspace.data_ptr(), workspace.numel(), _stream_handle(stream))
     check(rc, "tk_topk")
+    return out_keys, out_rowids
+
+
+def sort(keys, rowids=None, order="desc", out_keys=None, out_rowids=None, rid_dtype=None,
+         workspace=None, stream=None, want_keys: bool = True):
+    """ORDER BY key without LIMIT: every pair of device tensor ``keys``, best
+    first (equal to ``topk`` with k = n).  Returns ``(out_keys, out_rowids)``."""
+    import torch
+    if not keys.is_cuda:
+        raise TopKError("keys must be a device tensor")
+    keys = keys.contiguous()
+    n = keys.shape[0]
+    kc = key_code(keys.dtype)
+    if rowids is not None:
+        rowids = rowids.contiguous()
+        assert rowids.shape[0] == n and rowids.is_cuda
+        rdt = rowids.dtype
+    else:
+        rdt = rid_dtype if rid_dtype is not None else (torch.uint32 if n <= (1 << 32) else torch.uint64)
+    rc_ = rid_code(rdt)
+    dev = keys.device
+    if out_keys is None and want_keys:
+        out_keys = torch.empty(n, dtype=keys.dtype, device=dev)
+    if out_rowids is None:
+        out_rowids = torch.empty(n, dtype=rdt, device=dev)
+    ws_bytes = int(lib().tk_sort_workspace_size(n, kc, rc_))
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    rc = lib().tk_sort(_ptr(keys) if n else None, _ptr(rowids), n, kc, rc_, order_code(order),
+                       _ptr(out_keys), _ptr(out_rowids), workspace.data_ptr(), workspace.numel(),
+                       _stream_handle(stream))
+    check(rc, "tk_sort")
     return out_keys, out_rowids
 
 

@@ -4,6 +4,7 @@ device key buffer in one engine launch.  Argument marshalling only."""
 from __future__ import annotations
 
 import ctypes
+import sys
 
 import numpy as np
 
@@ -112,11 +113,11 @@ class Plan:
             _bind().tk_plan_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP calls while the interpreter shuts down: the runtime (or a
-        # profiler attached to it) may already be finalized; close() explicitly
-        import sys
-        if sys.is_finalizing():
+        # profiler attached to it) may already be finalized; close() explicitly.
+        # The check is bound at definition time: imports fail during shutdown.
+        if _finalizing():
             return
         try:
             self.close()

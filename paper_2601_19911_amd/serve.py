@@ -5,6 +5,7 @@ Argument marshalling only; the request loop runs in C++ threads."""
 from __future__ import annotations
 
 import ctypes
+import sys
 
 import numpy as np
 
@@ -186,11 +187,11 @@ class Server:
             _bind().tk_server_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP calls while the interpreter shuts down: the runtime (or a
-        # profiler attached to it) may already be finalized; close() explicitly
-        import sys
-        if sys.is_finalizing():
+        # profiler attached to it) may already be finalized; close() explicitly.
+        # The check is bound at definition time: imports fail during shutdown.
+        if _finalizing():
             return
         try:
             self.close()
