@@ -9,6 +9,8 @@
     python bench_suites.py gate              cost-model fit, predicted vs measured break-even N,
                                              margin sweep of the gate on the serving mixture
     python bench_suites.py e2e               headline query with pinned H2D and D2H included
+    python bench_suites.py join              key-only hash-join probe (matching primitive):
+                                             build and probe times, probes/s, bytes per probe
 
 Each suite prints one JSON object per measurement on stdout.  Every input is
 synthetic and seeded (inputgen); every GPU result that a suite reports is
@@ -568,9 +570,70 @@ def suite_gate(a):
     suite_c5(a)
 
 
+# ---- matching primitive: key-only hash-join probe ----------------------------------------------
+
+def suite_join(a):
+    """Build 2^b int32/int64 keys (uniform; int64 all distinct), probe 2^26
+    foreign keys drawn from twice the build's index range (hit rate 1/2),
+    row-ids implicit (uint32).  Times the build and the probe with events on
+    the launch stream; the first probe's pairs are compared with the oracle."""
+    torch = _torch()
+    import inputgen
+    import oracle
+    from inputgen import native as gen
+    from paper_2601_19911_amd.join import join_build, join_probe
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream()
+    cases = [(np.int64, 24), (np.int64, 20), (np.int32, 22)] if not a.quick else [(np.int64, 20)]
+    np_ = 1 << a.join_probe_log2
+    for dt, lb in cases:
+        nb = 1 << lb
+        seed = inputgen.config_seed(6, lb)
+        bkind = inputgen.KIND_U_I64 if dt == np.int64 else inputgen.KIND_U_I32
+        pkind = inputgen.KIND_JOIN_FK_I64 if dt == np.int64 else inputgen.KIND_JOIN_FK_I32
+        bk_h = gen.host_fill(bkind, seed, nb)
+        pk_h = gen.host_fill(pkind, seed, np_, n_total=2 * nb)
+        bk, pk = torch.from_numpy(bk_h).to(dev), torch.from_numpy(pk_h).to(dev)
+        t = join_build(bk)
+        op, ob, cnt = join_probe(t, pk)
+        torch.cuda.synchronize()
+        m = int(cnt.view(torch.int64).item())
+        if m > op.numel():
+            op, ob, cnt = join_probe(t, pk, capacity=m)
+            torch.cuda.synchronize()
+        gp, gb = dev_view_np(op)[:m].astype(np.uint64), dev_view_np(ob)[:m].astype(np.uint64)
+        o = np.lexsort((gb, gp))
+        ep, eb = oracle.join(bk_h, None, pk_h, None)
+        ok = bool(gp.shape == ep.shape and np.array_equal(gp[o], ep) and np.array_equal(gb[o], eb))
+        bt, pt = [], []
+        for _ in range(a.reps):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(st)
+            t = join_build(bk, table=t.buf)
+            e1.record(st)
+            join_probe(t, pk, capacity=op.numel(), out_probe=op, out_build=ob, count=cnt)
+            e2.record(st)
+            torch.cuda.synchronize()
+            bt.append(e0.elapsed_time(e1))
+            pt.append(e1.elapsed_time(e2))
+        kb = np.dtype(dt).itemsize
+        slot_b = 16 if dt == np.int64 else 8
+        probe_ms = float(np.median(pt))
+        # bytes per probe: the key, one slot, and the matched pairs written
+        alg = np_ * (kb + slot_b) + m * 8
+        emit({"suite": "join", "key_dtype": np.dtype(dt).name, "n_build": nb, "n_probe": np_,
+              "hit_rate_expected": 0.5, "matches": m, "table_bytes": int(t.buf.numel()),
+              "slots": t.slots, "build_ms": float(np.median(bt)), "probe_ms": probe_ms,
+              "probe_ms_p95": pct(pt, 95), "probes_per_s": np_ / (probe_ms * 1e-3),
+              "build_keys_per_s": nb / (float(np.median(bt)) * 1e-3),
+              "alg_bytes_per_probe": alg / np_, "probe_alg_gbs": alg / (probe_ms * 1e-3) / 1e9,
+              "probe_frac_of_peak": alg / (probe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "equal_to_oracle": ok, "reps": a.reps})
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("suite", choices=["c2", "c3", "c4", "c5", "crossover", "gate", "e2e"])
+    ap.add_argument("suite", choices=["c2", "c3", "c4", "c5", "crossover", "gate", "e2e", "join"])
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--q", type=int, default=4096)
     ap.add_argument("--n-hi-log2", type=float, default=24.0)
@@ -599,8 +662,9 @@ def main():
     ap.add_argument("--bisect", type=int, default=4, help="gate: bisections of each break-even")
     ap.add_argument("--fit-log2", type=int, default=20, help="gate: largest N of the model fit")
     ap.add_argument("--fit-lo-log2", type=int, default=10, help="gate: smallest N of the model fit")
+    ap.add_argument("--join-probe-log2", type=int, default=26, help="join: probe keys (log2)")
     a = ap.parse_args()
-    {"c2": suite_c2, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5, "crossover": suite_crossover,
+    {"join": suite_join, "c2": suite_c2, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5, "crossover": suite_crossover,
      "gate": suite_gate, "e2e": suite_e2e}[a.suite](a)
 
 

@@ -297,6 +297,81 @@ int tk_profile_end(double* total_ms, uint64_t* launches);
  * asynchronous; time it with events on `stream`.  TK_EINVAL on a bad argument. */
 int tk_read_probe(const void* buf, uint64_t bytes, uint32_t wg_per_cu, void* sink, void* stream);
 
+/* ---- Full sort: ORDER BY key without LIMIT ---------------------------------------------------
+ * The query template of sec. V-B with K = N: every pair, in the order every
+ * Top-K call uses (key descending or ascending, equal keys by ascending
+ * row-id), written as out_keys[0..n) / out_rowids[0..n).  The result equals
+ * tk_topk with k = n.  Least-significant-digit radix sort on 8-bit digits of the
+ * order-preserving key image: 4 passes for 32-bit keys, 8 for 64-bit, plus one
+ * per row-id byte when explicit row-ids are given (their order then decides
+ * ties; with rowids == NULL the input order is the row-id order).  Each pass
+ * reads and writes every pair once more; nothing waits across workgroups. */
+/* Device workspace bytes for n pairs (0 on a bad type): two ping-pong copies of
+ * the keys and row-ids, and 1 KiB of digit counts per 4096 pairs. */
+size_t tk_sort_workspace_size(uint64_t n, int key_type, int rid_type);
+/* keys: n device keys; rowids: n device row-ids of rid_type or NULL (row-id =
+ * position); out_keys: n keys or NULL; out_rowids: n row-ids of rid_type
+ * (required); workspace: >= tk_sort_workspace_size bytes, 256-byte aligned,
+ * scratch until the stream passes the call.  Inputs and outputs must not
+ * overlap the workspace.  Stream-ordered and asynchronous; n = 0 enqueues
+ * nothing.  TK_EINVAL on a bad argument (nothing enqueued). */
+int tk_sort(const void* keys, const void* rowids, uint64_t n, int key_type, int rid_type,
+            int order, void* out_keys, void* out_rowids, void* workspace, size_t workspace_bytes,
+            void* stream);
+
+/* ---- Matching primitive: key-only hash-join probe (paper sec. III-B) ---------------------
+ * The probe phase of an inner equi-join done key-only, as sec. III-B states it:
+ * the build side's (key, row-id) pairs go into a device hash table, the probe
+ * keys are looked up in parallel, and only matched pointers come back (sec.
+ * II-C, "Processing"); the host late-materializes the rows.  The result is the
+ * multiset of pairs (probe row-id, build row-id) with probe_key == build_key,
+ * one per equal (probe row, build row), returned in no particular order.  Keys
+ * are int32 or int64 and compare by numeric equality (float keys:
+ * TK_EUNSUPPORTED).  Row-ids may be NULL on either side (row-id = position).
+ *
+ * The table lives in a caller-owned device buffer; tk_join_table describes it
+ * (a plain struct the caller keeps; the library allocates nothing).  One build
+ * serves any number of probes, concurrent ones included, while the buffer
+ * stays untouched. */
+typedef struct {
+  void* table;           /* the device buffer given to tk_join_build */
+  uint64_t table_bytes;  /* its size */
+  uint64_t n_build;      /* build pairs */
+  uint64_t slots;        /* hash slots: a power of two >= 2 * n_build (load <= 1/2) */
+  int32_t key_type;      /* TK_KEY_I32 or TK_KEY_I64 */
+  int32_t rid_type;      /* build row-id type, also the type of out_build_rowids */
+} tk_join_table;
+
+/* Device bytes of the table for n_build pairs (0 on a bad type or n_build > 2^31):
+ * a 256-byte header, the slots (8 bytes each for int32 keys with uint32 row-ids,
+ * 16 bytes otherwise) and room for n_build row-ids. */
+size_t tk_join_table_size(uint64_t n_build, int key_type, int rid_type);
+/* Builds the table from n_build build pairs (stream-ordered, asynchronous).
+ *   keys     device array of n_build int32/int64 keys
+ *   rowids   device array of n_build row-ids of rid_type, or NULL (row-id = position)
+ *   table    device buffer of >= tk_join_table_size bytes, 256-byte aligned, needing
+ *            no initialization (the build clears it); reserved until the last probe
+ *            that reads it has run
+ *   out      host descriptor, filled before return
+ * TK_EUNSUPPORTED for float keys or n_build > 2^31; TK_EINVAL for other bad
+ * arguments (nothing is enqueued then). */
+int tk_join_build(const void* keys, const void* rowids, uint64_t n_build, int key_type,
+                  int rid_type, void* table, size_t table_bytes, tk_join_table* out, void* stream);
+/* Probes the table with n_probe keys (of the table's key type); stream-ordered,
+ * asynchronous.
+ *   rowids            device array of n_probe probe row-ids of rid_type, or NULL
+ *   out_probe_rowids  device array of `capacity` rid_type row-ids
+ *   out_build_rowids  device array of `capacity` row-ids of the table's rid_type
+ *   capacity          pairs the outputs hold (0: count only; the outputs may be NULL)
+ *   d_count           device uint64, set to the number of matched pairs M once the
+ *                     stream passes the call (the library zeroes it first)
+ * min(M, capacity) pairs are written; when M > capacity the written ones are
+ * an arbitrary subset and the caller probes again with capacity >= M.  Returns
+ * TK_OK or TK_EINVAL (nothing enqueued). */
+int tk_join_probe(const tk_join_table* table, const void* keys, const void* rowids,
+                  uint64_t n_probe, int rid_type, void* out_probe_rowids, void* out_build_rowids,
+                  uint64_t capacity, uint64_t* d_count, void* stream);
+
 /* Human-readable name of a tk_status_t value. */
 const char* tk_status_string(int status);
 

@@ -28,6 +28,12 @@ payload, sec. V-A; these synthetic inputs stand in for it):
 * presorted float32:  floor(i * 2^24 / n) * 2^-24
 * presorted int64:    floor(i * 2^24 / n) - 2^23
 * float64 payload in [0, 1):  (h >> 11) * 2^-53
+* join probe keys (foreign keys into a build side generated as uniform int32 or
+  int64 with the same seed):  key_j = build recipe at index (h'_j mod R), with
+  h' the stream of seed + 1 and R = n_total.  Index i < n_build is a hit on
+  build row i; for int64 an index i >= n_build gives a key that no build row
+  holds (SplitMix64 outputs of distinct indices are distinct), so the hit rate
+  is n_build / R in expectation.
 """
 
 from __future__ import annotations
@@ -52,6 +58,8 @@ KIND_IOTA_U32 = 7
 KIND_IOTA_U64 = 8
 KIND_PAYLOAD_F64 = 9
 KIND_ZIPF_I32 = 10
+KIND_JOIN_FK_I32 = 11
+KIND_JOIN_FK_I64 = 12
 KIND_U_F64 = KIND_PAYLOAD_F64  # uniform float64 keys in [0, 1): the same 2^-53 grid
 
 KIND_DTYPE = {
@@ -66,6 +74,8 @@ KIND_DTYPE = {
     KIND_IOTA_U64: np.uint64,
     KIND_PAYLOAD_F64: np.float64,
     KIND_ZIPF_I32: np.int32,
+    KIND_JOIN_FK_I32: np.int32,
+    KIND_JOIN_FK_I64: np.int64,
 }
 
 
@@ -128,6 +138,16 @@ def generate(kind: int, seed: int, n: int, start: int = 0, n_total: int | None =
         return ((h >> np.uint64(40)).astype(np.float32) * np.float32(2.0 ** -24)).astype(np.float32)
     if kind == KIND_PAYLOAD_F64:
         return _unit53(h)
+    if kind in (KIND_JOIN_FK_I32, KIND_JOIN_FK_I64):
+        idx = splitmix64(seed + 1, start, n) % np.uint64(n_total)
+        with np.errstate(over="ignore"):
+            z = np.uint64(seed % (1 << 64)) + (idx + np.uint64(1)) * GAMMA
+            z = (z ^ (z >> np.uint64(30))) * MIX1
+            z = (z ^ (z >> np.uint64(27))) * MIX2
+        hb = z ^ (z >> np.uint64(31))
+        if kind == KIND_JOIN_FK_I32:
+            return (hb >> np.uint64(33)).astype(np.int32)
+        return hb.view(np.int64)
     if kind in (KIND_ZIPF_I64, KIND_ZIPF_F32, KIND_ZIPF_I32):
         if cdf is None:
             raise ValueError("Zipf kinds need the cdf table")

@@ -15,7 +15,8 @@ namespace {
 
 enum Kind {
   U_I32 = 0, U_I64 = 1, U_F32 = 2, ZIPF_I64 = 3, ZIPF_F32 = 4, SORTED_F32 = 5,
-  SORTED_I64 = 6, IOTA_U32 = 7, IOTA_U64 = 8, PAYLOAD_F64 = 9, ZIPF_I32 = 10
+  SORTED_I64 = 6, IOTA_U32 = 7, IOTA_U64 = 8, PAYLOAD_F64 = 9, ZIPF_I32 = 10,
+  JOIN_FK_I32 = 11, JOIN_FK_I64 = 12
 };
 
 __host__ __device__ inline uint64_t splitmix(uint64_t seed, uint64_t i) {
@@ -54,6 +55,10 @@ __host__ __device__ inline void gen_one(int kind, uint64_t seed, uint64_t i, uin
     case SORTED_I64: ((int64_t*)dst)[j] = (int64_t)((i << 24) / n_total) - (int64_t(1) << 23); break;
     case IOTA_U32: ((uint32_t*)dst)[j] = (uint32_t)i; break;
     case IOTA_U64: ((uint64_t*)dst)[j] = i; break;
+    // a foreign key: the build recipe (uniform int32 / int64, same seed) at an
+    // index drawn from the stream of seed + 1, modulo n_total
+    case JOIN_FK_I32: ((int32_t*)dst)[j] = (int32_t)(splitmix(seed, splitmix(seed + 1, i) % n_total) >> 33); break;
+    case JOIN_FK_I64: ((int64_t*)dst)[j] = (int64_t)splitmix(seed, splitmix(seed + 1, i) % n_total); break;
   }
 }
 
@@ -64,7 +69,7 @@ __global__ void gen_kernel(int kind, uint64_t seed, uint64_t start, uint64_t n, 
     gen_one(kind, seed, start + j, n_total, cdf, m, dst, j);
 }
 
-bool kind_ok(int kind) { return kind >= 0 && kind <= 10; }
+bool kind_ok(int kind) { return kind >= 0 && kind <= 12; }
 bool needs_cdf(int kind) { return kind == ZIPF_I64 || kind == ZIPF_F32 || kind == ZIPF_I32; }
 
 }  // namespace

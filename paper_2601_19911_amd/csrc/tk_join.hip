@@ -1,0 +1,409 @@
+// Matching primitive (paper sec. III-B): the probe phase of an inner equi-join,
+// key-only.  The build side's (key, row-id) pairs go into a device hash table;
+// every probe key is looked up in parallel and each match returns the pair
+// (probe row-id, build row-id): the "set of matched pointers" of sec. II-C,
+// which the host late-materializes.
+//
+// Table (caller-owned device buffer, see tk_join_table_size):
+//   [header, 256 B][slots: S slots of (key word, row-id word)][side list]
+// S is a power of two >= 2 * n_build, so the load factor is at most 1/2.  Open
+// addressing with linear probing; duplicate build keys take one slot each, so
+// a probe walks its run until an empty slot and returns every equal key.  The
+// empty marker is the key whose bits are 1 << (width - 1) (INT_MIN); build keys
+// equal to it are not hashed but appended to the side list, which a probe of
+// that key reads in full.  The header counts the side list and records whether
+// any build key occurs twice; without duplicates a probe stops at its first
+// hit.
+//
+// Memory behaviour on MI355X: the probe is bound by random reads of slots
+// (one slot usually, in one 128-byte line; adjacent slots of a run share it).
+// Probe keys stream in coalesced; matches are staged per wave in LDS and
+// written out contiguously behind one global atomic per stage flush.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mitopk.h"
+#include "tk_device.hpp"
+
+namespace {
+
+constexpr uint64_t JOIN_HEADER_BYTES = 256;
+constexpr uint64_t JOIN_MAX_BUILD = 1ull << 31;
+constexpr int PROBE_NT = 256;   // threads per probe workgroup
+constexpr int PROBE_PER = 4;    // probe keys per thread per tile
+constexpr int STAGE = 256;      // staged matches per wave
+constexpr int PROBE_WG_PER_CU = 8;
+
+struct JoinHeader {
+  unsigned long long side_count;  // build keys equal to the empty marker
+  uint32_t dup;                   // 1: some build key occurs more than once
+  uint32_t pad[61];
+};
+static_assert(sizeof(JoinHeader) == JOIN_HEADER_BYTES, "join header is 256 bytes");
+
+// A slot: key bits and row-id in words of one width (4 bytes when both are
+// 4-byte types, else 8), so one aligned 8- or 16-byte load reads a slot.
+template <typename W>
+struct alignas(2 * sizeof(W)) Slot {
+  W key;
+  W rid;
+};
+
+template <int KT> struct JKey;
+template <> struct JKey<TK_KEY_I32> {
+  using Raw = uint32_t;
+  static constexpr Raw EMPTY = 0x80000000u;
+};
+template <> struct JKey<TK_KEY_I64> {
+  using Raw = unsigned long long;
+  static constexpr Raw EMPTY = 0x8000000000000000ull;
+};
+
+// Slot index: the key's bits folded and multiplied by 2^64 / golden ratio
+// (Knuth's multiplicative hashing); the top log2(S) bits of the product.
+__device__ __forceinline__ uint64_t slot_of(uint64_t x, uint32_t shift) {
+  x ^= x >> 31;
+  x *= 0x9E3779B97F4A7C15ull;
+  return x >> shift;
+}
+
+uint64_t slots_for(uint64_t n_build) {
+  uint64_t s = 64;
+  while (s < 2 * n_build) s <<= 1;
+  return s;
+}
+
+bool wide_slot(int key_type, int rid_type) {
+  return key_type == TK_KEY_I64 || rid_type == TK_RID_U64;
+}
+
+uint64_t round256(uint64_t b) { return (b + 255) & ~255ull; }
+
+size_t table_bytes_for(uint64_t n_build, int key_type, int rid_type) {
+  const uint64_t slot_b = wide_slot(key_type, rid_type) ? 16 : 8;
+  const uint64_t rid_b = rid_type == TK_RID_U64 ? 8 : 4;
+  return (size_t)(JOIN_HEADER_BYTES + round256(slots_for(n_build) * slot_b) +
+                  round256((n_build ? n_build : 1) * rid_b));
+}
+
+// ---- build ------------------------------------------------------------------------------
+
+template <typename W>
+__global__ __launch_bounds__(256) void k_jfill(Slot<W>* __restrict__ slots, uint64_t nslots,
+                                               W empty, JoinHeader* __restrict__ hdr) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hdr->side_count = 0;
+    hdr->dup = 0;
+  }
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots; i += stride) {
+    Slot<W> s;
+    s.key = empty;
+    s.rid = 0;
+    slots[i] = s;
+  }
+}
+
+template <int KT, typename W, typename BR>
+__global__ __launch_bounds__(256) void k_jbuild(const typename JKey<KT>::Raw* __restrict__ keys,
+                                                const BR* __restrict__ rids, uint64_t n,
+                                                Slot<W>* __restrict__ slots, uint64_t mask,
+                                                uint32_t shift, BR* __restrict__ side,
+                                                JoinHeader* __restrict__ hdr) {
+  using Raw = typename JKey<KT>::Raw;
+  constexpr Raw EMPTY = JKey<KT>::EMPTY;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const Raw key = keys[i];
+    const BR r = rids ? rids[i] : (BR)i;
+    if (key == EMPTY) {
+      const unsigned long long at = atomicAdd(&hdr->side_count, 1ull);
+      side[at] = r;
+      continue;
+    }
+    const W w = (W)key;
+    uint64_t p = slot_of((uint64_t)key, shift);
+    // at most n < S keys are hashed, so an empty slot is always ahead
+    for (uint64_t step = 0; step <= mask; ++step) {
+      const W prev = atomicCAS(&slots[p].key, (W)EMPTY, w);
+      if (prev == (W)EMPTY) {
+        slots[p].rid = (W)r;
+        break;
+      }
+      if (prev == w && hdr->dup == 0) hdr->dup = 1;
+      p = (p + 1) & mask;
+    }
+  }
+}
+
+// ---- probe ------------------------------------------------------------------------------
+
+template <typename W, typename BR, typename PR>
+struct ProbeArgs {
+  const void* keys;
+  const PR* rids;         // null: probe row-id = position
+  uint64_t n;
+  const Slot<W>* slots;
+  uint64_t mask;
+  uint32_t shift;
+  const BR* side;
+  const JoinHeader* hdr;
+  PR* out_p;
+  BR* out_b;
+  uint64_t cap;
+  unsigned long long* count;
+};
+
+// Writes one wave's `fill` staged matches behind one global atomic; pairs past
+// the output capacity are counted but not written.
+template <typename BR, typename PR>
+__device__ __forceinline__ void flush_stage(const PR* sp, const BR* sb, uint32_t fill,
+                                            PR* __restrict__ out_p, BR* __restrict__ out_b,
+                                            uint64_t cap, unsigned long long* count, uint32_t ln) {
+  __builtin_amdgcn_wave_barrier();
+  unsigned long long base = 0;
+  if (ln == 0) base = atomicAdd(count, (unsigned long long)fill);
+  base = __shfl(base, 0, 64);
+  for (uint32_t i = ln; i < fill; i += 64) {
+    const uint64_t o = base + i;
+    if (o < cap) {
+      out_p[o] = sp[i];
+      out_b[o] = sb[i];
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int KT, typename W, typename BR, typename PR>
+__global__ __launch_bounds__(PROBE_NT) void k_jprobe(ProbeArgs<W, BR, PR> a) {
+  using Raw = typename JKey<KT>::Raw;
+  constexpr Raw EMPTY = JKey<KT>::EMPTY;
+  constexpr uint64_t TILE = (uint64_t)PROBE_NT * PROBE_PER;
+  __shared__ PR sp[PROBE_NT / 64][STAGE];
+  __shared__ BR sb[PROBE_NT / 64][STAGE];
+  const uint32_t wv = threadIdx.x >> 6, ln = tk::lane_id();
+  const Raw* __restrict__ keys = static_cast<const Raw*>(a.keys);
+  const bool dup = a.hdr->dup != 0;
+  const uint64_t side_n = a.hdr->side_count;
+  uint32_t fill = 0;  // wave-uniform
+
+  for (uint64_t base = (uint64_t)blockIdx.x * TILE; base < a.n; base += (uint64_t)gridDim.x * TILE) {
+    Raw key[PROBE_PER];
+    uint64_t pos[PROBE_PER];
+    Slot<W> cur[PROBE_PER];
+    // every key of the tile first, then every first slot: the random reads of
+    // a thread's keys are in flight together
+#pragma unroll
+    for (int q = 0; q < PROBE_PER; ++q) {
+      const uint64_t j = base + (uint64_t)q * PROBE_NT + threadIdx.x;
+      key[q] = j < a.n ? keys[j] : EMPTY;
+    }
+#pragma unroll
+    for (int q = 0; q < PROBE_PER; ++q) {
+      pos[q] = slot_of((uint64_t)key[q], a.shift);
+      cur[q].key = (W)EMPTY;
+      cur[q].rid = 0;
+      if (key[q] != EMPTY) cur[q] = a.slots[pos[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < PROBE_PER; ++q) {
+      const uint64_t j = base + (uint64_t)q * PROBE_NT + threadIdx.x;
+      bool act = j < a.n;
+      const bool side = key[q] == EMPTY;
+      const W kw = (W)key[q];
+      uint64_t p = pos[q], t = 0;
+      Slot<W> c = cur[q];
+      while (true) {
+        bool emit = false;
+        BR brid = 0;
+        if (act) {
+          if (side) {
+            if (t < side_n) {
+              emit = true;
+              brid = a.side[t];
+              ++t;
+            } else {
+              act = false;
+            }
+          } else if (c.key == (W)EMPTY) {
+            act = false;
+          } else {
+            if (c.key == kw) {
+              emit = true;
+              brid = (BR)c.rid;
+              if (!dup) act = false;
+            }
+            if (act) {
+              p = (p + 1) & a.mask;
+              c = a.slots[p];
+            }
+          }
+        }
+        const uint64_t m = tk::ballot(emit);
+        if (m) {
+          const uint32_t nm = (uint32_t)__popcll(m);
+          if (fill + nm > (uint32_t)STAGE) {
+            flush_stage(sp[wv], sb[wv], fill, a.out_p, a.out_b, a.cap, a.count, ln);
+            fill = 0;
+          }
+          if (emit) {
+            const uint32_t at = fill + tk::lanes_below(m);
+            sp[wv][at] = a.rids ? a.rids[j] : (PR)j;
+            sb[wv][at] = brid;
+          }
+          fill += nm;
+        }
+        if (tk::ballot(act) == 0) break;
+      }
+    }
+  }
+  if (fill) flush_stage(sp[wv], sb[wv], fill, a.out_p, a.out_b, a.cap, a.count, ln);
+}
+
+__global__ void k_jclear(unsigned long long* count) { *count = 0; }
+
+int launch_grid(int dev_cus, uint64_t work, uint64_t per_wg, int wg_per_cu) {
+  uint64_t g = (work + per_wg - 1) / per_wg;
+  const uint64_t lim = (uint64_t)dev_cus * wg_per_cu;
+  if (g > lim) g = lim;
+  return (int)(g ? g : 1);
+}
+
+int cus() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
+    return 256;
+  return v;
+}
+
+template <int KT, typename W, typename BR>
+int build_t(const void* keys, const void* rids, uint64_t n, void* table, uint64_t nslots,
+            hipStream_t st) {
+  auto* hdr = static_cast<JoinHeader*>(table);
+  auto* slots = reinterpret_cast<Slot<W>*>(static_cast<char*>(table) + JOIN_HEADER_BYTES);
+  auto* side = reinterpret_cast<BR*>(reinterpret_cast<char*>(slots) + round256(nslots * sizeof(Slot<W>)));
+  const int c = cus();
+  hipLaunchKernelGGL(k_jfill<W>, dim3(launch_grid(c, nslots, 256 * 8, 8)), dim3(256), 0, st, slots,
+                     nslots, (W)JKey<KT>::EMPTY, hdr);
+  if (n) {
+    uint32_t lg = 0;
+    while ((1ull << lg) < nslots) ++lg;
+    hipLaunchKernelGGL((k_jbuild<KT, W, BR>), dim3(launch_grid(c, n, 256 * 4, 16)), dim3(256), 0, st,
+                       static_cast<const typename JKey<KT>::Raw*>(keys), static_cast<const BR*>(rids),
+                       n, slots, nslots - 1, 64u - lg, side, hdr);
+  }
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
+}
+
+template <int KT, typename W, typename BR, typename PR>
+int probe_t(const tk_join_table* t, const void* keys, const void* rids, uint64_t n, void* out_p,
+            void* out_b, uint64_t cap, uint64_t* d_count, hipStream_t st) {
+  auto* hdr = static_cast<const JoinHeader*>(t->table);
+  auto* slots = reinterpret_cast<const Slot<W>*>(static_cast<const char*>(t->table) + JOIN_HEADER_BYTES);
+  auto* side = reinterpret_cast<const BR*>(reinterpret_cast<const char*>(slots) +
+                                           round256(t->slots * sizeof(Slot<W>)));
+  auto* cnt = reinterpret_cast<unsigned long long*>(d_count);
+  hipLaunchKernelGGL(k_jclear, dim3(1), dim3(1), 0, st, cnt);
+  if (n) {
+    uint32_t lg = 0;
+    while ((1ull << lg) < t->slots) ++lg;
+    ProbeArgs<W, BR, PR> a;
+    a.keys = keys;
+    a.rids = static_cast<const PR*>(rids);
+    a.n = n;
+    a.slots = slots;
+    a.mask = t->slots - 1;
+    a.shift = 64u - lg;
+    a.side = side;
+    a.hdr = hdr;
+    a.out_p = static_cast<PR*>(out_p);
+    a.out_b = static_cast<BR*>(out_b);
+    a.cap = (out_p && out_b) ? cap : 0;
+    a.count = cnt;
+    hipLaunchKernelGGL((k_jprobe<KT, W, BR, PR>),
+                       dim3(launch_grid(cus(), n, (uint64_t)PROBE_NT * PROBE_PER, PROBE_WG_PER_CU)),
+                       dim3(PROBE_NT), 0, st, a);
+  }
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
+}
+
+template <int KT, typename W, typename BR>
+int probe_rid(const tk_join_table* t, const void* keys, const void* rids, uint64_t n, int prt,
+              void* out_p, void* out_b, uint64_t cap, uint64_t* d_count, hipStream_t st) {
+  if (prt == TK_RID_U32)
+    return probe_t<KT, W, BR, uint32_t>(t, keys, rids, n, out_p, out_b, cap, d_count, st);
+  return probe_t<KT, W, BR, unsigned long long>(t, keys, rids, n, out_p, out_b, cap, d_count, st);
+}
+
+}  // namespace
+
+extern "C" size_t tk_join_table_size(uint64_t n_build, int key_type, int rid_type) {
+  if ((key_type != TK_KEY_I32 && key_type != TK_KEY_I64) ||
+      (rid_type != TK_RID_U32 && rid_type != TK_RID_U64) || n_build > JOIN_MAX_BUILD)
+    return 0;
+  return table_bytes_for(n_build, key_type, rid_type);
+}
+
+extern "C" int tk_join_build(const void* keys, const void* rowids, uint64_t n_build, int key_type,
+                             int rid_type, void* table, size_t table_bytes, tk_join_table* out,
+                             void* stream) {
+  if (key_type == TK_KEY_F32 || key_type == TK_KEY_F64) return TK_EUNSUPPORTED;
+  if ((key_type != TK_KEY_I32 && key_type != TK_KEY_I64) ||
+      (rid_type != TK_RID_U32 && rid_type != TK_RID_U64) || !out || !table)
+    return TK_EINVAL;
+  if (n_build > JOIN_MAX_BUILD) return TK_EUNSUPPORTED;
+  if (n_build && !keys) return TK_EINVAL;
+  if (rid_type == TK_RID_U32 && !rowids && n_build > (1ull << 32)) return TK_EINVAL;
+  if (((uintptr_t)table & 255) != 0) return TK_EINVAL;
+  if (table_bytes < table_bytes_for(n_build, key_type, rid_type)) return TK_EINVAL;
+  const uint64_t nslots = slots_for(n_build);
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if (key_type == TK_KEY_I32 && rid_type == TK_RID_U32)
+    rc = build_t<TK_KEY_I32, uint32_t, uint32_t>(keys, rowids, n_build, table, nslots, st);
+  else if (key_type == TK_KEY_I32)
+    rc = build_t<TK_KEY_I32, unsigned long long, unsigned long long>(keys, rowids, n_build, table, nslots, st);
+  else if (rid_type == TK_RID_U32)
+    rc = build_t<TK_KEY_I64, unsigned long long, uint32_t>(keys, rowids, n_build, table, nslots, st);
+  else
+    rc = build_t<TK_KEY_I64, unsigned long long, unsigned long long>(keys, rowids, n_build, table, nslots, st);
+  if (rc != TK_OK) return rc;
+  out->table = table;
+  out->table_bytes = table_bytes;
+  out->n_build = n_build;
+  out->slots = nslots;
+  out->key_type = key_type;
+  out->rid_type = rid_type;
+  return TK_OK;
+}
+
+extern "C" int tk_join_probe(const tk_join_table* t, const void* keys, const void* rowids,
+                             uint64_t n_probe, int rid_type, void* out_probe_rowids,
+                             void* out_build_rowids, uint64_t capacity, uint64_t* d_count,
+                             void* stream) {
+  if (!t || !t->table || !d_count) return TK_EINVAL;
+  if ((t->key_type != TK_KEY_I32 && t->key_type != TK_KEY_I64) ||
+      (t->rid_type != TK_RID_U32 && t->rid_type != TK_RID_U64) ||
+      (rid_type != TK_RID_U32 && rid_type != TK_RID_U64))
+    return TK_EINVAL;
+  if (t->slots != slots_for(t->n_build) ||
+      t->table_bytes < table_bytes_for(t->n_build, t->key_type, t->rid_type))
+    return TK_EINVAL;
+  if (n_probe && !keys) return TK_EINVAL;
+  if (capacity && (!out_probe_rowids || !out_build_rowids)) return TK_EINVAL;
+  if (rid_type == TK_RID_U32 && !rowids && n_probe > (1ull << 32)) return TK_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (t->key_type == TK_KEY_I32 && t->rid_type == TK_RID_U32)
+    return probe_rid<TK_KEY_I32, uint32_t, uint32_t>(t, keys, rowids, n_probe, rid_type,
+                                                     out_probe_rowids, out_build_rowids, capacity,
+                                                     d_count, st);
+  if (t->key_type == TK_KEY_I32)
+    return probe_rid<TK_KEY_I32, unsigned long long, unsigned long long>(
+        t, keys, rowids, n_probe, rid_type, out_probe_rowids, out_build_rowids, capacity, d_count, st);
+  if (t->rid_type == TK_RID_U32)
+    return probe_rid<TK_KEY_I64, unsigned long long, uint32_t>(
+        t, keys, rowids, n_probe, rid_type, out_probe_rowids, out_build_rowids, capacity, d_count, st);
+  return probe_rid<TK_KEY_I64, unsigned long long, unsigned long long>(
+      t, keys, rowids, n_probe, rid_type, out_probe_rowids, out_build_rowids, capacity, d_count, st);
+}

@@ -64,3 +64,19 @@ def test_batched_query_shapes():
     assert n.min() >= 2 ** 10 and n.max() < 2 ** 24
     assert k.min() >= 1 and k.max() <= 4096 and np.all(k <= n)
     assert int(o.sum()) == 2048
+
+
+@pytest.mark.parametrize("kind,bkind", [(inputgen.KIND_JOIN_FK_I64, inputgen.KIND_U_I64),
+                                        (inputgen.KIND_JOIN_FK_I32, inputgen.KIND_U_I32)])
+def test_join_foreign_keys_point_into_the_build_side(kind, bkind):
+    nb, rng_ = 5000, 10000
+    build = inputgen.generate(bkind, 42, nb)
+    probe = inputgen.generate(kind, 42, 20000, n_total=rng_)
+    idx = inputgen.splitmix64(43, 0, 20000) % np.uint64(rng_)
+    hit = idx < nb
+    assert np.array_equal(probe[hit], build[idx[hit].astype(np.int64)])
+    # the miss indices continue the build recipe past n_build
+    tail = inputgen.generate(bkind, 42, rng_)
+    assert np.array_equal(probe, tail[idx.astype(np.int64)])
+    if kind == inputgen.KIND_JOIN_FK_I64:
+        assert not np.isin(probe[~hit], build).any()
