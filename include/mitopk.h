@@ -78,6 +78,24 @@ int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int ke
             int rid_type, int order, void* out_keys, void* out_rowids, uint64_t* out_count,
             void* workspace, size_t workspace_bytes, void* stream);
 
+/* Allocation-free tk_topk, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and asynchrony as tk_topk, without the
+ * workspace: the query's workspace is a library-owned device array of
+ * TK_NOALLOC_SCRATCH_BYTES, one per device, held from the library's load until
+ * the process ends.  The call allocates nothing.  A query whose
+ * tk_workspace_size exceeds TK_NOALLOC_SCRATCH_BYTES (K of a few hundred
+ * thousand and up; every K <= 100000 fits at any N <= 2^30) returns
+ * TK_EUNSUPPORTED and enqueues nothing.  Every call on one device shares that
+ * device's array: two calls whose work may overlap on one device (different
+ * streams without ordering between them, different host threads) race and
+ * may return wrong results; order them on one stream.  The array's contents
+ * are left from the last call; each query sets up every word it reads. */
+#define TK_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int tk_topk_noalloc(const void* keys, const void* rowids, uint64_t n, uint64_t k, int key_type,
+                    int rid_type, int order, void* out_keys, void* out_rowids, uint64_t* out_count,
+                    void* stream);
+
 /* What the device did for the last tk_topk that used `workspace`.  Copies a
  * few words from the device synchronously; call after the stream has passed
  * the query. */

@@ -53,6 +53,9 @@ def lib():
         L.tk_topk.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, ctypes.POINTER(u64), vp,
                               ctypes.c_size_t, vp]
         L.tk_topk.restype = i32
+        L.tk_topk_noalloc.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, ctypes.POINTER(u64),
+                                      vp]
+        L.tk_topk_noalloc.restype = i32
         L.tk_query_info.argtypes = [vp, ctypes.POINTER(tk_info)]
         L.tk_query_info.restype = i32
         L.tk_set_tuning.argtypes = [ctypes.POINTER(tk_tuning)]
@@ -175,6 +178,36 @@ def topk(keys, k: int, rowids=None, order="desc", out_keys=None, out_rowids=None
                        _ptr(out_keys), _ptr(out_rowids), ctypes.byref(cnt),
                        workspace.data_ptr(), workspace.numel(), _stream_handle(stream))
     check(rc, "tk_topk")
+    return out_keys, out_rowids
+
+
+# Bytes of the library's own device array behind topk_noalloc (TK_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def topk_noalloc(keys, k: int, out_keys, out_rowids, rowids=None, order="desc", stream=None):
+    """``topk`` through tk_topk_noalloc: no workspace, nothing allocated by the
+    call (the caller passes the outputs).  Queries whose workspace would exceed
+    NOALLOC_SCRATCH_BYTES raise (TK_EUNSUPPORTED).  Calls that may overlap on
+    one device race on the library's shared array: keep them on one stream."""
+    if not keys.is_cuda:
+        raise TopKError("keys must be a device tensor")
+    if not keys.is_contiguous() or (rowids is not None and not rowids.is_contiguous()):
+        raise TopKError("keys and rowids must be contiguous")
+    n = keys.shape[0]
+    k_eff = min(int(k), n)
+    if out_rowids is None or out_rowids.numel() < k_eff:
+        raise TopKError("out_rowids must hold min(k, n) row-ids")
+    if out_keys is not None and out_keys.numel() < k_eff:
+        raise TopKError("out_keys must hold min(k, n) keys")
+    if rowids is not None and rowids.shape[0] != n:
+        raise TopKError("rowids must have one entry per key")
+    rc_ = rid_code(out_rowids.dtype if rowids is None else rowids.dtype)
+    cnt = ctypes.c_uint64(0)
+    rc = lib().tk_topk_noalloc(_ptr(keys) if n else None, _ptr(rowids), n, int(k),
+                               key_code(keys.dtype), rc_, order_code(order), _ptr(out_keys),
+                               _ptr(out_rowids), ctypes.byref(cnt), _stream_handle(stream))
+    check(rc, "tk_topk_noalloc")
     return out_keys, out_rowids
 
 

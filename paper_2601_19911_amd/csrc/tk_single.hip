@@ -582,6 +582,60 @@ extern "C" int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_
 #undef TK_RUN
 }
 
+// ---- allocation-free variant of tk_topk ------------------------------------------------------
+//
+// The workspace of tk_topk lives in a file-scope device array instead of a
+// caller buffer, for callers that cannot allocate device memory.  Each device
+// the library runs on holds its own copy of the array (loaded with the code
+// object, kept until the process ends); its device address is looked up once
+// per device on the first call there and cached.  Every call on one device
+// uses the same array: calls that overlap on one device (different streams,
+// different host threads without ordering between their streams) race on it.
+// The kernels set up every word of the workspace they read, so nothing has to
+// be cleared between calls.
+
+static __device__ __align__(256) unsigned char scratch[TK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // device address of `scratch`, per device
+
+// Device address of this device's copy of `scratch` (nullptr on failure).
+void* scratch_on(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" int tk_topk_noalloc(const void* keys, const void* rowids, uint64_t n, uint64_t k,
+                               int key_type, int rid_type, int order, void* out_keys,
+                               void* out_rowids, uint64_t* out_count, void* stream) {
+  if (key_type < 0 || key_type > 3 || rid_type < 0 || rid_type > 1 || order < 0 || order > 1)
+    return TK_EINVAL;
+  if (n > 0 && !keys) return TK_EINVAL;
+  const uint64_t k_eff = k < n ? k : n;
+  if (k_eff == 0) {
+    if (out_count) *out_count = 0;
+    return TK_OK;
+  }
+  const size_t need = tk_workspace_size(n, k, key_type, rid_type);
+  if (need > TK_NOALLOC_SCRATCH_BYTES) return TK_EUNSUPPORTED;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TK_EHIP;
+  void* ws = scratch_on(dev);
+  if (!ws) return TK_EHIP;
+  return tk_topk(keys, rowids, n, k, key_type, rid_type, order, out_keys, out_rowids, out_count, ws,
+                 TK_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 extern "C" int tk_query_info(const void* workspace, tk_info* info) {
   if (!workspace || !info) return TK_EINVAL;
   Header h;

@@ -70,3 +70,29 @@ def test_workspace_size_is_pure_arithmetic():
                 assert s >= 8192 and s % 256 == 0
     # grows with k
     assert tk.workspace_size(1 << 28, 100000, 2, 0) > tk.workspace_size(1 << 28, 1000, 2, 0)
+
+
+def test_noalloc_argument_errors_before_device_work():
+    L = tk.lib()
+    cnt = ctypes.c_uint64(99)
+    assert L.tk_topk_noalloc(None, None, 0, 1, 9, 0, 0, None, None, ctypes.byref(cnt), None) == -1
+    assert L.tk_topk_noalloc(None, None, 10, 1, 0, 0, 0, None, None, ctypes.byref(cnt), None) == -1
+    assert L.tk_topk_noalloc(None, None, 0, 5, 0, 0, 0, None, None, ctypes.byref(cnt), None) == 0
+    assert cnt.value == 0
+    # a workspace beyond the library's array is refused before any device call
+    n, k = 1 << 24, 1 << 22
+    assert tk.workspace_size(n, k, 1, 1) > tk.NOALLOC_SCRATCH_BYTES
+    assert L.tk_topk_noalloc(ctypes.c_void_p(256), None, n, k, 1, 1, 0, None, None,
+                             ctypes.byref(cnt), None) == -4
+
+
+def test_noalloc_array_size_matches_header():
+    text = open(os.path.join(ROOT, "include", "mitopk.h")).read()
+    m = re.search(r"#define TK_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and (int(m.group(1)) << int(m.group(2))) == tk.NOALLOC_SCRATCH_BYTES
+    # every K up to 100000 fits at any N up to 2^30, all key and row-id types
+    for lg in range(1, 31):
+        for n in ((1 << lg) - 1, 1 << lg, 3 << (lg - 1)):
+            for kt in range(4):
+                for rt in range(2):
+                    assert tk.workspace_size(n, 100000, kt, rt) <= tk.NOALLOC_SCRATCH_BYTES
