@@ -11,6 +11,9 @@
     python bench_suites.py e2e               headline query with pinned H2D and D2H included
     python bench_suites.py join              key-only hash-join probe (matching primitive):
                                              build and probe times, probes/s, bytes per probe
+    python bench_suites.py sort --log2n 24   ORDER BY without LIMIT: LSD radix sort per key type
+    python bench_suites.py stream --log2n 26 chunk-pipelined key-only streaming from pinned host
+                                             memory vs the pure copy of the key bytes
 
 Each suite prints one JSON object per measurement on stdout.  Every input is
 synthetic and seeded (inputgen); every GPU result that a suite reports is
@@ -278,6 +281,129 @@ def suite_e2e(a):
           "median_s": t, "p95_s": pct(times, 95), "keys_per_s": n / t,
           "h2d_median_s": float(np.median(h2d)), "h2d_gbs": n * 8 / float(np.median(h2d)) / 1e9,
           "reps": a.reps, "oracle_match": bool(match)})
+
+
+def suite_sort(a):
+    """ORDER BY key without LIMIT (tk_sort, LSD radix): 2^log2n pairs per key
+    type, uniform keys, implicit row-ids (uint32), descending.  Times the sort
+    with events on the launch stream; the first result is compared with the
+    oracle (Top-K with K = N).  Bytes: the minimum a sort moves (one read of
+    the keys, one write of keys and row-ids) and what this design moves (per
+    digit pass two reads and one write of every pair; the first pass reads the
+    keys only, the last writes the outputs)."""
+    torch = _torch()
+    import inputgen
+    import oracle
+    import paper_2601_19911_amd as tk
+    from inputgen import native as gen
+
+    dev = torch.device("cuda:0")
+    n = 1 << a.log2n
+    s = torch.cuda.current_stream()
+    for name, kind, tdt in [("int32", inputgen.KIND_U_I32, torch.int32),
+                            ("float32", inputgen.KIND_U_F32, torch.float32),
+                            ("int64", inputgen.KIND_U_I64, torch.int64),
+                            ("float64", inputgen.KIND_U_F64, torch.float64)]:
+        hk = gen.host_fill(kind, inputgen.config_seed(5, 90), n)
+        dk = torch.from_numpy(hk).to(dev)
+        kb, rb = hk.dtype.itemsize, 4
+        ok, orr = tk.sort(dk, order="desc")
+        ws = torch.empty(int(tk.lib().tk_sort_workspace_size(n, tk.key_code(tdt), tk.TK_RID_U32)),
+                         dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        match = None
+        if not a.no_check:
+            ek, er = oracle.topk(hk, None, n, oracle.DESC)
+            match = same(dev_view_np(ok), dev_view_np(orr), ek, er)
+        ts = []
+        for r in range(a.reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            tk.sort(dk, order="desc", out_keys=ok, out_rowids=orr, workspace=ws, stream=s)
+            e1.record(s)
+            torch.cuda.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+        t = float(np.median(ts))
+        passes = kb
+        min_bytes = n * kb + n * (kb + rb)
+        design_bytes = (passes * 3 * n * (kb + rb)) - 2 * n * rb  # first pass reads keys only
+        emit({"suite": "sort", "workload": f"ORDER BY key without LIMIT, N=2^{a.log2n} {name} "
+              "uniform keys, implicit uint32 row-ids, desc", "key_dtype": name, "n": n,
+              "digit_passes": passes, "median_s": t, "p95_s": pct(ts, 95), "keys_per_s": n / t,
+              "min_bytes": min_bytes, "min_bytes_gbs": min_bytes / t / 1e9,
+              "design_bytes": design_bytes, "design_bytes_gbs": design_bytes / t / 1e9,
+              "design_frac_of_peak": design_bytes / t / 1e9 / HBM_PEAK_GBS,
+              "oracle_match": match, "reps": a.reps})
+        del dk, ok, orr, ws
+
+
+def suite_stream(a):
+    """Chunk-pipelined key-only streaming (tk_topk_stream): a key column in
+    pinned host memory, K = 1000 desc, implicit row-ids.  Times (events on the
+    compute stream) the pure host-to-device copy of the key bytes, the copy
+    followed by a device-resident query, and the pipelined call at several
+    chunk sizes; every pipelined result is compared with the oracle."""
+    torch = _torch()
+    import inputgen
+    import oracle
+    import paper_2601_19911_amd as tk
+    from inputgen import native as gen
+
+    dev = torch.device("cuda:0")
+    n, k = 1 << a.log2n, 1000
+    s = torch.cuda.current_stream()
+    cs = torch.cuda.Stream()
+    for name, kind, tdt in [("float32", inputgen.KIND_U_F32, torch.float32),
+                            ("int64", inputgen.KIND_U_I64, torch.int64)]:
+        hk = gen.host_fill(kind, inputgen.config_seed(4, 80), n)
+        pk = _pinned_copy(hk)
+        kb = hk.dtype.itemsize
+        dk = torch.empty(n, dtype=tdt, device=dev)
+        ws = tk.new_workspace(n, k, tk.key_code(tdt), tk.TK_RID_U32, device=dev)
+        ok = torch.empty(k, dtype=tdt, device=dev)
+        orr = torch.empty(k, dtype=torch.uint32, device=dev)
+        ek, er = oracle.topk(hk, None, k, oracle.DESC)
+
+        def timed(fn):
+            out = []
+            for r in range(a.reps + 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                fn()
+                e1.record(s)
+                torch.cuda.synchronize()
+                if r:
+                    out.append(e0.elapsed_time(e1) * 1e-3)
+            return out
+
+        copy_t = timed(lambda: dk.copy_(pk, non_blocking=True))
+
+        def serial():
+            dk.copy_(pk, non_blocking=True)
+            tk.topk(dk, k, out_keys=ok, out_rowids=orr, workspace=ws, stream=s)
+
+        serial_t = timed(serial)
+        tcopy = float(np.median(copy_t))
+        for chunk_log2 in a.chunks_log2:
+            chunk = 1 << chunk_log2
+            sws = torch.empty(tk.lib().tk_stream_workspace_size(n, k, chunk, tk.key_code(tdt),
+                                                                 tk.TK_RID_U32, 0),
+                              dtype=torch.uint8, device=dev)
+            tk.topk_stream(pk, k, chunk=chunk, out_keys=ok, out_rowids=orr, workspace=sws,
+                           stream=s, copy_stream=cs)
+            torch.cuda.synchronize()
+            match = same(dev_view_np(ok), dev_view_np(orr), ek, er)
+            st = timed(lambda: tk.topk_stream(pk, k, chunk=chunk, out_keys=ok, out_rowids=orr,
+                                              workspace=sws, stream=s, copy_stream=cs))
+            t = float(np.median(st))
+            emit({"suite": "stream", "workload": f"N=2^{a.log2n} {name} keys in pinned host memory, "
+                  "implicit row-ids, K=1000 desc", "key_dtype": name, "chunk": chunk,
+                  "workspace_bytes": int(sws.numel()), "copy_only_s": tcopy,
+                  "copy_gbs": n * kb / tcopy / 1e9, "serial_copy_then_query_s": float(np.median(serial_t)),
+                  "stream_s": t, "stream_p95_s": pct(st, 95), "stream_over_copy": t / tcopy,
+                  "keys_per_s": n / t, "oracle_match": bool(match), "reps": a.reps})
+        del dk, ws, pk
 
 
 # ---- C4: key-only vs full-row with late materialization ----------------------------------------
@@ -601,10 +727,12 @@ def suite_join(a):
         if m > op.numel():
             op, ob, cnt = join_probe(t, pk, capacity=m)
             torch.cuda.synchronize()
-        gp, gb = dev_view_np(op)[:m].astype(np.uint64), dev_view_np(ob)[:m].astype(np.uint64)
-        o = np.lexsort((gb, gp))
-        ep, eb = oracle.join(bk_h, None, pk_h, None)
-        ok = bool(gp.shape == ep.shape and np.array_equal(gp[o], ep) and np.array_equal(gb[o], eb))
+        ok = None
+        if not a.no_check:
+            gp, gb = dev_view_np(op)[:m].astype(np.uint64), dev_view_np(ob)[:m].astype(np.uint64)
+            o = np.lexsort((gb, gp))
+            ep, eb = oracle.join(bk_h, None, pk_h, None)
+            ok = bool(gp.shape == ep.shape and np.array_equal(gp[o], ep) and np.array_equal(gb[o], eb))
         bt, pt = [], []
         for _ in range(a.reps):
             e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -633,7 +761,8 @@ def suite_join(a):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("suite", choices=["c2", "c3", "c4", "c5", "crossover", "gate", "e2e", "join"])
+    ap.add_argument("suite", choices=["c2", "c3", "c4", "c5", "crossover", "gate", "e2e", "join",
+                                      "stream", "sort"])
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--q", type=int, default=4096)
     ap.add_argument("--n-hi-log2", type=float, default=24.0)
@@ -663,9 +792,13 @@ def main():
     ap.add_argument("--fit-log2", type=int, default=20, help="gate: largest N of the model fit")
     ap.add_argument("--fit-lo-log2", type=int, default=10, help="gate: smallest N of the model fit")
     ap.add_argument("--join-probe-log2", type=int, default=26, help="join: probe keys (log2)")
+    ap.add_argument("--no-check", action="store_true",
+                    help="join, sort: skip the oracle comparison (profiling runs)")
+    ap.add_argument("--chunks-log2", type=int, nargs="+", default=[22, 24],
+                    help="stream: chunk sizes (log2 keys)")
     a = ap.parse_args()
     {"join": suite_join, "c2": suite_c2, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5, "crossover": suite_crossover,
-     "gate": suite_gate, "e2e": suite_e2e}[a.suite](a)
+     "gate": suite_gate, "e2e": suite_e2e, "stream": suite_stream, "sort": suite_sort}[a.suite](a)
 
 
 if __name__ == "__main__":

@@ -315,6 +315,40 @@ int tk_profile_end(double* total_ms, uint64_t* launches);
  * asynchronous; time it with events on `stream`.  TK_EINVAL on a bad argument. */
 int tk_read_probe(const void* buf, uint64_t bytes, uint32_t wg_per_cu, void* sink, void* stream);
 
+/* ---- Chunk-pipelined key-only streaming ------------------------------------------------------
+ * Top-K over a key column left in host memory (paper sec. II-C: only keys and
+ * row-ids cross the host link; sec. IV-A: the link bounds the end-to-end
+ * time).  The column is copied in chunks of `chunk` keys into two device
+ * staging buffers on `copy_stream` while the previous chunk's Top-K runs on
+ * `stream`; each chunk's best min(k, chunk) pairs, with their column row-ids,
+ * are merged into the running result by one more Top-K over the two lists.
+ * The result equals tk_topk over the whole column: the best K of the column
+ * are among the union of the chunks' best K, and every step breaks ties by
+ * row-id.  The device holds two chunks and a few K-sized lists, so n may
+ * exceed the device memory.
+ *   h_keys      host array of n keys; pinned (hipHostMalloc) for the copies to
+ *               overlap the queries, pageable works but copies synchronously
+ *   h_rowids    host array of n row-ids of rid_type, or NULL (row-id = column
+ *               position, also across chunks)
+ *   chunk       keys per chunk (0: 2^24)
+ *   out_keys, out_rowids, out_count   as for tk_topk (device outputs)
+ *   workspace   device buffer of >= tk_stream_workspace_size bytes, 256-byte
+ *               aligned, needing no initialization
+ *   stream      compute stream; copy_stream: the stream of the copies (NULL:
+ *               the compute stream, no overlap).  The copies wait for the work
+ *               enqueued on `stream` before the call; the outputs are valid
+ *               once `stream` passes the call, and the host arrays must stay
+ *               unchanged until then.
+ * Stream-ordered and asynchronous.  TK_EINVAL on a bad argument (nothing
+ * enqueued); TK_EHIP if a runtime call fails part-way (the outputs are then
+ * undefined). */
+size_t tk_stream_workspace_size(uint64_t n, uint64_t k, uint64_t chunk, int key_type, int rid_type,
+                                int with_rowids);
+int tk_topk_stream(const void* h_keys, const void* h_rowids, uint64_t n, uint64_t k, int key_type,
+                   int rid_type, int order, uint64_t chunk, void* out_keys, void* out_rowids,
+                   uint64_t* out_count, void* workspace, size_t workspace_bytes, void* stream,
+                   void* copy_stream);
+
 /* ---- Full sort: ORDER BY key without LIMIT ---------------------------------------------------
  * The query template of sec. V-B with K = N: every pair, in the order every
  * Top-K call uses (key descending or ascending, equal keys by ascending

@@ -72,6 +72,11 @@ def lib():
         L.tk_profile_end.restype = i32
         L.tk_read_probe.argtypes = [vp, u64, ctypes.c_uint32, vp, vp]
         L.tk_read_probe.restype = i32
+        L.tk_stream_workspace_size.argtypes = [u64, u64, u64, i32, i32, i32]
+        L.tk_stream_workspace_size.restype = ctypes.c_size_t
+        L.tk_topk_stream.argtypes = [vp, vp, u64, u64, i32, i32, i32, u64, vp, vp,
+                                     ctypes.POINTER(u64), vp, ctypes.c_size_t, vp, vp]
+        L.tk_topk_stream.restype = i32
         L.tk_sort_workspace_size.argtypes = [u64, i32, i32]
         L.tk_sort_workspace_size.restype = ctypes.c_size_t
         L.tk_sort.argtypes = [vp, vp, u64, i32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp]
@@ -208,6 +213,59 @@ def topk_noalloc(keys, k: int, out_keys, out_rowids, rowids=None, order="desc", 
                                key_code(keys.dtype), rc_, order_code(order), _ptr(out_keys),
                                _ptr(out_rowids), ctypes.byref(cnt), _stream_handle(stream))
     check(rc, "tk_topk_noalloc")
+    return out_keys, out_rowids
+
+
+def _host_ptr(a) -> int | None:
+    """Address of a host array: a CPU torch tensor (pinned or not) or a numpy array."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise TopKError("host arrays must be contiguous")
+        return a.ctypes.data
+    if a.is_cuda or not a.is_contiguous():
+        raise TopKError("host arrays must be contiguous CPU tensors or numpy arrays")
+    return a.data_ptr()
+
+
+def topk_stream(h_keys, k: int, h_rowids=None, order="desc", chunk: int = 0, rid_dtype=None,
+                out_keys=None, out_rowids=None, workspace=None, stream=None, copy_stream=None,
+                device="cuda"):
+    """Top-K of a host key column (tk_topk_stream): copied in chunks through two
+    device staging buffers, the copies on ``copy_stream`` overlapping the
+    chunk queries on ``stream``.  ``h_keys``/``h_rowids``: CPU tensors (pinned
+    for overlap) or numpy arrays, unchanged until the stream passes the call.
+    Returns device ``(out_keys, out_rowids)``."""
+    import torch
+    n = int(h_keys.shape[0])
+    kc = key_code(h_keys.dtype)
+    if h_rowids is not None:
+        if int(h_rowids.shape[0]) != n:
+            raise TopKError("h_rowids must have one entry per key")
+        rdt_code = rid_code(h_rowids.dtype)
+    else:
+        rdt_code = rid_code(rid_dtype if rid_dtype is not None else
+                            (torch.uint32 if n <= (1 << 32) else torch.uint64))
+    tdt = torch.uint32 if rdt_code == TK_RID_U32 else torch.uint64
+    kdt = {TK_KEY_I32: torch.int32, TK_KEY_I64: torch.int64, TK_KEY_F32: torch.float32,
+           TK_KEY_F64: torch.float64}[kc]
+    k_eff = min(int(k), n)
+    if out_keys is None:
+        out_keys = torch.empty(k_eff, dtype=kdt, device=device)
+    if out_rowids is None:
+        out_rowids = torch.empty(k_eff, dtype=tdt, device=device)
+    ws_bytes = int(lib().tk_stream_workspace_size(n, int(k), int(chunk), kc, rdt_code,
+                                                  int(h_rowids is not None)))
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+    cnt = ctypes.c_uint64(0)
+    cs = None if copy_stream is None else _stream_handle(copy_stream)
+    rc = lib().tk_topk_stream(_host_ptr(h_keys) if n else None, _host_ptr(h_rowids), n, int(k), kc,
+                              rdt_code, order_code(order), int(chunk), _ptr(out_keys),
+                              _ptr(out_rowids), ctypes.byref(cnt), workspace.data_ptr(),
+                              workspace.numel(), _stream_handle(stream), cs)
+    check(rc, "tk_topk_stream")
     return out_keys, out_rowids
 
 

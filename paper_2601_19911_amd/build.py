@@ -17,7 +17,7 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmitopk.so")
 HIPCC = "/opt/rocm/bin/hipcc"
 
-SOURCES = ["tk_single.hip", "tk_sampled.hip", "tk_multi.hip", "tk_batched.hip", "tk_serve.hip", "tk_gather.hip", "tk_probe.hip", "tk_join.hip", "tk_sort.hip", "tk_cpu.cpp"]
+SOURCES = ["tk_single.hip", "tk_sampled.hip", "tk_multi.hip", "tk_batched.hip", "tk_serve.hip", "tk_gather.hip", "tk_probe.hip", "tk_join.hip", "tk_sort.hip", "tk_stream.hip", "tk_cpu.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 # packed fp32 instructions are switched off for all device code

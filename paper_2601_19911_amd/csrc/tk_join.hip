@@ -17,7 +17,7 @@
 //
 // Memory behaviour on MI355X: the probe is bound by random reads of slots
 // (one slot usually, in one 128-byte line; adjacent slots of a run share it).
-// Probe keys stream in coalesced; matches are staged per wave in LDS and
+// Probe keys stream in coalesced; matches are staged per workgroup in LDS and
 // written out contiguously behind one global atomic per stage flush.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -31,8 +31,7 @@ constexpr uint64_t JOIN_HEADER_BYTES = 256;
 constexpr uint64_t JOIN_MAX_BUILD = 1ull << 31;
 constexpr int PROBE_NT = 256;   // threads per probe workgroup
 constexpr int PROBE_PER = 4;    // probe keys per thread per tile
-constexpr int STAGE = 256;      // staged matches per wave
-constexpr int PROBE_WG_PER_CU = 8;
+constexpr int PROBE_WG_PER_CU = 4;
 
 struct JoinHeader {
   unsigned long long side_count;  // build keys equal to the empty marker
@@ -154,110 +153,155 @@ struct ProbeArgs {
   unsigned long long* count;
 };
 
-// Writes one wave's `fill` staged matches behind one global atomic; pairs past
-// the output capacity are counted but not written.
+// Matches are staged per workgroup in LDS and written out behind one global
+// atomic per flush: the output counter is a single address that every
+// workgroup of the device updates, so the number of updates, not the bytes,
+// bounds the probe when they are frequent (a flush per wave and 256 matches
+// took 2.4 ms for 2^26 probes at a hit rate of 1/2, whatever the table size).
+// A stage of 32 KiB is flushed once it holds 3/4 of its capacity; matches
+// that find it full go straight to the output behind one atomic per wave.
 template <typename BR, typename PR>
-__device__ __forceinline__ void flush_stage(const PR* sp, const BR* sb, uint32_t fill,
+struct ProbeStage {
+  static constexpr uint32_t CAP = 32768u / (uint32_t)(sizeof(PR) + sizeof(BR));
+  PR p[CAP];
+  BR b[CAP];
+  unsigned long long fill;  // reservations made (may pass CAP; those past it were spilled)
+  unsigned long long base;
+};
+
+template <typename BR, typename PR>
+__device__ __forceinline__ void stage_match(bool emit, PR pr, BR br, ProbeStage<BR, PR>& st,
                                             PR* __restrict__ out_p, BR* __restrict__ out_b,
-                                            uint64_t cap, unsigned long long* count, uint32_t ln) {
-  __builtin_amdgcn_wave_barrier();
-  unsigned long long base = 0;
-  if (ln == 0) base = atomicAdd(count, (unsigned long long)fill);
-  base = __shfl(base, 0, 64);
-  for (uint32_t i = ln; i < fill; i += 64) {
-    const uint64_t o = base + i;
+                                            uint64_t cap, unsigned long long* count) {
+  constexpr uint32_t CAP = ProbeStage<BR, PR>::CAP;
+  const uint64_t m = tk::ballot(emit);
+  if (m == 0) return;
+  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+  unsigned long long b = 0;
+  if (tk::lane_id() == leader) b = atomicAdd(&st.fill, (unsigned long long)__popcll(m));
+  b = __shfl(b, (int)leader, 64);
+  const uint64_t pos = b + tk::lanes_below(m);
+  if (emit && pos < CAP) {
+    st.p[pos] = pr;
+    st.b[pos] = br;
+  }
+  const bool spill = emit && pos >= CAP;
+  const uint64_t ms = tk::ballot(spill);
+  if (ms == 0) return;
+  const uint32_t l2 = (uint32_t)__builtin_ctzll(ms);
+  unsigned long long g = 0;
+  if (tk::lane_id() == l2) g = atomicAdd(count, (unsigned long long)__popcll(ms));
+  g = __shfl(g, (int)l2, 64);
+  if (spill) {
+    const uint64_t o = g + tk::lanes_below(ms);
     if (o < cap) {
-      out_p[o] = sp[i];
-      out_b[o] = sb[i];
+      out_p[o] = pr;
+      out_b[o] = br;
     }
   }
-  __builtin_amdgcn_wave_barrier();
 }
 
+// Whole workgroup: writes the staged matches behind one global atomic and
+// empties the stage.  Pairs past the output capacity are counted, not written.
+template <typename BR, typename PR>
+__device__ __forceinline__ void flush_stage(ProbeStage<BR, PR>& st, PR* __restrict__ out_p,
+                                            BR* __restrict__ out_b, uint64_t cap,
+                                            unsigned long long* count) {
+  constexpr uint32_t CAP = ProbeStage<BR, PR>::CAP;
+  __syncthreads();  // every stage write is done
+  const uint32_t c = st.fill < CAP ? (uint32_t)st.fill : CAP;
+  if (threadIdx.x == 0) st.base = c ? atomicAdd(count, (unsigned long long)c) : 0ull;
+  __syncthreads();
+  const uint64_t base = st.base;
+  for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) {
+    const uint64_t o = base + i;
+    if (o < cap) {
+      out_p[o] = st.p[i];
+      out_b[o] = st.b[i];
+    }
+  }
+  __syncthreads();  // the stage has been read
+  if (threadIdx.x == 0) st.fill = 0;
+  __syncthreads();
+}
+
+// Every tile: each thread's PROBE_PER keys are loaded, then their first slots;
+// the linear-probing walks of all of them advance together, one slot each per
+// round, so a thread has up to PROBE_PER dependent slot loads in flight.  Keys
+// equal to the empty marker are served from the side list afterwards.
 template <int KT, typename W, typename BR, typename PR>
 __global__ __launch_bounds__(PROBE_NT) void k_jprobe(ProbeArgs<W, BR, PR> a) {
   using Raw = typename JKey<KT>::Raw;
   constexpr Raw EMPTY = JKey<KT>::EMPTY;
   constexpr uint64_t TILE = (uint64_t)PROBE_NT * PROBE_PER;
-  __shared__ PR sp[PROBE_NT / 64][STAGE];
-  __shared__ BR sb[PROBE_NT / 64][STAGE];
-  const uint32_t wv = threadIdx.x >> 6, ln = tk::lane_id();
+  constexpr uint32_t FLUSH_AT = ProbeStage<BR, PR>::CAP / 4 * 3;
+  __shared__ ProbeStage<BR, PR> st;
+  if (threadIdx.x == 0) st.fill = 0;
+  __syncthreads();
   const Raw* __restrict__ keys = static_cast<const Raw*>(a.keys);
   const bool dup = a.hdr->dup != 0;
   const uint64_t side_n = a.hdr->side_count;
-  uint32_t fill = 0;  // wave-uniform
 
   for (uint64_t base = (uint64_t)blockIdx.x * TILE; base < a.n; base += (uint64_t)gridDim.x * TILE) {
     Raw key[PROBE_PER];
     uint64_t pos[PROBE_PER];
     Slot<W> cur[PROBE_PER];
-    // every key of the tile first, then every first slot: the random reads of
-    // a thread's keys are in flight together
+    bool act[PROBE_PER], side[PROBE_PER];
 #pragma unroll
     for (int q = 0; q < PROBE_PER; ++q) {
       const uint64_t j = base + (uint64_t)q * PROBE_NT + threadIdx.x;
       key[q] = j < a.n ? keys[j] : EMPTY;
+      side[q] = j < a.n && key[q] == EMPTY;
+      act[q] = j < a.n && key[q] != EMPTY;
     }
 #pragma unroll
     for (int q = 0; q < PROBE_PER; ++q) {
       pos[q] = slot_of((uint64_t)key[q], a.shift);
       cur[q].key = (W)EMPTY;
       cur[q].rid = 0;
-      if (key[q] != EMPTY) cur[q] = a.slots[pos[q]];
+      if (act[q]) cur[q] = a.slots[pos[q]];
+    }
+    while (true) {
+      bool any = false;
+#pragma unroll
+      for (int q = 0; q < PROBE_PER; ++q) {
+        bool emit = false;
+        BR brid = 0;
+        if (act[q]) {
+          if (cur[q].key == (W)EMPTY) {
+            act[q] = false;
+          } else {
+            if (cur[q].key == (W)key[q]) {
+              emit = true;
+              brid = (BR)cur[q].rid;
+              if (!dup) act[q] = false;
+            }
+            if (act[q]) pos[q] = (pos[q] + 1) & a.mask;
+          }
+        }
+        const uint64_t j = base + (uint64_t)q * PROBE_NT + threadIdx.x;
+        stage_match<BR, PR>(emit, emit ? (a.rids ? a.rids[j] : (PR)j) : (PR)0, brid, st, a.out_p,
+                            a.out_b, a.cap, a.count);
+        any |= act[q];
+      }
+      if (tk::ballot(any) == 0) break;
+#pragma unroll
+      for (int q = 0; q < PROBE_PER; ++q)
+        if (act[q]) cur[q] = a.slots[pos[q]];
     }
 #pragma unroll
     for (int q = 0; q < PROBE_PER; ++q) {
+      if (tk::ballot(side[q]) == 0 || side_n == 0) continue;
       const uint64_t j = base + (uint64_t)q * PROBE_NT + threadIdx.x;
-      bool act = j < a.n;
-      const bool side = key[q] == EMPTY;
-      const W kw = (W)key[q];
-      uint64_t p = pos[q], t = 0;
-      Slot<W> c = cur[q];
-      while (true) {
-        bool emit = false;
-        BR brid = 0;
-        if (act) {
-          if (side) {
-            if (t < side_n) {
-              emit = true;
-              brid = a.side[t];
-              ++t;
-            } else {
-              act = false;
-            }
-          } else if (c.key == (W)EMPTY) {
-            act = false;
-          } else {
-            if (c.key == kw) {
-              emit = true;
-              brid = (BR)c.rid;
-              if (!dup) act = false;
-            }
-            if (act) {
-              p = (p + 1) & a.mask;
-              c = a.slots[p];
-            }
-          }
-        }
-        const uint64_t m = tk::ballot(emit);
-        if (m) {
-          const uint32_t nm = (uint32_t)__popcll(m);
-          if (fill + nm > (uint32_t)STAGE) {
-            flush_stage(sp[wv], sb[wv], fill, a.out_p, a.out_b, a.cap, a.count, ln);
-            fill = 0;
-          }
-          if (emit) {
-            const uint32_t at = fill + tk::lanes_below(m);
-            sp[wv][at] = a.rids ? a.rids[j] : (PR)j;
-            sb[wv][at] = brid;
-          }
-          fill += nm;
-        }
-        if (tk::ballot(act) == 0) break;
-      }
+      const PR pr = side[q] ? (a.rids ? a.rids[j] : (PR)j) : (PR)0;
+      for (uint64_t t = 0; t < side_n; ++t)
+        stage_match<BR, PR>(side[q], pr, side[q] ? a.side[t] : (BR)0, st, a.out_p, a.out_b, a.cap,
+                            a.count);
     }
+    __syncthreads();
+    if (st.fill >= FLUSH_AT) flush_stage<BR, PR>(st, a.out_p, a.out_b, a.cap, a.count);
   }
-  if (fill) flush_stage(sp[wv], sb[wv], fill, a.out_p, a.out_b, a.cap, a.count, ln);
+  flush_stage<BR, PR>(st, a.out_p, a.out_b, a.cap, a.count);
 }
 
 __global__ void k_jclear(unsigned long long* count) { *count = 0; }
