@@ -34,6 +34,8 @@ def parse(argv=None):
                     help="CPU budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the result")
+    ap.add_argument("--no-f64", action="store_true",
+                    help="skip the float64 record measured beside a float32 run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--read-ceiling", action="store_true",
@@ -262,7 +264,21 @@ def main():
     if args.read_ceiling:
         read_ceiling()
         return
-    print(json.dumps(measure(args)), flush=True)
+    rec = measure(args)
+    if args.dtype == "float32" and not args.no_f64:
+        # the paper's own key type (double, sec. V-A) on the same workload, as
+        # a second record inside the line
+        a2 = parse([f"--log2n={args.log2n}", f"--k={args.k}", "--dtype=float64", f"--dist={args.dist}",
+                    f"--order={args.order}", f"--steps={args.steps}", f"--warmup={args.warmup}",
+                    "--no-cpu"] + (["--no-check"] if args.no_check else []))
+        r2 = measure(a2)
+        rec["float64_headline"] = {
+            "workload": r2["config"]["workload"], "value": r2["value"], "unit": "keys/s",
+            "ms_per_step": r2["ms_per_step"], "whole_query_frac_of_peak": r2["whole_query_frac_of_peak"],
+            "kernel_frac_of_peak": r2["roofline"]["frac"], "kernel_avg_ms": r2["roofline"]["kernel_avg_ms"],
+            "alg_bytes_per_launch": r2["roofline"]["alg_bytes_per_launch"], "path": r2["path"],
+            "oracle_match": r2["oracle_match"]}
+    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -121,43 +121,29 @@ def suite_c3(a):
     L = tk.lib()
     reps = a.reps
 
-    # (i)/(ii) per-query tk_topk launches on S streams, all queries released at t0
+    # (i)/(ii) per-query tk_topk launches from C (tk_topk_each) on S streams, all
+    # queries released at t0 (a start event every stream waits for); per-query
+    # completion times from an event after each query
     def per_query(nstreams):
+        from paper_2601_19911_amd.batched import topk_each
         streams = [torch.cuda.Stream() for _ in range(nstreams)]
-        wsb = max(tk.workspace_size(int(n), int(k), tk.TK_KEY_I64, tk.TK_RID_U32)
-                  for n, k in zip(ns, kef))
-        wss = [torch.zeros(wsb, dtype=torch.uint8, device=dev) for _ in range(nstreams)]
         ok = torch.empty(int(oo[-1]), dtype=torch.int64, device=dev)
         orr = torch.empty(int(oo[-1]), dtype=torch.uint32, device=dev)
-        cnt = ctypes.c_uint64()
         best = None
         for rep in range(reps + 1):
-            evs = [torch.cuda.Event(enable_timing=True) for _ in range(Q)]
-            t0 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
-            t0.record(torch.cuda.current_stream())
-            for s in streams:
-                s.wait_event(t0)
             w0 = time.perf_counter()
-            for q in range(Q):
-                s = streams[q % nstreams]
-                rc = L.tk_topk(kp + int(off[q]) * 8, None, int(ns[q]), int(ks[q]), tk.TK_KEY_I64,
-                               tk.TK_RID_U32, int(orders[q]), ok.data_ptr() + int(oo[q]) * 8,
-                               orr.data_ptr() + int(oo[q]) * 4, ctypes.byref(cnt),
-                               wss[q % nstreams].data_ptr(), wsb, s.cuda_stream)
-                tk.check(rc, "tk_topk")
-                evs[q].record(s)
-            torch.cuda.synchronize()
+            lat = topk_each(off, ks, orders, keys, ok, orr, streams)
             wall = time.perf_counter() - w0
-            lat = np.array([t0.elapsed_time(e) for e in evs]) * 1e-3
             total_s = float(lat.max())
             if rep and (best is None or total_s < best[0]):
                 best = (total_s, lat, wall)
         return best, ok, orr
 
-    def plan_run():
+    def plan_run(params, label):
         s = torch.cuda.Stream()
-        plan = Plan(off, ks, orders, key_dtype=torch.int64, rid_dtype=torch.uint32, stream=s)
+        plan = Plan(off, ks, orders, key_dtype=torch.int64, rid_dtype=torch.uint32, stream=s,
+                    **params)
         ok, orr = plan.alloc_outputs()
         torch.cuda.synchronize()
         plan.launch(keys, ok, orr, stream=s)  # eager first launch
@@ -173,9 +159,9 @@ def suite_c3(a):
             t1.record(s)
             torch.cuda.synchronize()
             total_s = t0.elapsed_time(t1) * 1e-3
-            # every query of a launch completes when the launch does: its
-            # latency from the common release time is the launch time
-            lat = np.full(Q, total_s)
+            # per-query completion from the device clock: each query's tail
+            # stamps its end, the launch's first kernel its start
+            lat = plan.query_times()
             st = plan.stats()
             if best is None or total_s < best[0]:
                 best = (total_s, lat, st)
@@ -190,13 +176,28 @@ def suite_c3(a):
               "lat_p50_ms": pct(lat, 50) * 1e3, "lat_p95_ms": pct(lat, 95) * 1e3,
               "lat_p99_ms": pct(lat, 99) * 1e3, "lat_max_ms": float(np.max(lat)) * 1e3, **extra})
 
-    (pb, pok, porr, pinfo, plan) = plan_run()
-    report("batched_plan", pb[0], pb[1], {"plan": pinfo, "stats": pb[2], "reps": reps})
+    from paper_2601_19911_amd import autotune
+    (pb, pok, porr, pinfo, plan) = plan_run({}, "default")
+    report("batched_plan", pb[0], pb[1], {"plan": pinfo, "stats": pb[2], "reps": reps,
+                                          "params": "default"})
     pk, pr = dev_view_np(pok), dev_view_np(porr)
+    if a.tune:
+        cache = os.path.join(a.tune_cache_dir, "tuned_plans.json") if a.tune_cache_dir else None
+        best, secs, table = autotune.tune(off, ks, orders, keys, quick=a.quick, reps=2,
+                                          cache_path=cache)
+        for row in table:
+            emit({"suite": "c3", "tune_candidate": row})
+        (tb, tok, torr, tinfo, tplan) = plan_run(best, "tuned")
+        report("batched_plan_tuned", tb[0], tb[1], {"plan": tinfo, "stats": tb[2], "reps": reps,
+                                                    "params": best})
+        tuned_same = bool(np.array_equal(dev_view_np(tok), pk) and np.array_equal(dev_view_np(torr), pr))
+        emit({"suite": "c3", "check": "tuned_equals_default", "equal": tuned_same})
+        tplan.close()
     results = {}
     for S in (1, 4):
         (b, ok, orr) = per_query(S)
-        report(f"per_query_{S}_stream", b[0], b[1], {"host_submit_s": b[2], "reps": reps})
+        report(f"per_query_{S}_stream", b[0], b[1], {"host_call_s": b[2], "reps": reps,
+                                                       "launched_from": "C (tk_topk_each)"})
         results[S] = (dev_view_np(ok), dev_view_np(orr))
     # parity: per-query == batched everywhere; a sample of queries == oracle
     agree = all(np.array_equal(results[S][0], pk) and np.array_equal(results[S][1], pr)
@@ -792,6 +793,9 @@ def main():
     ap.add_argument("--fit-log2", type=int, default=20, help="gate: largest N of the model fit")
     ap.add_argument("--fit-lo-log2", type=int, default=10, help="gate: smallest N of the model fit")
     ap.add_argument("--join-probe-log2", type=int, default=26, help="join: probe keys (log2)")
+    ap.add_argument("--tune", action="store_true", help="c3: also autotune the plan and time it")
+    ap.add_argument("--tune-cache-dir", type=str, default="",
+                    help="c3: where the tuned parameters are stored (default: the package's cache)")
     ap.add_argument("--no-check", action="store_true",
                     help="join, sort: skip the oracle comparison (profiling runs)")
     ap.add_argument("--chunks-log2", type=int, nargs="+", default=[22, 24],

@@ -107,7 +107,9 @@ typedef struct {
                            7 a small query (N within one LDS tile) ranked across
                            workgroups over the whole input;
                            4 sampled, but the sample misjudged: exact select
-                           over the input; 5 exact radix select over the input
+                           over the input (by the whole device from 2^29 keys,
+                           see tk_tuning.recover_min_log2; by one workgroup
+                           below); 5 exact radix select over the input
                            (no usable sample: N below 2^15, K above N / 2, or K
                            above N / 16 with N above 2^20); 0 after a
                            one-workgroup query (N within one LDS tile, K > 2048) */
@@ -132,6 +134,11 @@ typedef struct {
                                 (default), 2: one workgroup selects and sorts them */
   int32_t filter_unroll;     /* 16-byte loads in flight per thread in the streaming pass:
                                 4 or 8 (others leave it unchanged) */
+  int32_t recover_min_log2;  /* sampled queries of at least 2^this keys (default 29) enqueue a
+                                cooperative exact select over the device, which returns at
+                                once unless the sample misjudged (the launch itself costs
+                                about 21 us per query); smaller ones (or all, when < 0) fall
+                                back to one workgroup's select over the input */
 } tk_tuning;
 int tk_set_tuning(const tk_tuning* t);
 
@@ -148,8 +155,9 @@ int tk_set_tuning(const tk_tuning* t);
  * kernels over all queries (sample workgroups, one threshold workgroup per
  * sampled query, filter workgroups, one tail workgroup per query); from the
  * second launch with the same pointers and stream they are replayed from a
- * captured hipGraph.  Results equal tk_topk on
- * each query alone. */
+ * captured hipGraph.  A one-thread kernel before them stamps the launch's
+ * start and every tail workgroup its query's end (tk_plan_query_times).
+ * Results equal tk_topk on each query alone. */
 typedef struct tk_plan tk_plan;
 typedef struct {
   uint32_t tile_keys;        /* keys each filter workgroup streams; 0: 65536 (>= 4096) */
@@ -160,6 +168,8 @@ typedef struct {
   int32_t use_graph;         /* >= 0: capture launches on a created stream in a hipGraph and
                                 replay it (the default stream is never captured: launches
                                 there are direct); < 0: always launch directly */
+  double cap_sigma;          /* survivor capacity margin (std devs); 0: the process tuning's
+                                (default 6) */
 } tk_plan_params;
 
 /* Workspace bytes for a plan (0 on invalid arguments).  Host arrays:
@@ -168,12 +178,12 @@ size_t tk_plan_workspace_size(const uint64_t* offsets, const uint32_t* ks, const
                               uint32_t q, int key_type, int rid_type, const tk_plan_params* params);
 /* Creates a plan bound to `workspace` (device, 256-byte aligned, at least
  * tk_plan_workspace_size bytes, needing no initialization, owned by the
- * caller and reserved for the plan until
- * tk_plan_destroy).  *plan receives an object owned by the library.
- * `stream` is kept for compatibility and not used. */
+ * caller and reserved for the plan until tk_plan_destroy).  *plan receives an
+ * object owned by the library, which also holds a pinned host staging buffer
+ * of the plan's argument records.  Enqueues nothing. */
 int tk_plan_create(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders, uint32_t q,
                    int key_type, int rid_type, const tk_plan_params* params, void* workspace,
-                   size_t workspace_bytes, void* stream, tk_plan** plan);
+                   size_t workspace_bytes, tk_plan** plan);
 /* out_offsets[q+1]: where each query's results start in the packed outputs. */
 int tk_plan_output_offsets(const tk_plan* plan, uint64_t* out_offsets);
 /* Queries on the sampled route, queries on the whole-input route, and the
@@ -182,18 +192,40 @@ int tk_plan_info(const tk_plan* plan, uint32_t* n_sampled, uint32_t* n_exact, ui
 /* Runs every query of the plan on `stream` (asynchronous).  keys: the packed
  * device key buffer; rowids: packed row-ids or NULL; out_keys/out_rowids:
  * packed outputs (out_keys may be NULL).  When the pointer set differs from
- * the previous launch, the per-query argument records are uploaded first
- * (a synchronous copy on `stream`).  Calls on one plan must not overlap. */
+ * the previous launch, the per-query argument records are uploaded first, by
+ * an asynchronous copy on `stream` from the plan's pinned staging (the host
+ * waits only if the previous upload's copy has not yet run).  Calls on one
+ * plan must not overlap. */
 int tk_plan_launch(tk_plan* plan, const void* keys, const void* rowids, void* out_keys,
                    void* out_rowids, void* stream);
-/* Per-query device completion times are not recorded by this design: every
- * query of a launch completes when the launch does.  Returns TK_EUNSUPPORTED. */
+/* Per-query completion times of the last launch: seconds[i] is the time from
+ * the launch's start (a stamp its first kernel writes) to the end of query i's
+ * tail workgroup, both read from the device's constant-rate clock (0 for a
+ * query with min(k, n) = 0).  Every query's tail writes its stamp in every
+ * launch, replays included.  Synchronous copy of q + 1 words; call after the
+ * launch's stream has been synchronized.  TK_EINVAL before the first launch. */
 int tk_plan_query_times(const tk_plan* plan, double* seconds);
 /* After a launch has finished: sampled queries whose sample misjudged (the
  * tail selected over the whole input instead), and sampled queries with no
  * recorded path (must be 0).  Synchronous copy of the 64-byte query states. */
 int tk_plan_stats(const tk_plan* plan, uint32_t* fallbacks, uint32_t* unfinished);
 void tk_plan_destroy(tk_plan* plan);
+
+/* The per-query baseline of the batched form: every query of a plan's
+ * description run as its own tk_topk, enqueued from C in query order,
+ * round robin over `nstreams` streams; results packed as by a plan
+ * (tk_plan_output_offsets).  workspace: nstreams x
+ * tk_topk_each_workspace_size bytes (256-byte aligned), stream s using slice
+ * s.  With `seconds` (q entries) the call also records an event after every
+ * query and a start event that every stream waits for, waits for them all,
+ * and returns each query's completion time from that start; without it the
+ * call is asynchronous.  TK_EINVAL on a bad argument. */
+size_t tk_topk_each_workspace_size(const uint64_t* offsets, const uint32_t* ks, uint32_t q,
+                                   int key_type, int rid_type);
+int tk_topk_each(const void* keys, const void* rowids, const uint64_t* offsets, const uint32_t* ks,
+                 const uint8_t* orders, uint32_t q, int key_type, int rid_type, void* out_keys,
+                 void* out_rowids, void* workspace, size_t workspace_bytes, void* const* streams,
+                 uint32_t nstreams, double* seconds);
 
 /* ---- Served form -----------------------------------------------------------------------------
  * Continuous batching of Top-K requests over key columns with the cost gate

@@ -37,7 +37,8 @@ class tk_tuning(ctypes.Structure):
     _fields_ = [("sample_sigma", ctypes.c_double), ("cap_sigma", ctypes.c_double),
                 ("max_sample_log2", ctypes.c_int32), ("filter_grid", ctypes.c_int32),
                 ("force_cap", ctypes.c_int64), ("force_exact", ctypes.c_int32),
-                ("tail_mode", ctypes.c_int32), ("filter_unroll", ctypes.c_int32)]
+                ("tail_mode", ctypes.c_int32), ("filter_unroll", ctypes.c_int32),
+                ("recover_min_log2", ctypes.c_int32)]
 
 
 def lib():
@@ -309,13 +310,14 @@ def query_info(workspace) -> dict:
 
 
 def set_tuning(sample_sigma=0.0, cap_sigma=0.0, max_sample_log2=0, filter_grid=0, force_cap=0,
-               force_exact=0, tail_mode=0, filter_unroll=0):
+               force_exact=0, tail_mode=0, filter_unroll=0, recover_min_log2=0):
     """Process-wide knobs; 0 leaves a field unchanged (force_cap=-1,
-    force_exact=2, tail_mode=1 and filter_grid=-1 restore the defaults;
-    tail_mode=2 makes one workgroup select and sort the survivors;
-    filter_unroll is 4 or 8)."""
+    force_exact=2, tail_mode=1, filter_grid=-1 and recover_min_log2=29 restore
+    the defaults; tail_mode=2 makes one workgroup select and sort the
+    survivors; filter_unroll is 4 or 8; recover_min_log2=-1 leaves every
+    misjudged sample to one workgroup)."""
     t = tk_tuning(sample_sigma, cap_sigma, max_sample_log2, filter_grid, force_cap, force_exact,
-                  tail_mode, filter_unroll)
+                  tail_mode, filter_unroll, recover_min_log2)
     check(lib().tk_set_tuning(ctypes.byref(t)), "tk_set_tuning")
 
 

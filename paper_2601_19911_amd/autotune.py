@@ -9,7 +9,10 @@ efficiency and survivor traffic:
                      how far above the expected survivor count the sampled
                      threshold sits, and the largest sample: these size the
                      survivor buffers and decide how often the exact fallback
-                     (a second pass over a query) runs.
+                     (a second pass over a query) runs;
+* ``cap_sigma``      the survivor buffers' margin over the expected count;
+* ``filter_grid``    filter workgroups looping over all the slices (0: one
+                     workgroup per slice).
 
 ``tune()`` times every candidate on the caller's own batch (each run is a
 full, exact ``tk_plan_launch``; the tuner never changes a result, only how
@@ -31,15 +34,18 @@ import numpy as np
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_plans.json")
 
 
-def candidates(key_bytes: int, quick: bool = False):
+def candidates(key_bytes: int, quick: bool = False, cus: int = 256):
     """Parameter sets to try, as dicts of tk_plan_params fields."""
     tiles = ([1 << 14, 1 << 15, 1 << 16, 1 << 17] if key_bytes == 8 else
              [1 << 15, 1 << 16, 1 << 17, 1 << 18])
     sigmas = [(3.0, 20), (2.0, 20), (4.0, 22), (3.0, 18)]
+    caps = [6.0, 4.0]
+    grids = [0, 3 * cus]
     if quick:
-        tiles, sigmas = tiles[1:3], sigmas[:2]
-    return [{"tile_keys": t, "sample_sigma": s, "max_sample_log2": m}
-            for t, (s, m) in itertools.product(tiles, sigmas)]
+        tiles, sigmas, caps, grids = tiles[1:3], sigmas[:2], caps[:1], grids
+    return [{"tile_keys": t, "sample_sigma": s, "max_sample_log2": m, "cap_sigma": c,
+             "filter_grid": g}
+            for t, (s, m), c, g in itertools.product(tiles, sigmas, caps, grids)]
 
 
 def _key(device_name: str, key_dtype: str) -> str:
@@ -82,7 +88,8 @@ def tune(offsets, ks, orders, keys, rid_dtype=None, reps: int = 3, quick: bool =
     s = stream or torch.cuda.Stream()
     table = []
     best = None
-    for p in candidates(keys.element_size(), quick):
+    cus = torch.cuda.get_device_properties(keys.device).multi_processor_count
+    for p in candidates(keys.element_size(), quick, cus):
         plan = Plan(offsets, ks, orders, key_dtype=keys.dtype, rid_dtype=rid_dtype, stream=s, **p)
         ok, orr = plan.alloc_outputs()
         torch.cuda.synchronize()

@@ -39,6 +39,11 @@ struct tk_plan {
   hipGraph_t graph = nullptr;
   hipStream_t g_stream = nullptr;
   bool warm = false;              // this pointer set has run once on g_stream
+  // pinned staging of the records: the upload is an asynchronous copy on the
+  // launch stream; the event marks when the copy has read the staging
+  char* h_stage = nullptr;
+  hipEvent_t staged = nullptr;
+  bool stage_pending = false;
   std::mutex mu;
 };
 
@@ -53,6 +58,7 @@ Tuning plan_tuning(const tk_plan_params* p) {
     if (p->min_sample_log2) t.min_sample_log2 = p->min_sample_log2;
     if (p->max_sample_log2) t.max_sample_log2 = p->max_sample_log2;
     if (p->sample_sigma > 0) t.sample_sigma = p->sample_sigma;
+    if (p->cap_sigma > 0) t.cap_sigma = p->cap_sigma;
   }
   return t;
 }
@@ -93,8 +99,14 @@ size_t build(tk_plan& P, const uint64_t* offsets, const uint32_t* ks, const uint
   sizes.fa.resize(P.L.n_sampled);
   sizes.fmap.resize(P.L.n_filt_blocks);
   sizes.ta.resize(P.L.n_sampled + P.L.n_input);
+  sizes.tq.resize(P.L.n_sampled + P.L.n_input);
   P.rec_bytes = multi_pack_bytes(sizes);
-  return lay + P.rec_bytes;
+  return lay + P.rec_bytes + align_up((uint64_t)(q + 1) * sizeof(unsigned long long), 256);
+}
+
+// Device address of the plan's completion stamps: after the layout and the records.
+unsigned long long* stamps_of(tk_plan& P) {
+  return reinterpret_cast<unsigned long long*>(P.ws + P.L.total + P.rec_bytes);
 }
 
 int upload(tk_plan& P, const void* keys, const void* rowids, void* out_keys, void* out_rowids,
@@ -114,15 +126,27 @@ int upload(tk_plan& P, const void* keys, const void* rowids, void* out_keys, voi
   MRecords r;
   multi_records(qs, P.L, P.key_type, P.rid_type, P.ws, r);
   const uint64_t bytes = multi_pack_bytes(r);
-  if (P.L.total + bytes > P.ws_bytes) return TK_EINVAL;
-  std::vector<char> host(bytes + 256);
+  if (bytes != P.rec_bytes) return TK_EINVAL;
+  // the staging is rewritten only once the previous upload's copy has read it
+  // (in practice long done: uploads happen when the pointer set changes)
+  if (P.stage_pending && hipEventSynchronize(P.staged) != hipSuccess) return TK_EHIP;
+  P.stage_pending = false;
   char* dev = P.ws + P.L.total;
-  P.launch = multi_pack(r, host.data(), dev);
+  P.launch = multi_pack(r, P.h_stage, dev);
   P.launch.filt_grid = P.params.filter_grid;
-  if (hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
+  P.launch.stamps = stamps_of(P);
+  if (hipMemcpyAsync(dev, P.h_stage, bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipEventRecord(P.staged, st) != hipSuccess)
     return TK_EHIP;
+  P.stage_pending = true;
   return TK_OK;
+}
+
+void release(tk_plan* P) {
+  if (P->stage_pending) (void)hipEventSynchronize(P->staged);
+  if (P->staged) (void)hipEventDestroy(P->staged);
+  if (P->h_stage) (void)hipHostFree(P->h_stage);
+  delete P;
 }
 
 void drop_graph(tk_plan& P) {
@@ -151,8 +175,7 @@ extern "C" size_t tk_plan_workspace_size(const uint64_t* offsets, const uint32_t
 extern "C" int tk_plan_create(const uint64_t* offsets, const uint32_t* ks, const uint8_t* orders,
                               uint32_t q, int key_type, int rid_type,
                               const tk_plan_params* params, void* workspace,
-                              size_t workspace_bytes, void* stream, tk_plan** out) {
-  (void)stream;
+                              size_t workspace_bytes, tk_plan** out) {
   if (!out || !valid_inputs(offsets, ks, orders, q, key_type, rid_type, params)) return TK_EINVAL;
   if (!workspace || ((uintptr_t)workspace & 255u)) return TK_EINVAL;
   tk_plan* P = new (std::nothrow) tk_plan;
@@ -166,6 +189,12 @@ extern "C" int tk_plan_create(const uint64_t* offsets, const uint32_t* ks, const
   if (workspace_bytes < need) {
     delete P;
     return TK_EINVAL;
+  }
+  if (hipHostMalloc((void**)&P->h_stage, P->rec_bytes ? P->rec_bytes : 256, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&P->staged, hipEventDisableTiming) != hipSuccess) {
+    release(P);
+    return TK_EHIP;
   }
   P->ws = static_cast<char*>(workspace);
   P->ws_bytes = workspace_bytes;
@@ -238,9 +267,20 @@ extern "C" int tk_plan_launch(tk_plan* P, const void* keys, const void* rowids, 
 }
 
 extern "C" int tk_plan_query_times(const tk_plan* P, double* seconds) {
-  (void)P;
-  (void)seconds;
-  return TK_EUNSUPPORTED;
+  if (!P || !seconds) return TK_EINVAL;
+  if (!P->uploaded) return TK_EINVAL;  // no launch yet
+  std::vector<unsigned long long> st(P->q + 1);
+  if (hipMemcpy(st.data(), const_cast<tk_plan*>(P)->ws + P->L.total + P->rec_bytes,
+                st.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess)
+    return TK_EHIP;
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return TK_EHIP;
+  const double hz = (double)khz * 1e3;
+  for (uint32_t i = 0; i < P->q; ++i)
+    seconds[i] = P->L.cls[i] == MC_EMPTY ? 0.0 : (double)(int64_t)(st[1 + i] - st[0]) / hz;
+  return TK_OK;
 }
 
 extern "C" int tk_plan_stats(const tk_plan* P, uint32_t* fallbacks, uint32_t* unfinished) {
@@ -262,5 +302,81 @@ extern "C" int tk_plan_stats(const tk_plan* P, uint32_t* fallbacks, uint32_t* un
 extern "C" void tk_plan_destroy(tk_plan* P) {
   if (!P) return;
   drop_graph(*P);
-  delete P;
+  release(P);
+}
+
+// ---- per-query launches from C: the baseline of the batched form ---------------------------
+
+extern "C" size_t tk_topk_each_workspace_size(const uint64_t* offsets, const uint32_t* ks,
+                                              uint32_t q, int key_type, int rid_type) {
+  if (!offsets || !ks || key_type < 0 || key_type > 3 || rid_type < 0 || rid_type > 1) return 0;
+  size_t m = 256;
+  for (uint32_t i = 0; i < q; ++i) {
+    if (offsets[i + 1] < offsets[i]) return 0;
+    const size_t w = tk_workspace_size(offsets[i + 1] - offsets[i], ks[i], key_type, rid_type);
+    m = w > m ? w : m;
+  }
+  return align_up(m, 256);
+}
+
+extern "C" int tk_topk_each(const void* keys, const void* rowids, const uint64_t* offsets,
+                            const uint32_t* ks, const uint8_t* orders, uint32_t q, int key_type,
+                            int rid_type, void* out_keys, void* out_rowids, void* workspace,
+                            size_t workspace_bytes, void* const* streams, uint32_t nstreams,
+                            double* seconds) {
+  if (!keys || !out_rowids || !offsets || !ks || !orders || !workspace || !streams || nstreams == 0)
+    return TK_EINVAL;
+  if (key_type < 0 || key_type > 3 || rid_type < 0 || rid_type > 1) return TK_EINVAL;
+  const size_t per = tk_topk_each_workspace_size(offsets, ks, q, key_type, rid_type);
+  if (per == 0 || workspace_bytes < per * nstreams || ((uintptr_t)workspace & 255u)) return TK_EINVAL;
+  const uint32_t kb = key_bytes(key_type), rb = rid_type == TK_RID_U64 ? 8 : 4;
+  // events: one start on stream 0 that every stream waits for, one per query
+  std::vector<hipEvent_t> ev;
+  auto cleanup = [&]() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  };
+  if (seconds) {
+    ev.assign((size_t)q + 1, nullptr);
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+        cleanup();
+        return TK_EHIP;
+      }
+    if (hipEventRecord(ev[0], (hipStream_t)streams[0]) != hipSuccess) {
+      cleanup();
+      return TK_EHIP;
+    }
+    for (uint32_t s = 1; s < nstreams; ++s)
+      if (hipStreamWaitEvent((hipStream_t)streams[s], ev[0], 0) != hipSuccess) {
+        cleanup();
+        return TK_EHIP;
+      }
+  }
+  uint64_t out = 0;
+  int rc = TK_OK;
+  for (uint32_t i = 0; i < q && rc == TK_OK; ++i) {
+    const uint32_t s = i % nstreams;
+    const uint64_t n = offsets[i + 1] - offsets[i];
+    rc = tk_topk(static_cast<const char*>(keys) + offsets[i] * kb,
+                 rowids ? static_cast<const char*>(rowids) + offsets[i] * rb : nullptr, n, ks[i],
+                 key_type, rid_type, orders[i],
+                 out_keys ? static_cast<char*>(out_keys) + out * kb : nullptr,
+                 static_cast<char*>(out_rowids) + out * rb, nullptr,
+                 static_cast<char*>(workspace) + (size_t)s * per, per, streams[s]);
+    if (rc == TK_OK && seconds && hipEventRecord(ev[1 + i], (hipStream_t)streams[s]) != hipSuccess)
+      rc = TK_EHIP;
+    out += ks[i] < n ? ks[i] : n;
+  }
+  if (rc == TK_OK && seconds) {
+    for (uint32_t i = 0; i < q && rc == TK_OK; ++i) {
+      float ms = 0;
+      if (hipEventSynchronize(ev[1 + i]) != hipSuccess ||
+          hipEventElapsedTime(&ms, ev[0], ev[1 + i]) != hipSuccess)
+        rc = TK_EHIP;
+      seconds[i] = ms * 1e-3;
+    }
+  }
+  cleanup();
+  return rc;
 }

@@ -53,13 +53,24 @@ __global__ __launch_bounds__(FILT_NT) void k_mfilter(const FiltArgs* __restrict_
   }
 }
 
+// One tail workgroup per query; with stamps, its end on the device clock
+// (the constant-rate real-time counter) is recorded as the query's completion.
 template <int KT, int RT>
-__global__ __launch_bounds__(TAIL_NT) void k_mtail(const TailArgs1* __restrict__ ta) {
+__global__ __launch_bounds__(TAIL_NT) void k_mtail(const TailArgs1* __restrict__ ta,
+                                                   const uint32_t* __restrict__ tq,
+                                                   unsigned long long* __restrict__ stamps) {
   __shared__ LdsTile<KT, RT> t;
   __shared__ SelScratch sc;
   const TailArgs1 a = ta[blockIdx.x];
   tail_body<KT, RT>(a, t, sc);
+  if (stamps) {
+    __syncthreads();
+    if (threadIdx.x == 0) stamps[1 + tq[blockIdx.x]] = wall_clock64();
+  }
 }
+
+// The start of a stamped launch, before any of its other kernels.
+__global__ void k_mstamp(unsigned long long* stamps) { stamps[0] = wall_clock64(); }
 #endif  // TK_EMU
 
 namespace {
@@ -137,6 +148,7 @@ void multi_records(const std::vector<MQuery>& q, const MLayout& L, int key_type,
   r.fa.clear();
   r.fmap.clear();
   r.ta.clear();
+  r.tq.clear();
   // tails of the largest queries first, so the long ones start early
   std::vector<uint32_t> order(q.size());
   std::iota(order.begin(), order.end(), 0u);
@@ -178,13 +190,14 @@ void multi_records(const std::vector<MQuery>& q, const MLayout& L, int key_type,
     r.ta.push_back(TailArgs1{Q.keys, Q.rids, Q.n, dmask, h, sk, sf, sampled ? p.cap : 0, ck, cf,
                              tk_, tf, ke, Q.out_keys, Q.out_rids,
                              sampled ? TAIL_SURVIVORS : TAIL_INPUT, 0});
+    r.tq.push_back(i);
   }
 }
 
 uint64_t multi_pack_bytes(const MRecords& r) {
   return align_up(r.sa.size() * sizeof(SampArgs), 256) + align_up(r.smap.size() * sizeof(uint2), 256) +
          align_up(r.fa.size() * sizeof(FiltArgs), 256) + align_up(r.fmap.size() * sizeof(uint2), 256) +
-         align_up(r.ta.size() * sizeof(TailArgs1), 256);
+         align_up(r.ta.size() * sizeof(TailArgs1), 256) + align_up(r.tq.size() * sizeof(uint32_t), 256);
 }
 
 MLaunch multi_pack(const MRecords& r, char* dst, char* dev) {
@@ -201,6 +214,7 @@ MLaunch multi_pack(const MRecords& r, char* dst, char* dev) {
   m.fa = reinterpret_cast<const FiltArgs*>(put(r.fa.data(), r.fa.size() * sizeof(FiltArgs)));
   m.fmap = reinterpret_cast<const uint2*>(put(r.fmap.data(), r.fmap.size() * sizeof(uint2)));
   m.ta = reinterpret_cast<const TailArgs1*>(put(r.ta.data(), r.ta.size() * sizeof(TailArgs1)));
+  m.tq = reinterpret_cast<const uint32_t*>(put(r.tq.data(), r.tq.size() * sizeof(uint32_t)));
   m.n_samp = (uint32_t)r.smap.size();
   m.n_fa = (uint32_t)r.fa.size();
   m.n_filt = (uint32_t)r.fmap.size();
@@ -213,13 +227,15 @@ namespace {
 
 template <int KT, int RT>
 void enqueue_typed(const MLaunch& m, hipStream_t st) {
+  if (m.stamps) hipLaunchKernelGGL(k_mstamp, dim3(1), dim3(1), 0, st, m.stamps);
   if (m.n_samp) hipLaunchKernelGGL((k_msample<KT, RT>), dim3(m.n_samp), dim3(SAMP_NT), 0, st, m.sa, m.smap);
   if (m.n_fa) hipLaunchKernelGGL((k_msfinal<KT, RT>), dim3(m.n_fa), dim3(FILT_NT), 0, st, m.fa);
   profile_mark(st, true);
   const uint32_t fg = m.filt_grid && m.filt_grid < m.n_filt ? m.filt_grid : m.n_filt;
   if (m.n_filt) hipLaunchKernelGGL((k_mfilter<KT, RT>), dim3(fg), dim3(FILT_NT), 0, st, m.fa, m.fmap, m.n_filt);
   profile_mark(st, false);
-  if (m.n_tail) hipLaunchKernelGGL((k_mtail<KT, RT>), dim3(m.n_tail), dim3(TAIL_NT), 0, st, m.ta);
+  if (m.n_tail)
+    hipLaunchKernelGGL((k_mtail<KT, RT>), dim3(m.n_tail), dim3(TAIL_NT), 0, st, m.ta, m.tq, m.stamps);
 }
 
 template <int KT>

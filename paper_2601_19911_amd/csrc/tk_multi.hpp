@@ -52,6 +52,7 @@ struct MRecords {
   std::vector<FiltArgs> fa;
   std::vector<uint2> fmap;  // (fa index, workgroup within the query)
   std::vector<TailArgs1> ta;
+  std::vector<uint32_t> tq;  // query index of each tail record
 };
 
 // Fills the records for queries q (absolute device addresses; ws is the
@@ -69,8 +70,12 @@ struct MLaunch {
   const uint2* fmap = nullptr;
   uint32_t n_filt = 0;
   const TailArgs1* ta = nullptr;
+  const uint32_t* tq = nullptr;  // query index of each tail record
   uint32_t n_tail = 0;
   uint32_t filt_grid = 0;  // filter workgroups looping over the slices; 0: one per slice
+  // per-query completion stamps (device clock), or nullptr: stamps[0] is the
+  // launch's start, stamps[1 + i] the end of query i's tail
+  unsigned long long* stamps = nullptr;
 };
 
 // Byte sizes of the records as laid out by multi_pack (each part 256-aligned).

@@ -42,7 +42,18 @@ struct Tuning {
   uint32_t tile_len = 0;       // keys per streaming tile of the engine (0: 256 KiB of keys)
   int rank_tail = 1;           // 1: survivors ranked across workgroups when they fit; 0: one
                                // workgroup selects and sorts them
+  uint32_t recover_min_log2 = 29;  // sampled queries of at least 2^this keys hand a misjudged
+                                   // sample to a cooperative exact select over the device (0:
+                                   // never; one workgroup selects over the input instead).
+                                   // The conditional cooperative launch costs about 21 us on
+                                   // every query (MI355X), 11 % at N = 2^28 float32
 };
+
+// Whether a sampled query of n keys enqueues the cooperative exact select that
+// takes over when its sample misjudged.
+inline bool recover_on_device(uint64_t n, const Tuning& t) {
+  return t.recover_min_log2 > 0 && t.recover_min_log2 < 63 && n >= (1ull << t.recover_min_log2);
+}
 
 // Chooses the sample for a query of n keys and k_eff results.  The threshold
 // is the r1-th best of S sampled keys; survivors ~ r1 * n / S.  The sample is

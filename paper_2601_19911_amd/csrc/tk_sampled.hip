@@ -21,7 +21,9 @@
 //             choice): if K <= survivors <= capacity, radix-selects the best
 //             K of the survivors, bitonic-sorts them in LDS and writes the
 //             result; otherwise (the sample misjudged) it radix-selects over
-//             the whole input instead.
+//             the whole input instead, or, for large inputs, leaves the query
+//             to the cooperative exact select over the whole device that the
+//             caller enqueues next (it returns at once when the sample held).
 // Any threshold with at least K survivors yields the exact answer, and a
 // misjudged one falls back to the exact select, so the result never depends on
 // the sample.
@@ -128,7 +130,8 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
   const bool bucketed = tun.rank_tail && bucket_tail_for(k_eff);
   const uint32_t nb = bucket_count(8 * (uint32_t)(sizeof(U) + sizeof(R)));
   uint32_t* bt_words = bucketed ? wsp<uint32_t>(ws, L.btail) : nullptr;  // gh, cur, chunk
-  const SampArgs sa{keys, rids, n, dmask, p.S, p.r1, h, samp_k, samp_f, p.blocks, 0,
+  const uint32_t defer = recover_on_device(n, tun) ? 1u : 0u;
+  const SampArgs sa{keys, rids, n, dmask, p.S, p.r1, h, samp_k, samp_f, p.blocks, defer,
                     bt_words, bucketed ? 2ull * nb : 0ull};
   hipLaunchKernelGGL((k_sample<KT, RT>), dim3(p.blocks), dim3(SAMP_NT), 0, st, sa);
   constexpr int VEC = 16 / sizeof(Raw);
@@ -144,7 +147,7 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
     hipLaunchKernelGGL((k_filter<KT, RT, VEC, 4>), dim3(grid), dim3(FILT_NT), 0, st, fa);
   profile_mark(st, false);
   const TailArgs1 ta{keys, rids, n, dmask, h, surv_k, surv_f, p.cap, cand_k, cand_f,
-                     tmp_k, tmp_f, k_eff, out_keys, out_rids, TAIL_SURVIVORS, 0};
+                     tmp_k, tmp_f, k_eff, out_keys, out_rids, TAIL_SURVIVORS, defer};
   if (bucketed) {
     const size_t hot = align_up((size_t)3 * nb * 4 + 64, 256);
     const BTailArgs bt{ta, bt_words, bt_words + nb, bt_words + 2 * nb,

@@ -34,7 +34,8 @@ struct SampArgs {
   void* ck;
   void* cf;
   uint32_t nblk;  // sample workgroups of this query
-  uint32_t pad;
+  uint32_t clear_exact;  // 1: also clear the exact select's state in the query header (a
+                         // single query whose misjudged sample is taken over by it)
   uint32_t* zero;  // nzero words the sample workgroups clear for later launches, or nullptr
   uint64_t nzero;
 };
@@ -72,8 +73,10 @@ struct TailArgs1 {
   uint64_t k_eff;
   void* out_keys;
   void* out_rids;
-  uint32_t mode;  // TAIL_SURVIVORS or TAIL_INPUT
-  uint32_t pad;
+  uint32_t mode;   // TAIL_SURVIVORS or TAIL_INPUT
+  uint32_t defer;  // 1: a misjudged sample is left to the cooperative exact select that
+                   // follows (path 4 recorded, nothing written); 0: one workgroup selects
+                   // over the input
 };
 
 // TAIL_SURVIVORS: select over the survivors of the filter (falling back to
@@ -82,6 +85,15 @@ struct TailArgs1 {
 constexpr uint32_t TAIL_SURVIVORS = 0, TAIL_INPUT = 1;
 
 // ---- k_sample ----------------------------------------------------------------------------------
+
+// 64 uniform bits from a chunk index: the SplitMix64 finalizer (Steele, Lea,
+// Flood 2014) of the index times its increment.
+__device__ __forceinline__ uint64_t sample_hash(uint64_t c) {
+  uint64_t z = (c + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
 
 // blk: this workgroup's index among the query's a.nblk sample workgroups.
 // Each keeps the best r1 composites of its SAMPLE_PER_BLOCK sampled keys
@@ -102,16 +114,25 @@ __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, u
   if (a.zero)
     for (uint64_t i = (uint64_t)blk * NT + threadIdx.x; i < a.nzero; i += (uint64_t)a.nblk * NT)
       a.zero[i] = 0u;
+  if (a.clear_exact) {  // the words of the header past the query state
+    uint32_t* w = reinterpret_cast<uint32_t*>(reinterpret_cast<Header*>(h)) + sizeof(QHead) / 4;
+    constexpr uint32_t NW = (uint32_t)((sizeof(Header) - sizeof(QHead)) / 4);
+    for (uint32_t i = blk * NT + threadIdx.x; i < NW; i += a.nblk * NT) w[i] = 0u;
+  }
   const InputSrc<KT, RT> src{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, (U)a.dmask};
+  // Chunk c of 16 keys lies at a pseudo-random offset inside stratum c (of
+  // `stride` keys): a column periodic in the stride cannot line its extremes
+  // up with every sampled chunk, as it could with one fixed offset.
   const uint64_t nchunks = a.S / SAMPLE_CHUNK;
   const uint64_t stride = a.n / nchunks;  // >= 16: n >= 16 * S
-  const uint64_t off0 = (stride - SAMPLE_CHUNK) / 2;
+  const uint64_t span = stride - SAMPLE_CHUNK + 1;
   U k[E];
   R f[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const uint64_t j = (uint64_t)blk * SAMPLE_PER_BLOCK + (uint64_t)e * NT + threadIdx.x;
-    const uint64_t pos = (j / SAMPLE_CHUNK) * stride + off0 + (j % SAMPLE_CHUNK);
+    const uint64_t c = j / SAMPLE_CHUNK;
+    const uint64_t pos = c * stride + __umul64hi(sample_hash(c), span) + (j % SAMPLE_CHUNK);
     k[e] = src.key(pos);
     f[e] = src.flip(pos);
   }
@@ -607,9 +628,10 @@ __device__ __forceinline__ void tail_body(const TailArgs1& a, LdsTile<KT, RT>& t
   } else if (ok) {
     const BufSrc<U, R> src{static_cast<const U*>(a.sk), static_cast<const R*>(a.sf)};
     select_sort_write<KT, RT>(src, C, (U)h->thr_k, tail_out(a), t, sc);
-  } else {
+  } else if (!a.defer) {
     select_sort_write<KT, RT>(in, a.n, (U)0, tail_out(a), t, sc);
   }
+  // path 4 with defer set hands the query to the cooperative exact select
   if (threadIdx.x == 0) h->path = ok ? 2u : 4u;
 }
 

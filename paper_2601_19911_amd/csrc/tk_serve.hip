@@ -216,6 +216,7 @@ bool build_batch(const std::vector<Taken>& ids, int key_type, const Slot& sl, Ba
   sizes.fa.resize(b.L.n_sampled);
   sizes.fmap.resize(b.L.n_filt_blocks);
   sizes.ta.resize(b.L.n_sampled + b.L.n_input);
+  sizes.tq.resize(b.L.n_sampled + b.L.n_input);
   b.off_rec = off;
   b.rec_bytes = multi_pack_bytes(sizes);
   off = align_up(off + b.rec_bytes, 256);

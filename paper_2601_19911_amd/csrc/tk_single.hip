@@ -355,7 +355,14 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs a) {
   __shared__ int s_flag;
   Header* h = a.h;
   const U dmask = (U)a.dmask;
-  if (blockIdx.x == 0 && threadIdx.x == 0) h->q.path = 5u;
+  if (a.exact_only == 2) {
+    // after a sampled query: only when its tail found the sample misjudged
+    // (path 4, left by the previous launch); its sample workgroups cleared the
+    // select's counters, histograms and barrier
+    if (h->q.path != 4u) return;
+  } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+    h->q.path = 5u;
+  }
   const InputSrc<KT, RT> src{(const typename Key<KT>::Raw*)a.keys, (const R*)a.rids, dmask};
   const bool ok =
       exact_select<NT, U, R>(src, a.n, a.k_eff, h, (U*)a.ck, (R*)a.cf, lh, lh64, sh_u32, &s_flag);
@@ -466,6 +473,8 @@ Tuning current_tuning() {
 void set_tuning(const tk_tuning* t) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (t->sample_sigma > 0) g_tuning.sample_sigma = t->sample_sigma;
+  if (t->recover_min_log2 > 0) g_tuning.recover_min_log2 = (uint32_t)t->recover_min_log2;
+  if (t->recover_min_log2 < 0) g_tuning.recover_min_log2 = 0;
   if (t->cap_sigma > 0) g_tuning.cap_sigma = t->cap_sigma;
   if (t->max_sample_log2 > 0) g_tuning.max_sample_log2 = (uint32_t)t->max_sample_log2;
   if (t->filter_grid > 0) g_tuning.filter_grid = (uint32_t)t->filter_grid;
@@ -509,10 +518,14 @@ int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, i
     return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
   }
   const SamplePlan p = plan_sample(n, k_eff, tun);
-  if (p.fast)
-    return run_sampled<KT, RT>(keys, rids, n, k_eff, order, out_keys, out_rids, ws, ws_bytes, st,
-                               tun, p);
   const WsLayout L = ws_layout(n, k_eff, sizeof(U), sizeof(R), p);
+  int exact_mode = 1;
+  if (p.fast) {
+    const int rc = run_sampled<KT, RT>(keys, rids, n, k_eff, order, out_keys, out_rids, ws, ws_bytes,
+                                       st, tun, p);
+    if (rc != TK_OK || !recover_on_device(n, tun)) return rc;
+    exact_mode = 2;  // returns at once unless the sample misjudged
+  }
   if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return TK_EINVAL;
   Header* h = ws_ptr<Header>(ws, 0);
   U* cand_k = ws_ptr<U>(ws, L.cand);
@@ -521,10 +534,12 @@ int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, i
   R* tmp_f = ws_ptr<R>(ws, L.tmp + align_up((size_t)k_eff * sizeof(U), 16));
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return TK_EHIP;
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, h);
-  if (hipGetLastError() != hipSuccess) return TK_EHIP;
+  if (exact_mode == 1) {
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, h);
+    if (hipGetLastError() != hipSuccess) return TK_EHIP;
+  }
   TailArgs a{keys, rids, n, (uint64_t)dmask, h, cand_k, cand_f, tmp_k, tmp_f, k_eff, out_keys,
-             out_rids, 1};
+             out_rids, exact_mode};
   void* args[] = {&a};
   // one workgroup per 16 Ki keys, up to what the device holds at once: every
   // digit round ends in a grid barrier whose cost grows with the grid, so a

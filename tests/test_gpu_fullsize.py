@@ -116,3 +116,64 @@ def test_full_size(dtype, dist, k, order):
         first = np.flatnonzero(host == host.dtype.type(1))[:k]
         assert first.size == k
         assert np.all(gk == host.dtype.type(1)) and np.array_equal(gr.astype(np.int64), first)
+
+
+def _event_ms(fn, reps=5):
+    import torch
+    times = []
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times[1:]))
+
+
+def test_periodic_column_and_misjudged_sample_full_size():
+    """A float32 column whose largest keys sit in a 16-key window repeating
+    every 2^14 keys: the sample stride of N = 2^28, K = 1000, and the window at
+    the middle of each stride, where one fixed sample offset would see only the
+    largest keys (an underestimate of the survivors by a factor of 1000).  The
+    pseudo-random chunk offsets keep the sample sound (ranked tail, path 3).
+    Then the same query with a survivor capacity of 64 misjudges on purpose:
+    the cooperative exact select over the device takes it over (path 4); both
+    equal the oracle, and the recovered query is timed against the normal one."""
+    import torch
+    from tests.gpu_util import to_dev
+    k = 1000
+    host = gen.host_fill(inputgen.KIND_U_F32, inputgen.config_seed(2, 60), N) * np.float32(0.5)
+    win = host.reshape(-1, 1 << 14)
+    win[:, 8184:8200] += np.float32(0.5)
+    keys = to_dev(host)
+    ek, er = oracle.topk(host, None, k, oracle.DESC, rid_dtype=np.uint32)
+    ws = tk.new_workspace(N, k, tk.TK_KEY_F32, tk.TK_RID_U32, device=keys.device)
+    ok = torch.empty(k, dtype=torch.float32, device=keys.device)
+    orr = torch.empty(k, dtype=torch.uint32, device=keys.device)
+
+    def query():
+        tk.topk(keys, k, out_keys=ok, out_rowids=orr, workspace=ws)
+
+    say("periodic column: sampled path")
+    query()
+    torch.cuda.synchronize()
+    info = tk.query_info(ws)
+    say(f"  path {info['path']} survivors {info['survivors']}")
+    assert info["status"] == 0 and info["path"] == 3
+    assert_same(to_np(ok), to_np(orr), ek, er, what="periodic column")
+    normal_ms = _event_ms(query)
+    try:
+        tk.set_tuning(force_cap=64, recover_min_log2=24)
+        say("periodic column: forced misjudge, cooperative recovery")
+        query()
+        torch.cuda.synchronize()
+        info = tk.query_info(ws)
+        say(f"  path {info['path']} survivors {info['survivors']}")
+        assert info["status"] == 0 and info["path"] == 4
+        assert_same(to_np(ok), to_np(orr), ek, er, what="misjudged sample, recovered")
+        recovered_ms = _event_ms(query)
+    finally:
+        tk.set_tuning(force_cap=-1, recover_min_log2=29)
+    say(f"  normal {normal_ms:.3f} ms, recovered {recovered_ms:.3f} ms "
+        f"({recovered_ms / normal_ms:.2f}x)")

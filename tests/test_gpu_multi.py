@@ -114,3 +114,60 @@ def test_multi_plan_argument_errors():
 
 def test_multi_float64_given_rowids():
     _plan_run(inputgen.KIND_U_F64, 64, 8, 21, 5000, seed=49, with_rids=True, launches=2)
+
+
+def test_multi_query_times_from_the_device_clock():
+    """tk_plan_query_times: every non-empty query has a completion time after
+    the launch's start and no later than the launch's end (events around it),
+    on an eager launch and on graph replays; empty queries report 0."""
+    import torch
+    off, ks, orders = inputgen.batched_queries(200, seed=51, n_lo_log2=8, n_hi_log2=21, k_max=4096)
+    ks[7] = 0  # an empty query
+    keys = inputgen.generate(inputgen.KIND_U_I64, 51, int(off[-1]))
+    kd = to_dev(keys)
+    s = torch.cuda.Stream()
+    plan = Plan(off, ks, orders, key_dtype=torch.int64, rid_dtype=torch.uint32, stream=s)
+    ok, orr = plan.alloc_outputs()
+    for it in range(3):  # eager, capture, replay
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        plan.launch(kd, ok, orr, stream=s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        span = e0.elapsed_time(e1) * 1e-3
+        t = plan.query_times()
+        say(f"launch {it}: span {span * 1e3:.3f} ms, query times {t.min() * 1e3:.3f}.."
+            f"{t.max() * 1e3:.3f} ms, p50 {np.median(t) * 1e3:.3f} ms")
+        assert t[7] == 0.0
+        live = np.delete(t, 7)
+        assert np.all(live > 0)
+        # the device clock ticks at 100 MHz: allow a few ticks and the event granularity
+        assert np.all(live <= span + 5e-5)
+        _check(keys, None, off, ks, orders, to_np(ok), to_np(orr), plan, f"timed launch {it}")
+    plan.close()
+
+
+def test_topk_each_matches_the_plan():
+    """The C per-query launcher (tk_topk_each) on 1 and 3 streams writes the same
+    packed results as the plan, and reports increasing completion times."""
+    import torch
+    from paper_2601_19911_amd.batched import topk_each
+    off, ks, orders = inputgen.batched_queries(64, seed=53, n_lo_log2=8, n_hi_log2=20, k_max=3000)
+    keys = inputgen.generate(inputgen.KIND_U_F32, 53, int(off[-1]))
+    kd = to_dev(keys)
+    plan = Plan(off, ks, orders, key_dtype=torch.float32, rid_dtype=torch.uint32)
+    pk, pr = plan.alloc_outputs()
+    plan.launch(kd, pk, pr)
+    torch.cuda.synchronize()
+    for ns in (1, 3):
+        ok, orr = plan.alloc_outputs()
+        streams = [torch.cuda.Stream() for _ in range(ns)]
+        t = topk_each(off, ks, orders, kd, ok, orr, streams)
+        torch.cuda.synchronize()
+        say(f"topk_each {ns} streams: completion {t.min() * 1e3:.3f}..{t.max() * 1e3:.3f} ms")
+        assert np.all(t > 0)
+        if ns == 1:
+            assert np.all(np.diff(t) >= 0)
+        assert_same(to_np(ok), to_np(orr), to_np(pk), to_np(pr), what=f"topk_each {ns} streams")
+    plan.close()
