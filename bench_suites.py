@@ -572,7 +572,8 @@ class _Point:
         import paper_2601_19911_amd as tk
         from inputgen import native as gen
         kinds = {"int32": (inputgen.KIND_U_I32, torch.int32), "int64": (inputgen.KIND_U_I64, torch.int64),
-                 "float32": (inputgen.KIND_U_F32, torch.float32)}
+                 "float32": (inputgen.KIND_U_F32, torch.float32),
+                 "float64": (inputgen.KIND_U_F64, torch.float64)}
         kind, tdt = kinds[dt]
         self.dt, self.tdt, self.torch, self.tk = dt, tdt, torch, tk
         self.dev = torch.device("cuda:0")

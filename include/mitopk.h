@@ -111,8 +111,10 @@ typedef struct {
                            see tk_tuning.recover_min_log2; by one workgroup
                            below); 5 exact radix select over the input
                            (no usable sample: N below 2^15, K above N / 2, or K
-                           above N / 16 with N above 2^20); 0 after a
-                           one-workgroup query (N within one LDS tile, K > 2048) */
+                           above N / 16 with N above 2^20) by a cooperative grid,
+                           from 2^16 keys; 8 the same by one workgroup, below
+                           2^16 keys; 0 after a one-workgroup query (N within one
+                           LDS tile, K > 2048) */
   uint32_t status;      /* 0, or device failure bits (1: a grid barrier timed out,
                            2: a wait between engine items timed out) */
   uint64_t survivors;   /* keys that passed the sampled threshold (paths 2-4, 6) */
@@ -160,10 +162,10 @@ int tk_set_tuning(const tk_tuning* t);
  * Results equal tk_topk on each query alone. */
 typedef struct tk_plan tk_plan;
 typedef struct {
-  uint32_t tile_keys;        /* keys each filter workgroup streams; 0: 65536 (>= 4096) */
+  uint32_t tile_keys;        /* keys each filter workgroup streams; 0: 32768 (>= 4096) */
   uint32_t filter_grid;      /* filter workgroups, each looping over the slices; 0: one per slice */
   uint32_t min_sample_log2;  /* smallest sample; queries under 16x it take the exact select; 0: 12 */
-  uint32_t max_sample_log2;  /* largest sample; 0: 20 */
+  uint32_t max_sample_log2;  /* largest sample; 0: 14 */
   double sample_sigma;       /* margin of the sampled threshold; 0: 3 */
   int32_t use_graph;         /* >= 0: capture launches on a created stream in a hipGraph and
                                 replay it (the default stream is never captured: launches

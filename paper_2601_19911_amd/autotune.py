@@ -38,7 +38,7 @@ def candidates(key_bytes: int, quick: bool = False, cus: int = 256):
     """Parameter sets to try, as dicts of tk_plan_params fields."""
     tiles = ([1 << 14, 1 << 15, 1 << 16, 1 << 17] if key_bytes == 8 else
              [1 << 15, 1 << 16, 1 << 17, 1 << 18])
-    sigmas = [(3.0, 20), (2.0, 20), (4.0, 22), (3.0, 18)]
+    sigmas = [(3.0, 14), (2.0, 14), (3.0, 16), (3.0, 20)]
     caps = [6.0, 4.0]
     grids = [0, 3 * cus]
     if quick:

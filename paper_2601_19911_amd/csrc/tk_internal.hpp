@@ -60,6 +60,16 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
                 void* out_keys, void* out_rids, void* ws, size_t ws_bytes, hipStream_t st,
                 const Tuning& tun, const SamplePlan& p);
 
+// Inputs below this size that the sample cannot serve are selected by one
+// workgroup (path 8) instead of the cooperative grid.
+constexpr uint64_t ONE_WG_INPUT_MAX = 1ull << 16;
+
+// One workgroup's exact select + sort over the whole input (k_tail1 over the
+// input), with the workspace regions of layout L for K beyond one LDS tile.
+template <int KT, int RT>
+int run_input_one_wg(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, int order,
+                     void* out_keys, void* out_rids, void* ws, hipStream_t st, const WsLayout& L);
+
 template <int KT, int RT>
 int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, int order,
                void* out_keys, void* out_rids, void* ws, size_t ws_bytes, hipStream_t st,

@@ -23,7 +23,6 @@
 
 namespace tk {
 
-#ifndef TK_EMU
 template <int KT, int RT>
 __global__ __launch_bounds__(SAMP_NT) void k_msample(const SampArgs* __restrict__ sa,
                                                      const uint2* __restrict__ map) {
@@ -71,11 +70,10 @@ __global__ __launch_bounds__(TAIL_NT) void k_mtail(const TailArgs1* __restrict__
 
 // The start of a stamped launch, before any of its other kernels.
 __global__ void k_mstamp(unsigned long long* stamps) { stamps[0] = wall_clock64(); }
-#endif  // TK_EMU
 
 namespace {
 
-constexpr uint32_t DEFAULT_SLICE = 1u << 16;
+constexpr uint32_t DEFAULT_SLICE = 1u << 15;
 
 struct Regions {
   uint64_t samp, surv, cand, tmp, total;  // offsets within the query's regions
@@ -222,7 +220,6 @@ MLaunch multi_pack(const MRecords& r, char* dst, char* dev) {
   return m;
 }
 
-#ifndef TK_EMU
 namespace {
 
 template <int KT, int RT>
@@ -254,6 +251,5 @@ void multi_enqueue(const MLaunch& m, int key_type, int rid_type, hipStream_t st)
     default: enqueue_rid<KEY_I64>(m, rid_type, st); break;
   }
 }
-#endif  // TK_EMU
 
 }  // namespace tk

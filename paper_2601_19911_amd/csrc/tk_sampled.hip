@@ -38,7 +38,6 @@
 
 namespace tk {
 
-#ifndef TK_EMU
 template <int KT, int RT>
 __global__ __launch_bounds__(SAMP_NT) void k_sample(SampArgs a) {
   __shared__ SelScratch sc;
@@ -163,10 +162,28 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
   return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
 }
 
+template <int KT, int RT>
+int run_input_one_wg(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, int order,
+                     void* out_keys, void* out_rids, void* ws, hipStream_t st, const WsLayout& L) {
+  using U = typename Key<KT>::U;
+  const uint64_t dmask = order == TK_ASC ? (uint64_t)(U)~(U)0 : 0ull;
+  QHead* h = &wsp<Header>(ws, 0)->q;
+  void* cand_k = wsp<char>(ws, L.cand);
+  void* cand_f = wsp<char>(ws, L.cand + align_up((size_t)k_eff * sizeof(U), 16));
+  void* tmp_k = wsp<char>(ws, L.tmp);
+  void* tmp_f = wsp<char>(ws, L.tmp + align_up((size_t)k_eff * sizeof(U), 16));
+  const TailArgs1 ta{keys, rids, n, dmask, h, nullptr, nullptr, 0, cand_k, cand_f,
+                     tmp_k, tmp_f, k_eff, out_keys, out_rids, TAIL_INPUT, 0};
+  hipLaunchKernelGGL((k_tail1<KT, RT>), dim3(1), dim3(TAIL_NT), 0, st, ta);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
+}
+
 #define TK_INST(KT, RT)                                                                         \
   template int run_sampled<KT, RT>(const void*, const void*, uint64_t, uint64_t, int, void*,    \
                                    void*, void*, size_t, hipStream_t, const Tuning&,           \
-                                   const SamplePlan&);
+                                   const SamplePlan&);                                          \
+  template int run_input_one_wg<KT, RT>(const void*, const void*, uint64_t, uint64_t, int,      \
+                                        void*, void*, void*, hipStream_t, const WsLayout&);
 TK_INST(KEY_I32, RID_U32)
 TK_INST(KEY_I32, RID_U64)
 TK_INST(KEY_F32, RID_U32)
@@ -176,6 +193,5 @@ TK_INST(KEY_I64, RID_U64)
 TK_INST(KEY_F64, RID_U32)
 TK_INST(KEY_F64, RID_U64)
 #undef TK_INST
-#endif  // TK_EMU
 
 }  // namespace tk

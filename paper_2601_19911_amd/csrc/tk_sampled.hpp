@@ -617,6 +617,10 @@ __device__ __forceinline__ void tail_body(const TailArgs1& a, LdsTile<KT, RT>& t
   if (a.mode == TAIL_INPUT) {
     if (a.n <= (uint64_t)TAIL_NT * TAIL_E) select_sort_write_regs<KT, RT>(a, in, (uint32_t)a.n, (U)~(U)0, t, sc);
     else select_sort_write<KT, RT>(in, a.n, (U)0, tail_out(a), t, sc);
+    if (a.h && threadIdx.x == 0) {  // a single query's header (the batched form passes none)
+      a.h->path = 8u;
+      a.h->status = 0u;
+    }
     return;
   }
   QHead* h = a.h;

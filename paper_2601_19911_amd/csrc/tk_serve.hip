@@ -119,14 +119,15 @@ bool all_zero(const tk_cost_model& c) {
   return c.cpu_a == 0 && c.cpu_b == 0 && c.cpu_c == 0 && c.gpu_a == 0 && c.gpu_b == 0 && c.gpu_c == 0;
 }
 
-// Default cost models per key type (tk_key_t order): least-squares fits of
-// measured request times on an MI355X (device-resident keys, launch to
-// results on the host) and of the CPU route on 16 host threads.
+// Default cost models per key type (tk_key_t order): fits on relative
+// residuals of measured request times over N = 2^10 .. 2^20 and K in {10,
+// 100, 1000, 10000} on an MI355X (device-resident keys, launch to results on
+// the host) and of the CPU route on 16 host threads.
 constexpr tk_cost_model DEFAULT_COST[4] = {
-    {1.79e-10, 1.26e-8, 4.36e-5, 0.0, 1.48e-8, 5.30e-5},  // int32
-    {1.79e-10, 1.26e-8, 4.36e-5, 0.0, 1.48e-8, 5.30e-5},  // int64
-    {1.79e-10, 1.26e-8, 4.36e-5, 0.0, 1.48e-8, 5.30e-5},  // float32
-    {1.79e-10, 1.26e-8, 4.36e-5, 0.0, 1.48e-8, 5.30e-5},  // float64
+    {5.09e-10, 2.36e-9, 2.56e-5, 1.49e-11, 6.62e-9, 3.40e-5},  // int32
+    {4.88e-10, 2.67e-9, 2.14e-5, 1.54e-11, 6.96e-9, 3.71e-5},  // int64
+    {5.01e-10, 2.45e-9, 2.31e-5, 1.39e-11, 6.54e-9, 3.53e-5},  // float32
+    {4.88e-10, 2.41e-9, 2.58e-5, 1.39e-11, 6.89e-9, 3.88e-5},  // float64
 };
 constexpr double DEFAULT_H2D = 5.0e10;
 
@@ -201,6 +202,7 @@ bool build_batch(const std::vector<Taken>& ids, int key_type, const Slot& sl, Ba
   t.force_exact = 0;
   t.force_cap = 0;
   t.min_sample_log2 = 12;
+  t.max_sample_log2 = 14;  // as for plans: the batch's samples precede every filter
   std::vector<uint64_t> n(q), k(q);
   b.out_off.assign(q + 1, 0);
   for (size_t i = 0; i < q; ++i) {

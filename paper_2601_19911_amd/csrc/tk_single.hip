@@ -502,17 +502,17 @@ int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, i
   using R = typename Rid<RT>::R;
   const U dmask = order == TK_ASC ? (U)~(U)0 : (U)0;
   constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
+  // the header reports the path of the small routes when the caller passed a workspace
+  QHead* const hq = ws && ws_bytes >= HEADER_BYTES && !((uintptr_t)ws & 255u)
+                        ? &ws_ptr<Header>(ws, 0)->q : nullptr;
+  if (!tun.force_exact && tun.rank_tail && n <= RANK_CMAX && !bucket_tail_for(k_eff)) {
+    // ranked over the input by several workgroups
+    const TailArgs1 ta{keys, rids, n, (uint64_t)dmask, hq, nullptr, nullptr, 0, nullptr, nullptr,
+                       nullptr, nullptr, k_eff, out_keys, out_rids, TAIL_INPUT, 0};
+    hipLaunchKernelGGL((k_rsmall<KT, RT>), dim3(rank_grid(k_eff)), dim3(RANK_NT), 0, st, ta);
+    return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
+  }
   if (n <= CAP && !tun.force_exact) {
-    if (tun.rank_tail && n <= RANK_CMAX && !bucket_tail_for(k_eff)) {
-      // ranked over the input by several workgroups; the header reports the path
-      // when the caller passed a workspace
-      QHead* h = ws && ws_bytes >= HEADER_BYTES && !((uintptr_t)ws & 255u)
-                     ? &ws_ptr<Header>(ws, 0)->q : nullptr;
-      const TailArgs1 ta{keys, rids, n, (uint64_t)dmask, h, nullptr, nullptr, 0, nullptr, nullptr,
-                         nullptr, nullptr, k_eff, out_keys, out_rids, TAIL_INPUT, 0};
-      hipLaunchKernelGGL((k_rsmall<KT, RT>), dim3(rank_grid(k_eff)), dim3(RANK_NT), 0, st, ta);
-      return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
-    }
     hipLaunchKernelGGL((k_small<KT, RT>), dim3(1), dim3(1024), 0, st, (const Raw*)keys,
                        (const R*)rids, (uint32_t)n, (uint32_t)k_eff, dmask, out_keys, out_rids);
     return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
@@ -527,6 +527,11 @@ int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, i
     exact_mode = 2;  // returns at once unless the sample misjudged
   }
   if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return TK_EINVAL;
+  if (exact_mode == 1 && !tun.force_exact && n < ONE_WG_INPUT_MAX) {
+    // no usable sample and a small input: one workgroup selects over it (the
+    // cooperative launch of the grid-wide select costs more than it saves here)
+    return run_input_one_wg<KT, RT>(keys, rids, n, k_eff, order, out_keys, out_rids, ws, st, L);
+  }
   Header* h = ws_ptr<Header>(ws, 0);
   U* cand_k = ws_ptr<U>(ws, L.cand);
   R* cand_f = ws_ptr<R>(ws, L.cand + align_up((size_t)k_eff * sizeof(U), 16));

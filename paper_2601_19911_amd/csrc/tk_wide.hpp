@@ -1,7 +1,7 @@
 // The selection composite (key image above flipped row-id) read as one wide
 // unsigned integer, and logarithmic buckets of a distance between two
-// composites.  Used by the tails (tk_rank.hpp, tk_bucket.hpp) and by the
-// streaming pass, which counts survivors by bucket for the large-K tail.
+// composites.  Used by the tails over the survivors (tk_rank.hpp,
+// tk_bucket.hpp).
 #pragma once
 
 #include "tk_device.hpp"

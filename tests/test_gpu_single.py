@@ -329,11 +329,14 @@ def _run_path_cases(cases, want_path, seed):
 
 def test_exact_path_small_grids():
     """Inputs past one LDS tile that the sample cannot serve (N below 16 sample
-    chunks of 2048 keys, K above N / 2, or K above N / 16 at N past 2^20) take
-    the exact radix select over the input on a grid sized by N (path 5)."""
+    chunks of 2048 keys, K above N / 2, or K above N / 16 at N past 2^20): from
+    2^16 keys the exact radix select over the input on a grid sized by N
+    (path 5), below it one workgroup's select over the input (path 8)."""
+    _run_path_cases([("int32", 65536, 40000, "desc"), ("float32", 1 << 22, 1 << 19, "desc"),
+                     ("int64", 1 << 21, 1 << 20, "asc")], 5, seed=300)
     _run_path_cases([("int32", 23170, 10, "desc"), ("float32", 30048, 1000, "asc"),
-                     ("int64", 20000, 3000, "asc"), ("int32", 65536, 40000, "desc"),
-                     ("float32", 1 << 22, 1 << 19, "desc"), ("int64", 1 << 21, 1 << 20, "asc")], 5, seed=300)
+                     ("int64", 20000, 3000, "asc"), ("int64", 16385, 10, "desc"),
+                     ("float32", 65535, 40000, "asc"), ("int32", 40000, 20001, "desc")], 8, seed=301)
 
 
 def test_wide_k_sampled():
