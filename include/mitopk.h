@@ -59,8 +59,15 @@ typedef enum {
 
 /* Bytes of device workspace tk_topk needs for a query of n keys and limit k
  * (any k; it is capped at n).  Depends only on (n, min(k, n), key type,
- * row-id type) and the current tuning.  Never 0. */
+ * row-id type) and the current tuning.  Never 0.  For a query with no usable
+ * sample from 2^16 keys (path 9) it includes the full sort's scratch, about
+ * 2 n (key + row-id) bytes. */
 size_t tk_workspace_size(uint64_t n, uint64_t k, int key_type, int rid_type);
+/* The least workspace tk_topk accepts for the same query: tk_workspace_size
+ * without the full sort's scratch.  With less than tk_workspace_size (and at
+ * least this), a query with no usable sample takes path 5 instead of 9; the
+ * result is the same.  Never 0. */
+size_t tk_workspace_min_size(uint64_t n, uint64_t k, int key_type, int rid_type);
 
 /* One Top-K query (paper sec. III-A): selects the best min(k, n) (key,
  * row-id) pairs and writes them best first.
@@ -83,14 +90,15 @@ int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int ke
  * hipMalloc).  Same arguments, result and asynchrony as tk_topk, without the
  * workspace: the query's workspace is a library-owned device array of
  * TK_NOALLOC_SCRATCH_BYTES, one per device, held from the library's load until
- * the process ends.  The call allocates nothing.  A query whose
- * tk_workspace_size exceeds TK_NOALLOC_SCRATCH_BYTES (K of a few hundred
- * thousand and up; every K <= 100000 fits at any N <= 2^30) returns
- * TK_EUNSUPPORTED and enqueues nothing.  Every call on one device shares that
- * device's array: two calls whose work may overlap on one device (different
- * streams without ordering between them, different host threads) race and
- * may return wrong results; order them on one stream.  The array's contents
- * are left from the last call; each query sets up every word it reads. */
+ * the process ends.  The call allocates nothing.  A query that does not fit
+ * the array (K of a few hundred thousand and up; every K <= 100000 fits at any
+ * N <= 2^30) returns TK_EUNSUPPORTED and enqueues nothing; a query with no
+ * usable sample whose full-sort scratch does not fit takes path 5 instead of
+ * path 9.  Every call on one device shares that device's array: two calls
+ * whose work may overlap on one device (different streams without ordering
+ * between them, different host threads) race and may return wrong results;
+ * order them on one stream.  The array's contents are left from the last
+ * call; each query sets up every word it reads. */
 #define TK_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
 int tk_topk_noalloc(const void* keys, const void* rowids, uint64_t n, uint64_t k, int key_type,
                     int rid_type, int order, void* out_keys, void* out_rowids, uint64_t* out_count,
@@ -109,12 +117,16 @@ typedef struct {
                            4 sampled, but the sample misjudged: exact select
                            over the input (by the whole device from 2^29 keys,
                            see tk_tuning.recover_min_log2; by one workgroup
-                           below); 5 exact radix select over the input
-                           (no usable sample: N below 2^15, K above N / 2, or K
-                           above N / 16 with N above 2^20) by a cooperative grid,
-                           from 2^16 keys; 8 the same by one workgroup, below
-                           2^16 keys; 0 after a one-workgroup query (N within one
-                           LDS tile, K > 2048) */
+                           below); queries with no usable sample (N below 2^15,
+                           K above N / 2, or K above N / 16 with N above 2^20):
+                           8 exact radix select over the input by one workgroup,
+                           below 2^16 keys; 9 from 2^16 keys, the full radix
+                           sort of the input (as tk_sort) writing its first K
+                           pairs; 5 exact radix select over the input by a
+                           cooperative grid, where the workspace has no room for
+                           the sort's scratch (or with tk_tuning.force_exact);
+                           0 after a one-workgroup query (N within one LDS tile,
+                           K > 2048) */
   uint32_t status;      /* 0, or device failure bits (1: a grid barrier timed out,
                            2: a wait between engine items timed out) */
   uint64_t survivors;   /* keys that passed the sampled threshold (paths 2-4, 6) */
@@ -400,7 +412,8 @@ size_t tk_sort_workspace_size(uint64_t n, int key_type, int rid_type);
  * (required); workspace: >= tk_sort_workspace_size bytes, 256-byte aligned,
  * scratch until the stream passes the call.  Inputs and outputs must not
  * overlap the workspace.  Stream-ordered and asynchronous; n = 0 enqueues
- * nothing.  TK_EINVAL on a bad argument (nothing enqueued). */
+ * nothing.  TK_EINVAL on a bad argument, TK_EUNSUPPORTED for n >= 2^32 (the
+ * digit counts are 32-bit); nothing enqueued on an error. */
 int tk_sort(const void* keys, const void* rowids, uint64_t n, int key_type, int rid_type,
             int order, void* out_keys, void* out_rowids, void* workspace, size_t workspace_bytes,
             void* stream);

@@ -51,6 +51,8 @@ def lib():
         vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
         L.tk_workspace_size.argtypes = [u64, u64, i32, i32]
         L.tk_workspace_size.restype = ctypes.c_size_t
+        L.tk_workspace_min_size.argtypes = [u64, u64, i32, i32]
+        L.tk_workspace_min_size.restype = ctypes.c_size_t
         L.tk_topk.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, ctypes.POINTER(u64), vp,
                               ctypes.c_size_t, vp]
         L.tk_topk.restype = i32
@@ -141,11 +143,17 @@ def workspace_size(n: int, k: int, key_type: int, rid_type: int) -> int:
     return int(lib().tk_workspace_size(n, k, key_type, rid_type))
 
 
-def new_workspace(n: int, k: int, key_type: int, rid_type: int, device="cuda"):
+def workspace_min_size(n: int, k: int, key_type: int, rid_type: int) -> int:
+    """The least workspace tk_topk accepts (without the full sort's scratch)."""
+    return int(lib().tk_workspace_min_size(n, k, key_type, rid_type))
+
+
+def new_workspace(n: int, k: int, key_type: int, rid_type: int, device="cuda", least=False):
     """A workspace for tk_topk (zero-filled here only for reproducible contents;
-    the library needs no initialization)."""
+    the library needs no initialization); least=True: the smallest one accepted."""
     import torch
-    return torch.zeros(workspace_size(n, k, key_type, rid_type), dtype=torch.uint8, device=device)
+    size = (workspace_min_size if least else workspace_size)(n, k, key_type, rid_type)
+    return torch.zeros(size, dtype=torch.uint8, device=device)
 
 
 def topk(keys, k: int, rowids=None, order="desc", out_keys=None, out_rowids=None,
@@ -176,9 +184,10 @@ def topk(keys, k: int, rowids=None, order="desc", out_keys=None, out_rowids=None
         out_keys = torch.empty(k_eff, dtype=keys.dtype, device=dev)
     if out_rowids is None:
         out_rowids = torch.empty(k_eff, dtype=rdt, device=dev)
-    ws_bytes = workspace_size(n, k, kc, rc_)
-    if workspace is None or workspace.numel() < ws_bytes:
-        workspace = torch.zeros(ws_bytes, dtype=torch.uint8, device=dev)
+    if workspace is None:
+        workspace = torch.zeros(workspace_size(n, k, kc, rc_), dtype=torch.uint8, device=dev)
+    elif workspace.numel() < workspace_min_size(n, k, kc, rc_):
+        raise TopKError("workspace smaller than tk_workspace_min_size")
     cnt = ctypes.c_uint64(0)
     rc = lib().tk_topk(_ptr(keys) if n else None, _ptr(rowids), n, int(k), kc, rc_, oc,
                        _ptr(out_keys), _ptr(out_rowids), ctypes.byref(cnt),

@@ -70,6 +70,13 @@ template <int KT, int RT>
 int run_input_one_wg(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, int order,
                      void* out_keys, void* out_rids, void* ws, hipStream_t st, const WsLayout& L);
 
+// The Top-K of a query by its full sort (tk_sort.hip): the first k_eff pairs
+// of the order go to the outputs; scratch holds sort_scratch_bytes(n, ...)
+// bytes; h (or null) receives path 9.
+int topk_by_sort(const void* keys, const void* rowids, uint64_t n, uint64_t k_eff, int key_type,
+                 int rid_type, int order, void* out_keys, void* out_rowids, void* scratch,
+                 QHead* h, hipStream_t st);
+
 template <int KT, int RT>
 int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, int order,
                void* out_keys, void* out_rids, void* ws, size_t ws_bytes, hipStream_t st,

@@ -88,6 +88,19 @@ inline SamplePlan plan_sample(uint64_t n, uint64_t k_eff, const Tuning& t) {
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Bytes of the full sort's scratch for n pairs (tk_sort's layout): two
+// ping-pong copies of the keys and row-ids, a 4-byte count per digit and tile
+// of 4096 pairs, and the digit totals.
+inline size_t sort_scratch_bytes(uint64_t n, uint32_t kb, uint32_t rb) {
+  const uint64_t ntiles = n ? (n + 4095) / 4096 : 1;
+  return 2 * (align_up((size_t)n * kb, 256) + align_up((size_t)n * rb, 256)) +
+         align_up((size_t)ntiles * 256 * 4, 256) + align_up(256 * 4, 256);
+}
+
+// Queries without a usable sample from this size on are answered by the full
+// sort, keeping the first K (path 9); below it by one workgroup (path 8).
+constexpr uint64_t SORT_ROUTE_MIN_N = 1ull << 16;
+
 // The bucketed tail (large K): logarithmic buckets of a W-bit composite
 // distance with 2^sub buckets per octave.
 constexpr uint64_t BUCKET_TAIL_MIN_K = 2049;  // smaller K: the survivors are ranked directly
@@ -105,6 +118,8 @@ struct WsLayout {
   size_t tmp = 0;      // merge ping-pong: k_eff composites, SoA
   size_t btail = 0;    // bucketed tail (large K): histogram, cursors, offsets, state, and
                        // cap composites grouped by bucket (0 when not used)
+  size_t sort = 0;     // full sort's scratch (queries the sort answers; 0 when not used)
+  size_t base = 0;     // bytes without the sort's scratch (the exact select's minimum)
   size_t total = 0;
 };
 
@@ -130,8 +145,12 @@ inline WsLayout ws_layout(uint64_t n, uint64_t k_eff, uint32_t kb, uint32_t rb, 
     L.btail = off;
     off += btail_bytes(p.cap, kb, rb);
   }
+  L.base = off;
+  if (!p.fast && n >= SORT_ROUTE_MIN_N && n < (1ull << 32)) {  // the sort route's scratch
+    L.sort = align_up(off, 256);
+    off = L.sort + sort_scratch_bytes(n, kb, rb);
+  }
   L.total = off;
-  (void)n;
   return L;
 }
 

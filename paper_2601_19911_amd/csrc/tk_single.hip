@@ -488,9 +488,14 @@ void set_tuning(const tk_tuning* t) {
   if (t->filter_grid < 0) g_tuning.filter_grid = 0;
 }
 
-size_t single_ws_bytes(uint64_t n, uint64_t k_eff, uint32_t kb, uint32_t rb, const Tuning& t) {
+// with_sort: the bytes tk_workspace_size reports; else the least workspace a
+// query runs with (queries without a usable sample then take the grid-wide
+// select instead of the sort)
+size_t single_ws_bytes(uint64_t n, uint64_t k_eff, uint32_t kb, uint32_t rb, const Tuning& t,
+                       bool with_sort = true) {
   const SamplePlan p = plan_sample(n, k_eff, t);
-  return ws_layout(n, k_eff, kb, rb, p).total;
+  const WsLayout L = ws_layout(n, k_eff, kb, rb, p);
+  return with_sort ? L.total : L.base;
 }
 
 template <int KT, int RT>
@@ -526,11 +531,19 @@ int run_single(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, i
     if (rc != TK_OK || !recover_on_device(n, tun)) return rc;
     exact_mode = 2;  // returns at once unless the sample misjudged
   }
-  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return TK_EINVAL;
+  if (!ws || ws_bytes < L.base || ((uintptr_t)ws & 255u)) return TK_EINVAL;
   if (exact_mode == 1 && !tun.force_exact && n < ONE_WG_INPUT_MAX) {
     // no usable sample and a small input: one workgroup selects over it (the
     // cooperative launch of the grid-wide select costs more than it saves here)
     return run_input_one_wg<KT, RT>(keys, rids, n, k_eff, order, out_keys, out_rids, ws, st, L);
+  }
+  if (exact_mode == 1 && !tun.force_exact && L.sort && ws_bytes >= L.total) {
+    // no usable sample and K a large share of N: the full radix sort is a few
+    // streaming passes, where the grid-wide select takes a round per digit plus
+    // merge-path merges of K elements (a workspace without room for the sort's
+    // scratch keeps the grid-wide select)
+    return topk_by_sort(keys, rids, n, k_eff, KT, RT, order, out_keys, out_rids,
+                        ws_ptr<char>(ws, L.sort), &ws_ptr<Header>(ws, 0)->q, st);
   }
   Header* h = ws_ptr<Header>(ws, 0);
   U* cand_k = ws_ptr<U>(ws, L.cand);
@@ -577,6 +590,12 @@ extern "C" size_t tk_workspace_size(uint64_t n, uint64_t k, int key_type, int ri
   const uint64_t k_eff = k < n ? k : n;
   const uint32_t kb = key_bytes(key_type), rb = rid_type == TK_RID_U64 ? 8 : 4;
   return single_ws_bytes(n, k_eff, kb, rb, current_tuning());
+}
+
+extern "C" size_t tk_workspace_min_size(uint64_t n, uint64_t k, int key_type, int rid_type) {
+  const uint64_t k_eff = k < n ? k : n;
+  const uint32_t kb = key_bytes(key_type), rb = rid_type == TK_RID_U64 ? 8 : 4;
+  return single_ws_bytes(n, k_eff, kb, rb, current_tuning(), false);
 }
 
 extern "C" int tk_topk(const void* keys, const void* rowids, uint64_t n, uint64_t k, int key_type,
@@ -646,8 +665,10 @@ extern "C" int tk_topk_noalloc(const void* keys, const void* rowids, uint64_t n,
     if (out_count) *out_count = 0;
     return TK_OK;
   }
-  const size_t need = tk_workspace_size(n, k, key_type, rid_type);
-  if (need > TK_NOALLOC_SCRATCH_BYTES) return TK_EUNSUPPORTED;
+  // the least workspace the query runs with: a query without a usable sample
+  // whose sort scratch does not fit takes the grid-wide select
+  if (tk_workspace_min_size(n, k, key_type, rid_type) > TK_NOALLOC_SCRATCH_BYTES)
+    return TK_EUNSUPPORTED;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return TK_EHIP;
   void* ws = scratch_on(dev);

@@ -24,6 +24,7 @@
 
 #include "mitopk.h"
 #include "tk_device.hpp"
+#include "tk_internal.hpp"
 
 namespace {
 
@@ -50,6 +51,8 @@ struct PassArgs {
   uint32_t desc;
   uint32_t* counts;     // [RADIX][ntiles], scanned in place by k_sscan
   uint32_t* totals;     // [RADIX]
+  uint64_t limit;       // the last pass writes only positions below it (a Top-K of K = limit)
+  tk::QHead* h;         // a Top-K query's header (path recorded by the first pass), or null
 };
 
 template <int KT>
@@ -87,6 +90,10 @@ __global__ __launch_bounds__(SORT_NT) void k_sup(PassArgs<typename tk::Key<KT>::
   using U = typename tk::Key<KT>::U;
   __shared__ uint32_t h[SORT_WAVES][RADIX];
   const uint32_t w = threadIdx.x >> 6;
+  if (a.first && a.h && blockIdx.x == 0 && threadIdx.x == 0) {
+    a.h->path = 9u;
+    a.h->status = 0u;
+  }
   for (uint32_t i = threadIdx.x; i < SORT_WAVES * RADIX; i += SORT_NT) (&h[0][0])[i] = 0;
   __syncthreads();
   const uint64_t base = (uint64_t)blockIdx.x * TILE;
@@ -226,11 +233,14 @@ __global__ __launch_bounds__(SORT_NT) void k_sdown(PassArgs<typename tk::Key<KT>
     const uint32_t d = digit_of(sv, rv, a.shift, a.rid_digit);
     const uint64_t g = gbase[d] + (p - dstart[d]);
     if (a.last) {
-      if (a.out_keys) reinterpret_cast<Raw*>(a.out_keys)[g] = unimage<KT>(sv, a.desc);
+      if (g < a.limit) {
+        if (a.out_keys) reinterpret_cast<Raw*>(a.out_keys)[g] = unimage<KT>(sv, a.desc);
+        if (a.out_rids) a.out_rids[g] = rv;
+      }
     } else {
       a.out_keys[g] = sv;
+      a.out_rids[g] = rv;
     }
-    a.out_rids[g] = rv;
   }
 }
 
@@ -258,7 +268,7 @@ SortLayout layout(uint64_t n, int key_type, int rid_type) {
 
 template <int KT, typename R>
 int sort_t(const void* keys, const void* rids, uint64_t n, int order, void* out_keys, void* out_rids,
-           void* ws, hipStream_t st, int rid_type) {
+           void* ws, hipStream_t st, int rid_type, uint64_t limit, tk::QHead* hq) {
   using U = typename tk::Key<KT>::U;
   const SortLayout L = layout(n, KT, rid_type);
   char* w = static_cast<char*>(ws);
@@ -278,6 +288,8 @@ int sort_t(const void* keys, const void* rids, uint64_t n, int order, void* out_
   a.desc = order == TK_DESC ? 1u : 0u;
   a.counts = reinterpret_cast<uint32_t*>(w + L.counts);
   a.totals = reinterpret_cast<uint32_t*>(w + L.totals);
+  a.limit = limit;
+  a.h = hq;
   for (int p = 0; p < np; ++p) {
     a.first = p == 0;
     a.last = p == np - 1;
@@ -296,12 +308,37 @@ int sort_t(const void* keys, const void* rids, uint64_t n, int order, void* out_
 
 template <int KT>
 int sort_rid(const void* keys, const void* rids, uint64_t n, int rid_type, int order, void* ok,
-             void* orr, void* ws, hipStream_t st) {
-  if (rid_type == TK_RID_U32) return sort_t<KT, uint32_t>(keys, rids, n, order, ok, orr, ws, st, rid_type);
-  return sort_t<KT, unsigned long long>(keys, rids, n, order, ok, orr, ws, st, rid_type);
+             void* orr, void* ws, hipStream_t st, uint64_t limit, tk::QHead* hq) {
+  if (rid_type == TK_RID_U32)
+    return sort_t<KT, uint32_t>(keys, rids, n, order, ok, orr, ws, st, rid_type, limit, hq);
+  return sort_t<KT, unsigned long long>(keys, rids, n, order, ok, orr, ws, st, rid_type, limit, hq);
+}
+
+int sort_any(const void* keys, const void* rowids, uint64_t n, int key_type, int rid_type, int order,
+             void* out_keys, void* out_rowids, void* ws, hipStream_t st, uint64_t limit,
+             tk::QHead* hq) {
+  switch (key_type) {
+    case TK_KEY_I32: return sort_rid<tk::KEY_I32>(keys, rowids, n, rid_type, order, out_keys, out_rowids, ws, st, limit, hq);
+    case TK_KEY_I64: return sort_rid<tk::KEY_I64>(keys, rowids, n, rid_type, order, out_keys, out_rowids, ws, st, limit, hq);
+    case TK_KEY_F32: return sort_rid<tk::KEY_F32>(keys, rowids, n, rid_type, order, out_keys, out_rowids, ws, st, limit, hq);
+    default: return sort_rid<tk::KEY_F64>(keys, rowids, n, rid_type, order, out_keys, out_rowids, ws, st, limit, hq);
+  }
 }
 
 }  // namespace
+
+namespace tk {
+
+// The Top-K of a query by its full sort: the first k_eff pairs of the order
+// are written to the outputs (the last pass writes nothing past them).
+int topk_by_sort(const void* keys, const void* rowids, uint64_t n, uint64_t k_eff, int key_type,
+                 int rid_type, int order, void* out_keys, void* out_rowids, void* scratch,
+                 QHead* h, hipStream_t st) {
+  return sort_any(keys, rowids, n, key_type, rid_type, order, out_keys, out_rowids, scratch, st,
+                  k_eff, h);
+}
+
+}  // namespace tk
 
 extern "C" size_t tk_sort_workspace_size(uint64_t n, int key_type, int rid_type) {
   if (key_type < TK_KEY_I32 || key_type > TK_KEY_F64 || (rid_type != TK_RID_U32 && rid_type != TK_RID_U64))
@@ -320,12 +357,7 @@ extern "C" int tk_sort(const void* keys, const void* rowids, uint64_t n, int key
   if (((uintptr_t)workspace & 255) != 0) return TK_EINVAL;
   if (workspace_bytes < layout(n, key_type, rid_type).bytes) return TK_EINVAL;
   if (!rowids && rid_type == TK_RID_U32 && n > (1ull << 32)) return TK_EINVAL;
-  if ((n + TILE - 1) / TILE > 0xFFFFFFFFull) return TK_EUNSUPPORTED;
-  hipStream_t st = (hipStream_t)stream;
-  switch (key_type) {
-    case TK_KEY_I32: return sort_rid<tk::KEY_I32>(keys, rowids, n, rid_type, order, out_keys, out_rowids, workspace, st);
-    case TK_KEY_I64: return sort_rid<tk::KEY_I64>(keys, rowids, n, rid_type, order, out_keys, out_rowids, workspace, st);
-    case TK_KEY_F32: return sort_rid<tk::KEY_F32>(keys, rowids, n, rid_type, order, out_keys, out_rowids, workspace, st);
-    default: return sort_rid<tk::KEY_F64>(keys, rowids, n, rid_type, order, out_keys, out_rowids, workspace, st);
-  }
+  if (n >= (1ull << 32)) return TK_EUNSUPPORTED;  // 32-bit digit counts and offsets
+  return sort_any(keys, rowids, n, key_type, rid_type, order, out_keys, out_rowids, workspace,
+                  (hipStream_t)stream, n, nullptr);
 }

@@ -90,9 +90,30 @@ def test_noalloc_array_size_matches_header():
     text = open(os.path.join(ROOT, "include", "mitopk.h")).read()
     m = re.search(r"#define TK_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
     assert m and (int(m.group(1)) << int(m.group(2))) == tk.NOALLOC_SCRATCH_BYTES
-    # every K up to 100000 fits at any N up to 2^30, all key and row-id types
+    # every K up to 100000 runs in the array at any N up to 2^30, all key and
+    # row-id types (a query with no usable sample may do so without the sort's scratch)
     for lg in range(1, 31):
         for n in ((1 << lg) - 1, 1 << lg, 3 << (lg - 1)):
             for kt in range(4):
                 for rt in range(2):
-                    assert tk.workspace_size(n, 100000, kt, rt) <= tk.NOALLOC_SCRATCH_BYTES
+                    assert tk.workspace_min_size(n, 100000, kt, rt) <= tk.NOALLOC_SCRATCH_BYTES
+
+
+def test_workspace_min_size():
+    """The least workspace differs from tk_workspace_size only by the full
+    sort's scratch, only for queries without a usable sample from 2^16 keys
+    (K above N / 2, or K above N / 16 past 2^20 keys)."""
+    kb, rb = {0: 4, 1: 8, 2: 4, 3: 8}, {0: 4, 1: 8}
+    for n, k, sorts in [(1000, 900, False), (65535, 40000, False), (65536, 40000, True),
+                        (1 << 20, 1000, False), (1 << 20, 1 << 17, False), (1 << 22, 1 << 19, True),
+                        (1 << 28, 1000, False), ((1 << 21) + 1, 1 << 20, True)]:
+        for kt in range(4):
+            for rt in range(2):
+                full = tk.workspace_size(n, k, kt, rt)
+                least = tk.workspace_min_size(n, k, kt, rt)
+                assert 0 < least <= full
+                if sorts:
+                    # two ping-pong copies of every pair, plus digit counts
+                    assert full - least >= 2 * n * (kb[kt] + rb[rt])
+                else:
+                    assert full == least, (n, k, kt, rt)

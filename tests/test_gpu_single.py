@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 
 import paper_2601_19911_amd as tk
 
-KINDS = {"int32": inputgen.KIND_U_I32, "float32": inputgen.KIND_U_F32, "int64": inputgen.KIND_U_I64}
+KINDS = {"int32": inputgen.KIND_U_I32, "float32": inputgen.KIND_U_F32, "int64": inputgen.KIND_U_I64,
+         "float64": inputgen.KIND_U_F64}
 
 
 def run(keys, rids, k, order, rid_dtype=np.uint32, workspace=None, offset=0):
@@ -327,16 +328,31 @@ def _run_path_cases(cases, want_path, seed):
         assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"{dtype} n={n} k={k} {order}")
 
 
-def test_exact_path_small_grids():
+_NO_SAMPLE_LARGE = [("int32", 65536, 40000, "desc"), ("float32", 1 << 22, 1 << 19, "desc"),
+                    ("int64", 1 << 21, 1 << 20, "asc"), ("float64", 100_003, 60_000, "desc"),
+                    ("int32", (1 << 20) + 4097, 600_000, "asc")]
+
+
+def test_no_sample_paths():
     """Inputs past one LDS tile that the sample cannot serve (N below 16 sample
     chunks of 2048 keys, K above N / 2, or K above N / 16 at N past 2^20): from
-    2^16 keys the exact radix select over the input on a grid sized by N
-    (path 5), below it one workgroup's select over the input (path 8)."""
-    _run_path_cases([("int32", 65536, 40000, "desc"), ("float32", 1 << 22, 1 << 19, "desc"),
-                     ("int64", 1 << 21, 1 << 20, "asc")], 5, seed=300)
+    2^16 keys the full radix sort keeping its first K pairs (path 9), below it
+    one workgroup's select over the input (path 8)."""
+    _run_path_cases(_NO_SAMPLE_LARGE, 9, seed=300)
     _run_path_cases([("int32", 23170, 10, "desc"), ("float32", 30048, 1000, "asc"),
                      ("int64", 20000, 3000, "asc"), ("int64", 16385, 10, "desc"),
                      ("float32", 65535, 40000, "asc"), ("int32", 40000, 20001, "desc")], 8, seed=301)
+
+
+def test_exact_select_grid():
+    """The same queries by the exact radix select over the input on a grid
+    sized by N (path 5, taken here with force_exact; the sort route's queries
+    take it when their workspace has no room for the sort's scratch)."""
+    try:
+        tk.set_tuning(force_exact=1)
+        _run_path_cases(_NO_SAMPLE_LARGE, 5, seed=300)
+    finally:
+        tk.set_tuning(force_exact=2)
 
 
 def test_wide_k_sampled():

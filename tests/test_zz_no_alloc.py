@@ -51,12 +51,21 @@ def test_noalloc_two_calls_second_smaller():
 
 
 def test_noalloc_exact_and_small_paths():
-    # exact radix select over the input (K above N / 2), then a one-tile query
+    # no usable sample (K above N / 2): the full sort keeping K pairs, then a one-tile query
     n = 300_001
     keys = inputgen.generate(inputgen.KIND_U_I32, inputgen.config_seed(2, 52), n)
     _both(keys, None, 200_000, "desc", np.uint32)
     keys = inputgen.generate(inputgen.KIND_U_F32, inputgen.config_seed(2, 53), 5000)
     _both(keys, None, 300, "asc", np.uint32)
+
+
+def test_noalloc_sort_scratch_beyond_the_array():
+    # no usable sample, the sort's scratch (64 MiB) beyond the array: the grid-wide
+    # exact select (8 MiB) runs instead and equals tk_topk's sort route
+    n = 1 << 22
+    keys = inputgen.generate(inputgen.KIND_U_F32, inputgen.config_seed(2, 54), n)
+    assert tk.workspace_size(n, 1 << 19, tk.TK_KEY_F32, tk.TK_RID_U32) > tk.NOALLOC_SCRATCH_BYTES
+    _both(keys, None, 1 << 19, "desc", np.uint32)
 
 
 def test_noalloc_refuses_beyond_the_array():
