@@ -1,11 +1,11 @@
-// Sampled single-query Top-K (ordering primitive, paper sec. III-A): four
-// plain kernels on the caller's stream; no workgroup waits for or hands data
-// to another within a kernel, so no device-wide fence is needed.
+// Sampled single-query Top-K (ordering primitive, paper sec. III-A): three
+// plain kernels on the caller's stream; no workgroup waits for another.
 //
 //   k_sample  S keys in 16-key chunks spread over the query, 2048 per
-//             workgroup; each workgroup keeps its best r1 composites.
-//   k_sfinal  one workgroup selects the r1-th best of those candidates: the
-//             threshold T.
+//             workgroup; each workgroup keeps its best r1 composites, and the
+//             last one to finish selects the r1-th best of all of them: the
+//             threshold T (the only hand-over between workgroups, through a
+//             device-scope fence and an arrival count; no waiting).
 //   k_filter  the single streaming pass over the keys: composites >= T are
 //             staged in LDS (wave ballot + LDS atomic) and appended to the
 //             survivor buffer with one global atomic per workgroup.
@@ -13,7 +13,7 @@
 //             histogram of the survivors' distance to the threshold bounds a
 //             small hot set, whose members are ranked by counting and written
 //             at their rank (tk_rank.hpp).
-//   k_bhist, k_bscatter, k_bsort   the tail for large K (tk_bucket.hpp):
+//   k_bhist, k_bscan, k_bscatter, k_bsort   the tail for large K (tk_bucket.hpp):
 //             survivors grouped by a logarithmic bucket of their distance to
 //             the threshold, runs of whole hot buckets sorted in LDS and
 //             written at their offset.
@@ -42,6 +42,7 @@ template <int KT, int RT>
 __global__ __launch_bounds__(SAMP_NT) void k_sample(SampArgs a) {
   __shared__ SelScratch sc;
   sample_body<KT, RT>(a, sc, blockIdx.x);
+  if (a.fuse_final) sample_last_final<KT, RT>(a, sc);
 }
 
 template <int KT, int RT>
@@ -72,15 +73,21 @@ __global__ __launch_bounds__(RANK_NT) void k_rtail(TailArgs1 a) {
 template <int KT, int RT>
 __global__ __launch_bounds__(BT_NT) void k_bhist(BTailArgs b) {
   __shared__ uint32_t lh[BT<KT, RT>::NB];
-  bhist_body<KT, RT>(b, lh);
+  __shared__ uint32_t red[16];
+  bhist_body<KT, RT>(b, lh, red);
 }
 
 template <int KT, int RT>
-__global__ __launch_bounds__(BT_NT) void k_bscatter(BTailArgs b) {
-  __shared__ uint32_t loff[BT<KT, RT>::NB];
+__global__ __launch_bounds__(BS_NT) void k_bscan(BTailArgs b) {
+  __shared__ uint32_t loff[bs_padded<BT<KT, RT>::NB>()];
+  __shared__ uint32_t red[48];
+  bscan_body<KT, RT>(b, loff, red);
+}
+
+template <int KT, int RT>
+__global__ __launch_bounds__(BSC_NT) void k_bscatter(BTailArgs b) {
   __shared__ uint32_t lcnt[BT<KT, RT>::NB];
-  __shared__ uint32_t red[32];
-  bscatter_body<KT, RT>(b, loff, lcnt, red);
+  bscatter_body<KT, RT>(b, lcnt);
 }
 
 template <int KT, int RT>
@@ -131,7 +138,7 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
   uint32_t* bt_words = bucketed ? wsp<uint32_t>(ws, L.btail) : nullptr;  // gh, cur, chunk
   const uint32_t defer = recover_on_device(n, tun) ? 1u : 0u;
   const SampArgs sa{keys, rids, n, dmask, p.S, p.r1, h, samp_k, samp_f, p.blocks, defer,
-                    bt_words, bucketed ? 2ull * nb : 0ull};
+                    bt_words, bucketed ? 2ull * nb : 0ull, 0u, 0u};
   hipLaunchKernelGGL((k_sample<KT, RT>), dim3(p.blocks), dim3(SAMP_NT), 0, st, sa);
   constexpr int VEC = 16 / sizeof(Raw);
   const bool u8 = tun.filter_unroll == 8;
@@ -153,7 +160,8 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
                        wsp<BMeta>(ws, L.btail + (size_t)3 * nb * 4), wsp<char>(ws, L.btail + hot),
                        wsp<char>(ws, L.btail + hot + align_up((size_t)p.cap * sizeof(U), 256))};
     hipLaunchKernelGGL((k_bhist<KT, RT>), dim3(BT_SLICES), dim3(BT_NT), 0, st, bt);
-    hipLaunchKernelGGL((k_bscatter<KT, RT>), dim3(BT_SCATTER), dim3(BT_NT), 0, st, bt);
+    hipLaunchKernelGGL((k_bscan<KT, RT>), dim3(1), dim3(BS_NT), 0, st, bt);
+    hipLaunchKernelGGL((k_bscatter<KT, RT>), dim3(BT_SCATTER), dim3(BSC_NT), 0, st, bt);
     hipLaunchKernelGGL((k_bsort<KT, RT>), dim3(BT_GRID), dim3(TAIL_NT), 0, st, bt);
   } else if (tun.rank_tail)
     hipLaunchKernelGGL((k_rtail<KT, RT>), dim3(rank_grid(k_eff)), dim3(RANK_NT), 0, st, ta);

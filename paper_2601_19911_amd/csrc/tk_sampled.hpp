@@ -38,6 +38,8 @@ struct SampArgs {
                          // single query whose misjudged sample is taken over by it)
   uint32_t* zero;  // nzero words the sample workgroups clear for later launches, or nullptr
   uint64_t nzero;
+  uint32_t fuse_final;  // 1: the last sample workgroup to finish also selects the threshold
+  uint32_t pad;
 };
 
 struct FiltArgs {
@@ -95,6 +97,117 @@ __device__ __forceinline__ uint64_t sample_hash(uint64_t c) {
   return z ^ (z >> 31);
 }
 
+// ---- small sample ranks: a tournament instead of the radix select ------------------------------
+//
+// With r1 at most SMALL_R_MAX, the r1 best of a workgroup's composites take no
+// radix rounds: each lane sorts its few composites in registers, each wave
+// pops its r1 best with r1 wave-wide maxima of the lanes' heads, and one wave
+// ranks the waves' lists (at most 64 entries, one per lane) by counting.  One
+// barrier in all, where the radix select takes several per digit.
+constexpr uint32_t SMALL_R_MAX = 16;
+
+// Wave-wide maximum through DPP lane moves (a few cycles each, where a
+// shuffle goes through the LDS crossbar): xor 1 and xor 2 (quad
+// permutations), the half-row and row mirrors (xor 4 and xor 8 once the quads
+// and half-rows are uniform), then row 0 into row 1 and row 2 into row 3
+// (broadcast of lane 15) and rows 0-1 into rows 2-3 (broadcast of lane 31):
+// lane 63 ends up holding the maximum, which is read into every lane.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_max_step(T v) {
+  if constexpr (sizeof(T) == 8) {
+    const uint64_t w = ((uint64_t)dpp_move<CTRL, ROWS>((uint32_t)(v >> 32)) << 32) |
+                       (uint64_t)dpp_move<CTRL, ROWS>((uint32_t)v);
+    return w > v ? (T)w : v;
+  } else {
+    T w = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      w |= (T)dpp_move<CTRL, ROWS>((uint32_t)(v >> (32 * q))) << (32 * q);
+    return w > v ? w : v;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max_wide(T v) {
+  v = dpp_max_step<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+  v = dpp_max_step<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+  v = dpp_max_step<0x141, 0xF>(v);  // row_half_mirror
+  v = dpp_max_step<0x140, 0xF>(v);  // row_mirror
+  v = dpp_max_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_max_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  T r = 0;
+#pragma unroll
+  for (int q = 0; q < (int)sizeof(T) / 4; ++q)
+    r |= (T)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> (32 * q)), 63) << (32 * q);
+  return r;
+}
+
+// odd-even transposition sort of a lane's E composites, best (largest) first
+template <typename T, int E>
+__device__ __forceinline__ void regs_sort_desc(T (&v)[E]) {
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+#pragma unroll
+    for (int j = i & 1; j + 1 < E; j += 2) {
+      const T x = v[j], y = v[j + 1];
+      v[j] = x < y ? y : x;
+      v[j + 1] = x < y ? x : y;
+    }
+  }
+}
+
+// The r best composites of a workgroup of NT threads, each holding E of them
+// (padding: 0, the smallest composite), as a multiset: out_hi/out_lo (LDS, 64
+// words each) end up holding them in rank order for ranks < r.  Every thread
+// must call it (it holds a barrier); on return the list is visible to all.
+template <int NT, typename T, int E>
+__device__ __forceinline__ void block_top_small(T (&v)[E], uint32_t r, uint64_t* out_hi,
+                                                uint64_t* out_lo, uint64_t* lst_hi,
+                                                uint64_t* lst_lo) {
+  constexpr uint32_t NW = NT / 64;
+  static_assert(NW * SMALL_R_MAX <= 64, "the waves' lists fit one wave");
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  regs_sort_desc(v);
+  for (uint32_t i = 0; i < r; ++i) {
+    const T m = wave_max_wide(v[0]);
+    const uint64_t hit = ballot(v[0] == m);
+    if (lane == (uint32_t)__builtin_ctzll(hit)) {
+#pragma unroll
+      for (int e = 0; e + 1 < E; ++e) v[e] = v[e + 1];
+      v[E - 1] = 0;
+    }
+    if (lane == 0) {
+      lst_hi[w * r + i] = sizeof(T) == 8 ? 0ull : (uint64_t)((__uint128_t)m >> 64);
+      lst_lo[w * r + i] = (uint64_t)m;
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t tot = NW * r;
+    auto at = [&](uint32_t j) -> T {
+      if constexpr (sizeof(T) == 8) return (T)lst_lo[j];
+      else return (T)(((__uint128_t)lst_hi[j] << 64) | (__uint128_t)lst_lo[j]);
+    };
+    const T c = lane < tot ? at(lane) : (T)0;
+    uint32_t rank = 0;
+#pragma unroll 4
+    for (uint32_t j = 0; j < tot; ++j) {
+      const T x = at(j);
+      rank += (x > c || (x == c && j < lane)) ? 1u : 0u;
+    }
+    if (lane < tot && rank < r) {
+      out_hi[rank] = (uint64_t)((__uint128_t)c >> 64);
+      out_lo[rank] = (uint64_t)c;
+    }
+  }
+  __syncthreads();
+}
+
 // blk: this workgroup's index among the query's a.nblk sample workgroups.
 // Each keeps the best r1 composites of its SAMPLE_PER_BLOCK sampled keys
 // (the union of these holds the sample's best r1); the next launch selects
@@ -136,14 +249,29 @@ __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, u
     k[e] = src.key(pos);
     f[e] = src.flip(pos);
   }
+  U* ck = static_cast<U*>(a.ck);
+  R* cf = static_cast<R*>(a.cf);
+  if (a.r1 <= SMALL_R_MAX) {
+    using T = typename Wide<U, R>::T;
+    T v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = wide(k[e], f[e]);
+    uint64_t* sh = reinterpret_cast<uint64_t*>(sc.hist);  // the waves' lists: 64 + 64 words
+    block_top_small<NT, T, E>(v, a.r1, reinterpret_cast<uint64_t*>(sc.red),
+                              reinterpret_cast<uint64_t*>(sc.red2), sh, sh + 64);
+    if (threadIdx.x < a.r1) {
+      const T c = (T)(((__uint128_t)sc.red[threadIdx.x] << 64) | sc.red2[threadIdx.x]);
+      ck[(uint64_t)blk * a.r1 + threadIdx.x] = (U)(c >> (8 * sizeof(R)));
+      cf[(uint64_t)blk * a.r1 + threadIdx.x] = (R)c;
+    }
+    return;
+  }
   U lmin = k[0];
 #pragma unroll
   for (int e = 1; e < E; ++e) lmin = k[e] < lmin ? k[e] : lmin;
   const U base = block_min<NT, U>(lmin, sc);
   const RegElems<U, R, E> el{k, f, E};
   const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.r1, base, sc);
-  U* ck = static_cast<U*>(a.ck);
-  R* cf = static_cast<R*>(a.cf);
   block_compact_regs<NT, U, R, E>(el, s, a.r1, ck + (uint64_t)blk * a.r1,
                                   cf + (uint64_t)blk * a.r1, sc);
 }
@@ -228,27 +356,42 @@ __device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch&
       f2[e] = 0;
     }
   }
-  const U base = block_min<NT, U>(cmin, sc);
-  const RegElems<U, R, EF> el{k2, f2, nv};
-  const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.r1, base, sc);
-  // The threshold is the r1-th best candidate itself, the smallest of the
-  // selected ones.  The select may stop with low digits unresolved (its
-  // bucket held exactly the count needed); the prefix padded with zeros
-  // would also admit every key between it and that candidate, which for
-  // clustered keys (a presorted column) is a large share of the input.
-  const U lo = s.base + s.P;
-  const R lof = s.kind == SEL_KEY ? (R)0 : s.Pf;
   U mk = (U)~(U)0;
   R mf = (R)~(R)0;
+  if (a.r1 <= SMALL_R_MAX) {
+    // the r1-th entry of the tournament's list (padding 0 never ranks above
+    // a candidate it is not equal to)
+    using T = typename Wide<U, R>::T;
+    T v[EF];
 #pragma unroll
-  for (int e = 0; e < EF; ++e) {
-    const bool in = e < nv && (k2[e] > lo || (k2[e] == lo && f2[e] >= lof));
-    if (in && (k2[e] < mk || (k2[e] == mk && f2[e] < mf))) {
-      mk = k2[e];
-      mf = f2[e];
+    for (int e = 0; e < EF; ++e) v[e] = wide(k2[e], f2[e]);
+    uint64_t* sh = reinterpret_cast<uint64_t*>(sc.hist);
+    block_top_small<NT, T, EF>(v, a.r1, reinterpret_cast<uint64_t*>(sc.red),
+                               reinterpret_cast<uint64_t*>(sc.red2), sh, sh + 64);
+    const T c = (T)(((__uint128_t)sc.red[a.r1 - 1] << 64) | (__uint128_t)sc.red2[a.r1 - 1]);
+    mk = (U)(c >> (8 * sizeof(R)));
+    mf = (R)c;
+  } else {
+    const U base = block_min<NT, U>(cmin, sc);
+    const RegElems<U, R, EF> el{k2, f2, nv};
+    const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.r1, base, sc);
+    // The threshold is the r1-th best candidate itself, the smallest of the
+    // selected ones.  The select may stop with low digits unresolved (its
+    // bucket held exactly the count needed); the prefix padded with zeros
+    // would also admit every key between it and that candidate, which for
+    // clustered keys (a presorted column) is a large share of the input.
+    const U lo = s.base + s.P;
+    const R lof = s.kind == SEL_KEY ? (R)0 : s.Pf;
+#pragma unroll
+    for (int e = 0; e < EF; ++e) {
+      const bool in = e < nv && (k2[e] > lo || (k2[e] == lo && f2[e] >= lof));
+      if (in && (k2[e] < mk || (k2[e] == mk && f2[e] < mf))) {
+        mk = k2[e];
+        mf = f2[e];
+      }
     }
+    block_min_comp<NT, U, R>(mk, mf, sc);
   }
-  block_min_comp<NT, U, R>(mk, mf, sc);
   // candidates sharing the threshold's key: when they are most of them, keys
   // tied with the threshold are common and the streaming pass reads row-ids
   // along with the keys
@@ -267,6 +410,32 @@ __device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch&
     a.h->thr_f = (unsigned long long)mf;
     a.h->tie_heavy = 2 * tot >= a.ncand ? 1u : 0u;
   }
+}
+
+// The threshold selected by the last sample workgroup to finish, instead of a
+// launch of its own: each workgroup publishes its candidates (device-scope
+// fence) before counting its arrival; the one that completes the count reads
+// everyone's after a second fence.  The count starts at zero because the
+// streaming pass of the previous query on this state cleared it.  On a state
+// never used before the count is arbitrary: then the threshold may be
+// selected early, by the wrong workgroup or not at all, which changes how many
+// keys the streaming pass keeps but never the result (a survivor count
+// outside [K, capacity] sends the query to the exact select over the input).
+template <int KT, int RT>
+__device__ __forceinline__ void sample_last_final(const SampArgs& a, SelScratch& sc) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) sc.cnt[0] = atomicAdd(&a.h->samp_done, 1u);
+  __syncthreads();
+  if ((sc.cnt[0] + 1u) % a.nblk != 0u) return;
+  __threadfence();
+  FiltArgs f{};
+  f.h = a.h;
+  f.r1 = a.r1;
+  f.ck = a.ck;
+  f.cf = a.cf;
+  f.ncand = a.nblk * a.r1;
+  sample_final_body<KT, RT>(f, sc);
 }
 
 // Row-ids of VEC consecutive keys: 16-byte loads when the rows allow.
@@ -367,6 +536,9 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
   if (threadIdx.x == 0) st.cnt = 0;
   __syncthreads();
   QHead* h = a.h;
+  // the sample's arrival count, for the query that follows on this state (every
+  // sample workgroup of this query finished before this launch began)
+  if (blk == 0 && threadIdx.x == 0) h->samp_done = 0u;
   const U Tk = (U)h->thr_k;
   const R Tf = (R)h->thr_f;
   const R* rids = static_cast<const R*>(a.rids);

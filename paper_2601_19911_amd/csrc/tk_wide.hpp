@@ -42,6 +42,19 @@ __device__ __forceinline__ uint32_t log_bucket_s(T d) {
          ((uint32_t)(d >> (L - SUB - 1)) & ((1u << SUB) - 1u));
 }
 
+// The G bits of d right under the ones log_bucket_s<SUB> keeps (zero-padded
+// when fewer remain; 0 for the exact buckets): with the bucket, a finer key
+// that is still non-decreasing in d.
+template <int SUB, typename T>
+__device__ __forceinline__ uint32_t log_subdigit(T d, int G) {
+  const int L = wbitlen(d);
+  if (L <= SUB + 1) return 0u;
+  const int rem = L - SUB - 1;  // bits under the bucket's
+  const uint32_t mask = (1u << G) - 1u;
+  if (rem >= G) return (uint32_t)(d >> (rem - G)) & mask;
+  return ((uint32_t)d << (G - rem)) & mask;
+}
+
 // Buckets of the large-K tail: 256 per octave for 8-byte composites, else 128.
 template <typename U_, typename R_>
 struct BTU {
@@ -53,6 +66,9 @@ struct BTU {
   static constexpr uint32_t NB = (1u << SUB) * (uint32_t)(W - SUB + 1);
   static __device__ __forceinline__ uint32_t bucket(U u, R f, T base) {
     return log_bucket_s<SUB, T>(wide(u, f) - base);
+  }
+  static __device__ __forceinline__ uint32_t subdigit(U u, R f, T base, int G) {
+    return log_subdigit<SUB, T>(wide(u, f) - base, G);
   }
 };
 template <int KT, int RT>

@@ -105,6 +105,7 @@ def test_full_size(dtype, dist, k, order):
     say(f"full size: {dtype} {dist} N=2^28 K={k} {order}")
     keys, rids, host = cached_input(dtype, dist)
     gk, gr, info = run_query(keys, rids, k, order)
+    assert info["path"] == (6 if k > 2048 else 3)  # the sample held: no fallback
     ek, er = oracle.topk(host, None, k, oracle.DESC if order == "desc" else oracle.ASC,
                          rid_dtype=np.uint64 if dtype == "int64" else np.uint32)
     assert_same(gk, gr, ek, er, what=f"{dtype} {dist} K={k} {order}")

@@ -417,3 +417,98 @@ def test_read_probe():
     assert L.tk_read_probe(buf.data_ptr() + 4, 1 << 20, 3, sink.data_ptr(), None) == -1  # TK_EINVAL
     assert L.tk_read_probe(buf.data_ptr(), 1 << 20, 0, sink.data_ptr(), None) == -1  # TK_EINVAL
     assert L.tk_read_probe(buf.data_ptr(), 1 << 20, 3, None, None) == -1  # TK_EINVAL
+
+
+# ---- the sampled threshold, checked from the outside -------------------------------------------
+
+def _plan_sample(n, k):
+    """(S, r1) of the sampled path at the default tuning: the largest sample of
+    2^11..2^20 keys (at least 16 keys per sampled key) whose rank r1 =
+    ceil(m + 3 sqrt(m) + 3), m = K S / N, keeps r1 x S / 2048 candidates within
+    2048 for the final select."""
+    import math
+    for lg in range(20, 10, -1):
+        s = 1 << lg
+        if s * 16 > n:
+            continue
+        m = float(k) * float(s) / float(n)
+        r1 = math.ceil(m + 3.0 * math.sqrt(m) + 3.0)
+        if r1 <= 2048 and r1 * (s // 2048) <= 2048:
+            return s, r1
+    return None
+
+
+def _sample_positions(n, s):
+    """Chunk c of 16 consecutive keys starts at c x stride plus the high word of
+    (SplitMix64 finalizer of c + 1 times its increment) x (stride - 15)."""
+    m64 = (1 << 64) - 1
+    nch = s // 16
+    stride = n // nch
+    span = stride - 15
+    pos = np.empty(s, dtype=np.int64)
+    for c in range(nch):
+        z = ((c + 1) * 0x9E3779B97F4A7C15) & m64
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m64
+        z ^= z >> 31
+        pos[16 * c:16 * c + 16] = c * stride + ((z * span) >> 64) + np.arange(16)
+    return pos
+
+
+def _images(keys, order):
+    """Order-preserving unsigned images (totalOrder for floats), flipped for ascending."""
+    if keys.dtype in (np.float32, np.float64):
+        bits = 8 * keys.dtype.itemsize
+        ut = np.uint32 if bits == 32 else np.uint64
+        b = keys.view(ut)
+        sign = ut(1) << ut(bits - 1)
+        img = np.where(b & sign, ~b, b | sign).astype(np.uint64)
+    else:
+        bits = 8 * keys.dtype.itemsize
+        ut = np.uint32 if bits == 32 else np.uint64
+        img = (keys.view(ut) ^ (ut(1) << ut(bits - 1))).astype(np.uint64)
+    if order == "asc":
+        img = ~img & np.uint64((1 << bits) - 1 if bits < 64 else (1 << 64) - 1)
+    return img
+
+
+@pytest.mark.parametrize("dtype,n,k,order,explicit", [
+    ("float32", (1 << 24) + 12345, 100, "desc", False),   # r1 = 9: the tournament
+    ("float32", (1 << 24) + 12345, 5000, "asc", True),    # r1 = 36: the radix select
+    ("int64", (1 << 22) + 7, 10, "desc", False),          # r1 = 6, 16-byte composites
+    ("float64", 1 << 22, 1000, "asc", False),             # r1 = 31
+    ("int32", 1 << 22, 1, "desc", True),                  # r1 = 4, heavy ties
+])
+def test_sampled_threshold_is_the_samples_rank(dtype, n, k, order, explicit):
+    """The threshold is the r1-th best composite of the stratified sample and the
+    survivor count is the number of input composites at or above it: both
+    recomputed on the host from the sample's definition."""
+    import torch
+    kind = {"float32": inputgen.KIND_U_F32, "int64": inputgen.KIND_U_I64,
+            "float64": inputgen.KIND_U_F64, "int32": inputgen.KIND_U_I32}[dtype]
+    keys = inputgen.generate(kind, 900 + k, n)
+    if dtype == "int32":
+        keys = (keys % 1009).astype(np.int32)
+    rdt = np.uint64 if dtype in ("int64", "float64") else np.uint32
+    rb = 8 * np.dtype(rdt).itemsize
+    rids = np.random.default_rng(k).permutation(n).astype(rdt) if explicit else np.arange(n, dtype=rdt)
+    s, r1 = _plan_sample(n, k)
+    img = _images(keys, order)
+    flip = ~rids
+    pos = _sample_positions(n, s)
+    comp = sorted(((int(img[p]) << rb) | int(flip[p]) for p in pos), reverse=True)
+    t = comp[r1 - 1]
+    tk_, tf_ = t >> rb, t & ((1 << rb) - 1)
+    surv = int(np.count_nonzero(img > np.uint64(tk_)) +
+               np.count_nonzero((img == np.uint64(tk_)) & (flip.astype(np.uint64) >= np.uint64(tf_))))
+    ws = tk.new_workspace(n, k, tk.key_code(keys.dtype), tk.rid_code(np.dtype(rdt)))
+    ok, orr = tk.topk(to_dev(keys), k, rowids=to_dev(rids) if explicit else None, order=order,
+                      rid_dtype=torch.uint64 if rdt == np.uint64 else torch.uint32, workspace=ws)
+    torch.cuda.synchronize()
+    info = tk.query_info(ws)
+    say(f"{dtype} n={n} k={k} {order}: S={s} r1={r1} threshold {tk_:#x} survivors {surv}: {info}")
+    assert info["status"] == 0 and info["path"] in (3, 6)
+    assert info["threshold_key"] == tk_
+    assert info["survivors"] == surv
+    exp = oracle.topk(keys, rids if explicit else None, k, order_code(order), rid_dtype=rdt)
+    assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"{dtype} n={n} k={k}")
