@@ -8,14 +8,13 @@
 //               into the query's global histogram (cleared by the sample
 //               launch).  Few workgroups: every bucket counter they share
 //               takes one atomic from each.
-//   k_bscan     one workgroup derives from the histogram the boundary bucket
-//               b* holding rank K and the exclusive offset of every hot bucket
-//               (b >= b*), which starts that bucket's scatter cursor, and cuts
-//               the hot set into chunks of whole buckets that fit one LDS tile.
-//   k_bscatter  every workgroup reserves room in each hot bucket for its slice
-//               of the survivors with one global atomic per bucket and
+//   k_bscatter  every workgroup derives from the histogram the boundary
+//               bucket b* holding rank K and the exclusive offset of every
+//               bucket, reserves room in each hot bucket (b >= b*) for its
+//               slice of the survivors with one global atomic per bucket, and
 //               scatters its hot survivors there: the hot set grouped by
-//               bucket, best bucket first.
+//               bucket, best bucket first.  Workgroup 0 also cuts the hot set
+//               into chunks of whole buckets that fit one LDS tile.
 //   k_bsort     each workgroup sorts chunks in LDS and writes every member at
 //               chunk offset + rank, up to K.
 // The bucket is monotone in the composite, so a chunk's members take the
@@ -30,7 +29,6 @@
 namespace tk {
 
 constexpr int BT_NT = 256;           // k_bhist
-constexpr int BS_NT = 1024;          // k_bscan (one workgroup)
 constexpr int BSC_NT = 1024;         // k_bscatter
 constexpr uint32_t BT_SLICES = 128;  // workgroups of k_bhist
 // workgroups of k_bscatter: every one takes a global atomic on each hot
@@ -120,7 +118,7 @@ __device__ __forceinline__ void bhist_body(const BTailArgs& b, uint32_t* lh, uin
   hs.load(sk, sf, a.cap);
   const uint64_t C = a.h->surv_count;
   const typename B::T base = wide((U)a.h->thr_k, (R)a.h->thr_f);
-  if (!(C >= a.k_eff && C <= a.cap)) return;  // uniform; k_bscan flags the fallback
+  if (!(C >= a.k_eff && C <= a.cap)) return;  // uniform; k_bscatter flags the fallback
   const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
   // the range of buckets this workgroup touches: only it is cleared and added
   // into the global histogram (all of them when the slice is not all held)
@@ -163,44 +161,35 @@ __device__ __forceinline__ void bhist_body(const BTailArgs& b, uint32_t* lh, uin
   }
 }
 
-// k_bscan, one workgroup: the boundary bucket, every hot bucket's offset
-// (written as the scatter's starting cursor), and the chunks.
-// k_bscan's LDS copy of the histogram is read by each thread over BPT
+// k_bscatter's LDS copy of the histogram is read by each thread over BPT
 // consecutive buckets; a word of padding after every 32 keeps a wave's lanes
 // on distinct banks.
 __device__ __forceinline__ uint32_t bs_pad(uint32_t bin) { return bin + (bin >> 5); }
 template <uint32_t NB>
 constexpr uint32_t bs_padded() { return NB + (NB >> 5) + 1; }
 
+// From the global histogram: the boundary bucket b* (holding rank K), the
+// hot set's size and every bucket's exclusive offset (members of better
+// buckets, into loff at bs_pad), and the chunks.  Every workgroup of
+// k_bscatter derives the same; workgroup 0 also writes the chunk starts and
+// the tail's state.  Returns false (workgroup 0 having flagged the fallback)
+// when the survivor count or a hot bucket is outside this path's limits.
+// Every thread calls it.
 template <int KT, int RT>
-__device__ __forceinline__ void bscan_body(const BTailArgs& b, uint32_t* loff, uint32_t* red) {
+__device__ __forceinline__ bool bucket_offsets(const BTailArgs& b, uint64_t C, uint32_t* loff,
+                                               uint32_t* red, uint32_t& bstar_out) {
   using B = BT<KT, RT>;
-  constexpr uint32_t NB = B::NB, BPT = (NB + BS_NT - 1) / BS_NT;
+  constexpr uint32_t NB = B::NB, BPT = (NB + BSC_NT - 1) / BSC_NT;
   constexpr uint32_t CAP = LdsTile<KT, RT>::CAP;
   const TailArgs1& a = b.t;
   const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
-  // the histogram into LDS, every load of the thread in flight at once (and
-  // not waiting for the survivor count)
-  {
-    uint32_t c[BPT];
-#pragma unroll
-    for (uint32_t q = 0; q < BPT; ++q) {
-      const uint32_t i = q * BS_NT + t;
-      c[q] = i < NB ? b.gh[i] : 0u;
-    }
-#pragma unroll
-    for (uint32_t q = 0; q < BPT; ++q) {
-      const uint32_t i = q * BS_NT + t;
-      if (i < NB) loff[bs_pad(i)] = c[q];
-    }
-  }
-  const uint64_t C = a.h->surv_count;
+  const bool lead = blockIdx.x == 0;
   const uint64_t K = a.k_eff;
   if (!(C >= K && C <= a.cap)) {
-    if (t == 0) b.meta->fallback = 1u;
-    return;
+    if (lead && t == 0) b.meta->fallback = 1u;
+    return false;
   }
-  __syncthreads();
+  __syncthreads();  // the histogram is in loff
   // suffix sums: thread t holds buckets [t BPT, t BPT + BPT)
   uint32_t s = 0;
 #pragma unroll
@@ -218,9 +207,8 @@ __device__ __forceinline__ void bscan_body(const BTailArgs& b, uint32_t* loff, u
   __syncthreads();
   uint32_t above = x - s;
 #pragma unroll
-  for (int i = 0; i < BS_NT / 64; ++i) above += (uint32_t)i > w ? red[i] : 0u;
-  // exclusive offsets (members of better buckets); a bucket is hot while its
-  // offset is below K, and its scatter cursor starts at that offset; the
+  for (int i = 0; i < BSC_NT / 64; ++i) above += (uint32_t)i > w ? red[i] : 0u;
+  // exclusive offsets; a bucket is hot while its offset is below K; the
   // boundary bucket is the one that reaches K
   uint32_t mx = 0;
 #pragma unroll
@@ -229,10 +217,7 @@ __device__ __forceinline__ void bscan_body(const BTailArgs& b, uint32_t* loff, u
     if (bin >= NB) continue;
     const uint32_t c = loff[bs_pad(bin)];
     loff[bs_pad(bin)] = above;
-    if (above < K) {
-      mx = c > mx ? c : mx;
-      b.cur[bin] = above;
-    }
+    if (above < K) mx = c > mx ? c : mx;
     if (above < K && K <= (uint64_t)above + c) {
       red[16] = bin;
       red[17] = above + c;
@@ -244,7 +229,7 @@ __device__ __forceinline__ void bscan_body(const BTailArgs& b, uint32_t* loff, u
   __syncthreads();
   const uint32_t bstar = red[16], H = red[17];
 #pragma unroll
-  for (int i = 0; i < BS_NT / 64; ++i) mx = red[32 + i] > mx ? red[32 + i] : mx;
+  for (int i = 0; i < BSC_NT / 64; ++i) mx = red[32 + i] > mx ? red[32 + i] : mx;
   // chunks of whole buckets: chunk c holds the buckets whose offset lies in
   // [c tgt, (c + 1) tgt), at most tgt - 1 + mx <= CAP members
   // tgt = 2^sh: about one chunk per k_bsort workgroup, and tgt - 1 + mx <= CAP
@@ -254,49 +239,69 @@ __device__ __forceinline__ void bscan_body(const BTailArgs& b, uint32_t* loff, u
   while ((2u << sh) <= lim && (1u << sh) < want) ++sh;
   const uint32_t nch = (H + (1u << sh) - 1) >> sh;
   if (mx > CAP || nch + 1 > NB) {
-    if (t == 0) b.meta->fallback = 1u;
-    return;
+    if (lead && t == 0) b.meta->fallback = 1u;
+    return false;
   }
-  for (uint32_t c = t; c <= nch; c += BS_NT) b.chunk[c] = H;
-  __syncthreads();
-  // bucket bin starts the chunks c with off[bin + 1] < c tgt <= off[bin]
+  if (lead) {
+    for (uint32_t c = t; c <= nch; c += BSC_NT) b.chunk[c] = H;
+    __syncthreads();
+    // bucket bin starts the chunks c with off[bin + 1] < c tgt <= off[bin]
 #pragma unroll
-  for (uint32_t i = 0; i < BPT; ++i) {
-    const uint32_t bin = t * BPT + i;
-    if (bin >= NB || bin < bstar) continue;
-    const uint32_t o = loff[bs_pad(bin)];
-    const uint32_t c1 = o >> sh;
-    const uint32_t c0 = bin + 1 < NB ? (loff[bs_pad(bin + 1)] >> sh) + 1 : 0u;
-    for (uint32_t c = c0; c <= c1; ++c) b.chunk[c] = o;
+    for (uint32_t i = 0; i < BPT; ++i) {
+      const uint32_t bin = t * BPT + i;
+      if (bin >= NB || bin < bstar) continue;
+      const uint32_t o = loff[bs_pad(bin)];
+      const uint32_t c1 = o >> sh;
+      const uint32_t c0 = bin + 1 < NB ? (loff[bs_pad(bin + 1)] >> sh) + 1 : 0u;
+      for (uint32_t c = c0; c <= c1; ++c) b.chunk[c] = o;
+    }
+    if (t == 0) {
+      b.meta->bstar = bstar;
+      b.meta->hot = H;
+      b.meta->nchunk = nch;
+      b.meta->fallback = 0u;
+    }
   }
-  if (t == 0) {
-    b.meta->bstar = bstar;
-    b.meta->hot = H;
-    b.meta->nchunk = nch;
-    b.meta->fallback = 0u;
-  }
+  bstar_out = bstar;
+  return true;
 }
 
-// k_bscatter: each workgroup counts its slice's hot survivors per bucket,
-// reserves room in each hot bucket with one global atomic on the bucket's
-// cursor, and places them.  Only the hot buckets (>= the boundary) are held.
+// k_bscatter: each workgroup derives the offsets (bucket_offsets), counts its
+// slice's hot survivors per bucket, reserves room in each hot bucket with one
+// global atomic on the bucket's cursor (cleared by the sample launch), and
+// places them.  Only the hot buckets (>= the boundary) are counted.
 template <int KT, int RT>
-__device__ __forceinline__ void bscatter_body(const BTailArgs& b, uint32_t* lcnt) {
+__device__ __forceinline__ void bscatter_body(const BTailArgs& b, uint32_t* loff, uint32_t* lcnt,
+                                              uint32_t* red) {
   using B = BT<KT, RT>;
   using U = typename B::U;
   using R = typename B::R;
-  constexpr uint32_t NB = B::NB;
+  constexpr uint32_t NB = B::NB, BPT = (NB + BSC_NT - 1) / BSC_NT;
   const TailArgs1& a = b.t;
   const U* sk = static_cast<const U*>(a.sk);
   const R* sf = static_cast<const R*>(a.sf);
-  // the survivors, the query state and the tail's state, read together
+  const uint32_t t = threadIdx.x;
+  // the survivors, the histogram and the query state, read together: every
+  // load in flight at once, none waiting for the survivor count
   HeldSlice<U, R, BSC_NT> hs;
   hs.load(sk, sf, a.cap);
-  const uint32_t fallback = b.meta->fallback, bstar = b.meta->bstar;
+  {
+    uint32_t c[BPT];
+#pragma unroll
+    for (uint32_t q = 0; q < BPT; ++q) {
+      const uint32_t i = q * BSC_NT + t;
+      c[q] = i < NB ? b.gh[i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < BPT; ++q) {
+      const uint32_t i = q * BSC_NT + t;
+      if (i < NB) loff[bs_pad(i)] = c[q];
+    }
+  }
   const uint64_t C = a.h->surv_count;
   const typename B::T base = wide((U)a.h->thr_k, (R)a.h->thr_f);
-  if (fallback) return;  // uniform
-  const uint32_t t = threadIdx.x;
+  uint32_t bstar = 0;
+  if (!bucket_offsets<KT, RT>(b, C, loff, red, bstar)) return;  // uniform
   const uint32_t nh = NB - bstar;
   for (uint32_t i = t; i < nh; i += BSC_NT) lcnt[i] = 0;
   uint32_t bk[BT_BATCH];
@@ -327,7 +332,7 @@ __device__ __forceinline__ void bscatter_body(const BTailArgs& b, uint32_t* lcnt
 #pragma unroll
     for (int q = 0; q < BT_BATCH; ++q) {
       const uint32_t i = i0 + (uint32_t)q * BSC_NT;
-      if (c[q]) lcnt[i] = r[q];
+      if (c[q]) lcnt[i] = loff[bs_pad(bstar + i)] + r[q];
     }
   }
   __syncthreads();

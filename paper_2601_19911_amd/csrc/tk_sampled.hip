@@ -13,7 +13,7 @@
 //             histogram of the survivors' distance to the threshold bounds a
 //             small hot set, whose members are ranked by counting and written
 //             at their rank (tk_rank.hpp).
-//   k_bhist, k_bscan, k_bscatter, k_bsort   the tail for large K (tk_bucket.hpp):
+//   k_bhist, k_bscatter, k_bsort   the tail for large K (tk_bucket.hpp):
 //             survivors grouped by a logarithmic bucket of their distance to
 //             the threshold, runs of whole hot buckets sorted in LDS and
 //             written at their offset.
@@ -78,16 +78,11 @@ __global__ __launch_bounds__(BT_NT) void k_bhist(BTailArgs b) {
 }
 
 template <int KT, int RT>
-__global__ __launch_bounds__(BS_NT) void k_bscan(BTailArgs b) {
-  __shared__ uint32_t loff[bs_padded<BT<KT, RT>::NB>()];
-  __shared__ uint32_t red[48];
-  bscan_body<KT, RT>(b, loff, red);
-}
-
-template <int KT, int RT>
 __global__ __launch_bounds__(BSC_NT) void k_bscatter(BTailArgs b) {
+  __shared__ uint32_t loff[bs_padded<BT<KT, RT>::NB>()];
   __shared__ uint32_t lcnt[BT<KT, RT>::NB];
-  bscatter_body<KT, RT>(b, lcnt);
+  __shared__ uint32_t red[48];
+  bscatter_body<KT, RT>(b, loff, lcnt, red);
 }
 
 template <int KT, int RT>
@@ -160,7 +155,6 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
                        wsp<BMeta>(ws, L.btail + (size_t)3 * nb * 4), wsp<char>(ws, L.btail + hot),
                        wsp<char>(ws, L.btail + hot + align_up((size_t)p.cap * sizeof(U), 256))};
     hipLaunchKernelGGL((k_bhist<KT, RT>), dim3(BT_SLICES), dim3(BT_NT), 0, st, bt);
-    hipLaunchKernelGGL((k_bscan<KT, RT>), dim3(1), dim3(BS_NT), 0, st, bt);
     hipLaunchKernelGGL((k_bscatter<KT, RT>), dim3(BT_SCATTER), dim3(BSC_NT), 0, st, bt);
     hipLaunchKernelGGL((k_bsort<KT, RT>), dim3(BT_GRID), dim3(TAIL_NT), 0, st, bt);
   } else if (tun.rank_tail)
