@@ -197,12 +197,7 @@ __device__ __forceinline__ bool bucket_offsets(const BTailArgs& b, uint64_t C, u
     const uint32_t bin = t * BPT + i;
     s += bin < NB ? loff[bs_pad(bin)] : 0u;
   }
-  uint32_t x = s;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_down(x, o, 64);
-    if (lane + (uint32_t)o < 64) x += y;
-  }
+  const uint32_t x = wave_suffix_sum(s);  // sum over lanes >= this one
   if (lane == 0) red[w] = x;
   __syncthreads();
   uint32_t above = x - s;

@@ -87,14 +87,34 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
   return v;
 }
 
+// A DPP lane move within the wave (a few cycles, where a shuffle goes
+// through the LDS crossbar): lanes of the rows in ROWS take v from the lane
+// CTRL names; other lanes, and lanes whose source is outside their row, take
+// `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+// Inclusive prefix sum over the wave: shifts right by 1, 2, 4 and 8 inside
+// each row of 16 lanes, then the last lane of row 0 into row 1 and of row 2
+// into row 3 (row_bcast:15), and the last lane of row 1 into rows 2 and 3
+// (row_bcast:31).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-  const uint32_t l = lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
-    if (l >= (uint32_t)o) x += y;
-  }
+  x += dpp_move<0x111, 0xF>(0u, x);  // row_shr:1
+  x += dpp_move<0x112, 0xF>(0u, x);  // row_shr:2
+  x += dpp_move<0x114, 0xF>(0u, x);  // row_shr:4
+  x += dpp_move<0x118, 0xF>(0u, x);  // row_shr:8
+  x += dpp_move<0x142, 0xA>(0u, x);  // row_bcast:15
+  x += dpp_move<0x143, 0xC>(0u, x);  // row_bcast:31
   return x;
+}
+
+// Sum of v over the lanes at and above this one.
+__device__ __forceinline__ uint32_t wave_suffix_sum(uint32_t v) {
+  const uint32_t incl = wave_incl_scan(v);
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  return total - incl + v;
 }
 
 // ---- block primitives (NT threads, NT a multiple of 64) -----------------------------------

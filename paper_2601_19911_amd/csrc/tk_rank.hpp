@@ -163,12 +163,7 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
     const uint32_t bin = t * BPT + i;
     s += bin < NB ? L.hist[bin] : 0u;
   }
-  uint32_t x = s;  // sum over lanes >= this one
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_down(x, o, 64);
-    if (lane + (uint32_t)o < 64) x += y;
-  }
+  const uint32_t x = wave_suffix_sum(s);  // sum over lanes >= this one
   if (lane == 0) L.wsum[w] = x;
   __syncthreads();
   uint32_t above = x - s;
@@ -212,12 +207,7 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
     own_bits |= hot && j >= jlo && j < jhi ? 1u << e : 0u;
   }
   const uint32_t packed = ((uint32_t)__popc(hot_bits) << 16) | (uint32_t)__popc(own_bits);
-  uint32_t incl = packed;  // inclusive scan over the lanes
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o, 64);
-    if (lane >= (uint32_t)o) incl += y;
-  }
+  const uint32_t incl = wave_incl_scan(packed);  // inclusive scan over the lanes
   if (lane == 63) L.wsum[w] = incl;
   __syncthreads();
   uint32_t excl = incl - packed, tot = 0;

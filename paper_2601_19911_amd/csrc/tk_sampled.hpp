@@ -112,22 +112,17 @@ constexpr uint32_t SMALL_R_MAX = 16;
 // and half-rows are uniform), then row 0 into row 1 and row 2 into row 3
 // (broadcast of lane 15) and rows 0-1 into rows 2-3 (broadcast of lane 31):
 // lane 63 ends up holding the maximum, which is read into every lane.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ uint32_t dpp_move(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, ROWS, 0xF, false);
-}
-
 template <int CTRL, int ROWS, typename T>
 __device__ __forceinline__ T dpp_max_step(T v) {
   if constexpr (sizeof(T) == 8) {
-    const uint64_t w = ((uint64_t)dpp_move<CTRL, ROWS>((uint32_t)(v >> 32)) << 32) |
-                       (uint64_t)dpp_move<CTRL, ROWS>((uint32_t)v);
+    const uint64_t w = ((uint64_t)dpp_move<CTRL, ROWS>((uint32_t)(v >> 32), (uint32_t)(v >> 32)) << 32) |
+                       (uint64_t)dpp_move<CTRL, ROWS>((uint32_t)v, (uint32_t)v);
     return w > v ? (T)w : v;
   } else {
     T w = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      w |= (T)dpp_move<CTRL, ROWS>((uint32_t)(v >> (32 * q))) << (32 * q);
+      w |= (T)dpp_move<CTRL, ROWS>((uint32_t)(v >> (32 * q)), (uint32_t)(v >> (32 * q))) << (32 * q);
     return w > v ? w : v;
   }
 }
