@@ -23,9 +23,7 @@ struct QHead {
   uint32_t status;                // device failure bits (1: barrier timeout)
   uint32_t path;                  // path taken, see tk_info
   uint32_t tie_heavy;             // 1: most sample candidates share the threshold's key
-  uint32_t samp_done;             // sample workgroups finished (the last one selects the
-                                  // threshold); cleared by the streaming pass
-  uint32_t pad[6];
+  uint32_t pad[7];
 };
 static_assert(sizeof(QHead) == 64, "QHead is 64 bytes");
 

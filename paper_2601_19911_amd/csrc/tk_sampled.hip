@@ -1,11 +1,11 @@
-// Sampled single-query Top-K (ordering primitive, paper sec. III-A): three
-// plain kernels on the caller's stream; no workgroup waits for another.
+// Sampled single-query Top-K (ordering primitive, paper sec. III-A): four
+// plain kernels on the caller's stream; no workgroup waits for or hands data
+// to another within a kernel, so no device-wide fence is needed.
 //
 //   k_sample  S keys in 16-key chunks spread over the query, 2048 per
-//             workgroup; each workgroup keeps its best r1 composites, and the
-//             last one to finish selects the r1-th best of all of them: the
-//             threshold T (the only hand-over between workgroups, through a
-//             device-scope fence and an arrival count; no waiting).
+//             workgroup; each workgroup keeps its best r1 composites.
+//   k_sfinal  one workgroup selects the r1-th best of those candidates: the
+//             threshold T.
 //   k_filter  the single streaming pass over the keys: composites >= T are
 //             staged in LDS (wave ballot + LDS atomic) and appended to the
 //             survivor buffer with one global atomic per workgroup.
@@ -42,7 +42,6 @@ template <int KT, int RT>
 __global__ __launch_bounds__(SAMP_NT) void k_sample(SampArgs a) {
   __shared__ SelScratch sc;
   sample_body<KT, RT>(a, sc, blockIdx.x);
-  if (a.fuse_final) sample_last_final<KT, RT>(a, sc);
 }
 
 template <int KT, int RT>
@@ -133,7 +132,7 @@ int run_sampled(const void* keys, const void* rids, uint64_t n, uint64_t k_eff, 
   uint32_t* bt_words = bucketed ? wsp<uint32_t>(ws, L.btail) : nullptr;  // gh, cur, chunk
   const uint32_t defer = recover_on_device(n, tun) ? 1u : 0u;
   const SampArgs sa{keys, rids, n, dmask, p.S, p.r1, h, samp_k, samp_f, p.blocks, defer,
-                    bt_words, bucketed ? 2ull * nb : 0ull, 0u, 0u};
+                    bt_words, bucketed ? 2ull * nb : 0ull};
   hipLaunchKernelGGL((k_sample<KT, RT>), dim3(p.blocks), dim3(SAMP_NT), 0, st, sa);
   constexpr int VEC = 16 / sizeof(Raw);
   const bool u8 = tun.filter_unroll == 8;

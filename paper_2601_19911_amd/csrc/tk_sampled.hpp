@@ -38,8 +38,6 @@ struct SampArgs {
                          // single query whose misjudged sample is taken over by it)
   uint32_t* zero;  // nzero words the sample workgroups clear for later launches, or nullptr
   uint64_t nzero;
-  uint32_t fuse_final;  // 1: the last sample workgroup to finish also selects the threshold
-  uint32_t pad;
 };
 
 struct FiltArgs {
@@ -407,32 +405,6 @@ __device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch&
   }
 }
 
-// The threshold selected by the last sample workgroup to finish, instead of a
-// launch of its own: each workgroup publishes its candidates (device-scope
-// fence) before counting its arrival; the one that completes the count reads
-// everyone's after a second fence.  The count starts at zero because the
-// streaming pass of the previous query on this state cleared it.  On a state
-// never used before the count is arbitrary: then the threshold may be
-// selected early, by the wrong workgroup or not at all, which changes how many
-// keys the streaming pass keeps but never the result (a survivor count
-// outside [K, capacity] sends the query to the exact select over the input).
-template <int KT, int RT>
-__device__ __forceinline__ void sample_last_final(const SampArgs& a, SelScratch& sc) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) sc.cnt[0] = atomicAdd(&a.h->samp_done, 1u);
-  __syncthreads();
-  if ((sc.cnt[0] + 1u) % a.nblk != 0u) return;
-  __threadfence();
-  FiltArgs f{};
-  f.h = a.h;
-  f.r1 = a.r1;
-  f.ck = a.ck;
-  f.cf = a.cf;
-  f.ncand = a.nblk * a.r1;
-  sample_final_body<KT, RT>(f, sc);
-}
-
 // Row-ids of VEC consecutive keys: 16-byte loads when the rows allow.
 template <typename R, int VEC>
 __device__ __forceinline__ void load_rowids(const R* p, bool aligned16, R (&out)[VEC]) {
@@ -531,9 +503,6 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
   if (threadIdx.x == 0) st.cnt = 0;
   __syncthreads();
   QHead* h = a.h;
-  // the sample's arrival count, for the query that follows on this state (every
-  // sample workgroup of this query finished before this launch began)
-  if (blk == 0 && threadIdx.x == 0) h->samp_done = 0u;
   const U Tk = (U)h->thr_k;
   const R Tf = (R)h->thr_f;
   const R* rids = static_cast<const R*>(a.rids);
