@@ -28,12 +28,32 @@
 
 namespace {
 
-constexpr int SORT_NT = 256;           // threads per workgroup
+#ifndef TK_SORT_NT
+#define TK_SORT_NT 512
+#endif
+#ifndef TK_SORT_ITEMS_SMALL
+#define TK_SORT_ITEMS_SMALL 16
+#endif
+#ifndef TK_SORT_ITEMS_WIDE
+#define TK_SORT_ITEMS_WIDE 8
+#endif
+constexpr int SORT_NT = TK_SORT_NT;    // threads per workgroup of k_sup and k_sdown
 constexpr int SORT_WAVES = SORT_NT / 64;
+constexpr int SCAN_NT = 256;           // threads per workgroup of k_sscan
 constexpr int RADIX = 256;             // 8-bit digits
-constexpr int SORT_ITEMS = 16;         // pairs per thread
-constexpr uint32_t TILE = SORT_NT * SORT_ITEMS;
-constexpr uint32_t WAVE_CHUNK = 64 * SORT_ITEMS;  // a wave's contiguous share of a tile
+static_assert(SORT_NT >= RADIX, "a thread per digit");
+
+// Pairs per thread and per tile: a tile is staged in LDS by k_sdown, and the
+// longer a tile, the longer the run each digit writes.  Measured on MI355X at
+// 2^24 pairs: 512 threads with 8192-pair tiles (8-byte pairs; 4096 for wider
+// ones, 64 KiB of LDS, two workgroups per CU) beat 256 threads with 4096 pairs
+// by 9-12 %, and one workgroup per CU with longer tiles by 15-40 %.
+constexpr int items_for(uint32_t pair_bytes) {
+  return pair_bytes <= 8 ? TK_SORT_ITEMS_SMALL : TK_SORT_ITEMS_WIDE;
+}
+constexpr uint32_t tile_for(uint32_t pair_bytes) { return SORT_NT * items_for(pair_bytes); }
+static_assert(tile_for(8) >= 4096 && tile_for(16) >= 4096,
+              "the scratch bound of the sort route counts 4096-pair tiles");
 
 // Where a pass reads and writes.  Input keys are raw (encoded when first is
 // set); keys in the workspace hold the order image; the last pass decodes.
@@ -88,24 +108,29 @@ __device__ __forceinline__ uint32_t digit_of(U s, R r, uint32_t shift, uint32_t 
 template <int KT, typename R>
 __global__ __launch_bounds__(SORT_NT) void k_sup(PassArgs<typename tk::Key<KT>::U, R> a) {
   using U = typename tk::Key<KT>::U;
+  constexpr int SORT_ITEMS = items_for(sizeof(U) + sizeof(R));
+  constexpr uint32_t TILE = tile_for(sizeof(U) + sizeof(R));
   __shared__ uint32_t h[SORT_WAVES][RADIX];
   const uint32_t w = threadIdx.x >> 6;
   if (a.first && a.h && blockIdx.x == 0 && threadIdx.x == 0) {
     a.h->path = 9u;
     a.h->status = 0u;
   }
-  for (uint32_t i = threadIdx.x; i < SORT_WAVES * RADIX; i += SORT_NT) (&h[0][0])[i] = 0;
-  __syncthreads();
+  // every load of the thread in flight at once, then the counts
   const uint64_t base = (uint64_t)blockIdx.x * TILE;
-#pragma unroll 4
+  U s[SORT_ITEMS];
+  R r[SORT_ITEMS];
+#pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
     const uint64_t i = base + (uint64_t)it * SORT_NT + threadIdx.x;
-    if (i < a.n) {
-      U s;
-      R r;
-      load_pair<KT, R>(a, i, s, r);
-      atomicAdd(&h[w][digit_of(s, r, a.shift, a.rid_digit)], 1u);
-    }
+    if (i < a.n) load_pair<KT, R>(a, i, s[it], r[it]);
+  }
+  for (uint32_t i = threadIdx.x; i < SORT_WAVES * RADIX; i += SORT_NT) (&h[0][0])[i] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    const uint64_t i = base + (uint64_t)it * SORT_NT + threadIdx.x;
+    if (i < a.n) atomicAdd(&h[w][digit_of(s[it], r[it], a.shift, a.rid_digit)], 1u);
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < RADIX; d += SORT_NT) {
@@ -117,11 +142,11 @@ __global__ __launch_bounds__(SORT_NT) void k_sup(PassArgs<typename tk::Key<KT>::
 }
 
 // One workgroup per digit: exclusive scan of counts[d][0..ntiles) in place.
-__global__ __launch_bounds__(SORT_NT) void k_sscan(uint32_t* counts, uint32_t ntiles, uint32_t* totals) {
-  __shared__ uint32_t ws[SORT_WAVES];
+__global__ __launch_bounds__(SCAN_NT) void k_sscan(uint32_t* counts, uint32_t ntiles, uint32_t* totals) {
+  __shared__ uint32_t ws[SCAN_NT / 64];
   uint32_t* row = counts + (uint64_t)blockIdx.x * ntiles;
   uint32_t carry = 0;
-  for (uint32_t base = 0; base < ntiles; base += SORT_NT * 4) {
+  for (uint32_t base = 0; base < ntiles; base += SCAN_NT * 4) {
     uint32_t v[4], sum = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -130,7 +155,7 @@ __global__ __launch_bounds__(SORT_NT) void k_sscan(uint32_t* counts, uint32_t nt
       sum += v[q];
     }
     uint32_t total = 0;
-    const uint32_t off = tk::block_excl_scan<SORT_NT>(sum, ws, total);
+    const uint32_t off = tk::block_excl_scan<SCAN_NT>(sum, ws, total);
     uint32_t run = carry + off;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -147,6 +172,9 @@ template <int KT, typename R>
 __global__ __launch_bounds__(SORT_NT) void k_sdown(PassArgs<typename tk::Key<KT>::U, R> a) {
   using U = typename tk::Key<KT>::U;
   using Raw = typename tk::Key<KT>::Raw;
+  constexpr int SORT_ITEMS = items_for(sizeof(U) + sizeof(R));
+  constexpr uint32_t TILE = tile_for(sizeof(U) + sizeof(R));
+  constexpr uint32_t WAVE_CHUNK = 64 * SORT_ITEMS;  // a wave's contiguous share of a tile
   __shared__ uint32_t wcnt[SORT_WAVES][RADIX];  // per wave counts, then offsets
   __shared__ uint32_t dstart[RADIX];            // first local position of each digit
   __shared__ uint64_t gbase[RADIX];             // global position of each digit's run
@@ -157,17 +185,8 @@ __global__ __launch_bounds__(SORT_NT) void k_sdown(PassArgs<typename tk::Key<KT>
   const uint64_t tbase = (uint64_t)blockIdx.x * TILE;
   const uint32_t nt = (uint32_t)((a.n - tbase) < TILE ? (a.n - tbase) : TILE);
 
-  // global start of every digit: scan of the digit totals + this tile's prefix
-  {
-    const uint32_t d = threadIdx.x;  // SORT_NT == RADIX
-    uint32_t total = 0;
-    const uint32_t before = tk::block_excl_scan<SORT_NT>(a.totals[d], ws, total);
-    gbase[d] = (uint64_t)before + a.counts[(uint64_t)d * a.ntiles + blockIdx.x];
-    for (int x = 0; x < SORT_WAVES; ++x) wcnt[x][d] = 0;
-  }
-  __syncthreads();
-
-  // stable rank inside the wave: position order is (wave, round, lane)
+  // the tile's pairs, the digit totals and this tile's prefixes: every load in
+  // flight at once
   U s[SORT_ITEMS];
   R r[SORT_ITEMS];
   uint32_t rk[SORT_ITEMS];
@@ -177,6 +196,21 @@ __global__ __launch_bounds__(SORT_NT) void k_sdown(PassArgs<typename tk::Key<KT>
     const uint32_t li = wbase + it * 64 + ln;
     if (li < nt) load_pair<KT, R>(a, tbase + li, s[it], r[it]);
   }
+  // global start of every digit: scan of the digit totals + this tile's prefix
+  // (thread d < RADIX holds digit d)
+  {
+    const uint32_t d = threadIdx.x;
+    const bool dig = d < (uint32_t)RADIX;
+    const uint32_t tot_d = dig ? a.totals[d] : 0u;
+    const uint32_t pre_d = dig ? a.counts[(uint64_t)d * a.ntiles + blockIdx.x] : 0u;
+    uint32_t total = 0;
+    const uint32_t before = tk::block_excl_scan<SORT_NT>(tot_d, ws, total);
+    if (dig) gbase[d] = (uint64_t)before + pre_d;
+    for (uint32_t i = threadIdx.x; i < SORT_WAVES * RADIX; i += SORT_NT) (&wcnt[0][0])[i] = 0;
+  }
+  __syncthreads();
+
+  // stable rank inside the wave: position order is (wave, round, lane)
   const uint64_t below = (1ull << ln) - 1ull;
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
@@ -203,15 +237,19 @@ __global__ __launch_bounds__(SORT_NT) void k_sdown(PassArgs<typename tk::Key<KT>
   // per digit: offsets of the waves inside the digit's run, and the run's start
   {
     const uint32_t d = threadIdx.x;
+    const bool dig = d < (uint32_t)RADIX;
     uint32_t run = 0;
+    if (dig) {
 #pragma unroll
-    for (int x = 0; x < SORT_WAVES; ++x) {
-      const uint32_t c = wcnt[x][d];
-      wcnt[x][d] = run;
-      run += c;
+      for (int x = 0; x < SORT_WAVES; ++x) {
+        const uint32_t c = wcnt[x][d];
+        wcnt[x][d] = run;
+        run += c;
+      }
     }
     uint32_t total = 0;
-    dstart[d] = tk::block_excl_scan<SORT_NT>(run, ws, total);
+    const uint32_t st = tk::block_excl_scan<SORT_NT>(run, ws, total);
+    if (dig) dstart[d] = st;
   }
   __syncthreads();
 #pragma unroll
@@ -252,8 +290,9 @@ struct SortLayout {
 
 SortLayout layout(uint64_t n, int key_type, int rid_type) {
   const uint64_t kb = tk::key_bytes(key_type), rb = rid_type == TK_RID_U64 ? 8 : 4;
+  const uint64_t tile = tile_for((uint32_t)(kb + rb));
   SortLayout L;
-  L.ntiles = (n + TILE - 1) / TILE;
+  L.ntiles = (n + tile - 1) / tile;
   if (L.ntiles == 0) L.ntiles = 1;
   uint64_t o = 0;
   L.keys_a = o; o += align256(n * kb);
@@ -300,7 +339,7 @@ int sort_t(const void* keys, const void* rids, uint64_t n, int order, void* out_
     a.out_keys = a.last ? static_cast<U*>(out_keys) : kbuf[p & 1];
     a.out_rids = a.last ? static_cast<R*>(out_rids) : rbuf[p & 1];
     hipLaunchKernelGGL((k_sup<KT, R>), dim3(a.ntiles), dim3(SORT_NT), 0, st, a);
-    hipLaunchKernelGGL(k_sscan, dim3(RADIX), dim3(SORT_NT), 0, st, a.counts, a.ntiles, a.totals);
+    hipLaunchKernelGGL(k_sscan, dim3(RADIX), dim3(SCAN_NT), 0, st, a.counts, a.ntiles, a.totals);
     hipLaunchKernelGGL((k_sdown<KT, R>), dim3(a.ntiles), dim3(SORT_NT), 0, st, a);
   }
   return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
