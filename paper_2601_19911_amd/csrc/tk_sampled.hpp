@@ -97,12 +97,21 @@ __device__ __forceinline__ uint64_t sample_hash(uint64_t c) {
 
 // ---- small sample ranks: a tournament instead of the radix select ------------------------------
 //
-// With r1 at most SMALL_R_MAX, the r1 best of a workgroup's composites take no
-// radix rounds: each lane sorts its few composites in registers, each wave
-// pops its r1 best with r1 wave-wide maxima of the lanes' heads, and one wave
-// ranks the waves' lists (at most 64 entries, one per lane) by counting.  One
-// barrier in all, where the radix select takes several per digit.
+// With r1 at most SMALL_R_MAX (and 8-byte composites), the r1 best of a
+// workgroup's composites take no radix rounds: each lane sorts its few
+// composites in registers, each wave pops its r1 best with r1 wave-wide maxima
+// of the lanes' heads, and one wave ranks the waves' lists (at most 64
+// entries, one per lane) by counting.  One barrier in all, where the radix
+// select takes several per digit.
 constexpr uint32_t SMALL_R_MAX = 16;
+
+// The tournament pays off for 8-byte composites; with wider ones (two 64-bit
+// words per DPP move and compare) the radix select was faster on MI355X, by
+// 2-3 us a launch for one query and 2x for the batched launches.
+template <typename U, typename R>
+__device__ __forceinline__ bool small_r_tournament(uint32_t r1) {
+  return sizeof(U) + sizeof(R) == 8 && r1 <= SMALL_R_MAX;
+}
 
 // Wave-wide maximum through DPP lane moves (a few cycles each, where a
 // shuffle goes through the LDS crossbar): xor 1 and xor 2 (quad
@@ -244,7 +253,7 @@ __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, u
   }
   U* ck = static_cast<U*>(a.ck);
   R* cf = static_cast<R*>(a.cf);
-  if (a.r1 <= SMALL_R_MAX) {
+  if (small_r_tournament<U, R>(a.r1)) {
     using T = typename Wide<U, R>::T;
     T v[E];
 #pragma unroll
@@ -351,7 +360,7 @@ __device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch&
   }
   U mk = (U)~(U)0;
   R mf = (R)~(R)0;
-  if (a.r1 <= SMALL_R_MAX) {
+  if (small_r_tournament<U, R>(a.r1)) {
     // the r1-th entry of the tournament's list (padding 0 never ranks above
     // a candidate it is not equal to)
     using T = typename Wide<U, R>::T;
