@@ -636,18 +636,19 @@ __device__ __forceinline__ void filter_body(const FiltArgs& a, uint32_t blk,
     }
     stage_survivor<U, R>(pass, kk, ff, st, h, sk, sf, a.cap, drids);
   }
-  // append the stage to the query's survivor buffer
+  // append the stage to the query's survivor buffer: the whole stage's
+  // row-id loads and the reservation in the buffer in flight together
   __syncthreads();
   const uint32_t c = st.cnt < FILT_STAGE ? st.cnt : FILT_STAGE;
-  if (threadIdx.x == 0) st.base = c ? atomicAdd(&h->surv_count, (unsigned long long)c) : 0ull;
-  __syncthreads();
-  constexpr int FL = FILT_STAGE / NT;  // the whole stage's row-id loads in flight at once
+  constexpr int FL = FILT_STAGE / NT;
   R fv[FL];
 #pragma unroll
   for (int q = 0; q < FL; ++q) {
     const uint32_t j = (uint32_t)q * NT + threadIdx.x;
     if (j < c) fv[q] = drids ? (R)~drids[st.f[j]] : st.f[j];
   }
+  if (threadIdx.x == 0) st.base = c ? atomicAdd(&h->surv_count, (unsigned long long)c) : 0ull;
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < FL; ++q) {
     const uint32_t j = (uint32_t)q * NT + threadIdx.x;
