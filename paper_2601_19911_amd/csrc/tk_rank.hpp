@@ -66,13 +66,16 @@ __device__ __noinline__ void rank_tail_fallback(const TailArgs1 a, unsigned char
   tail_body<KT, RT>(a, t, sc);
 }
 
-// The tail over gridDim.x workgroups of RANK_NT threads (RANK_GMIN <=
-// gridDim.x <= RANK_GMAX).  INPUT = false: over the filter's survivors
+// The tail over G workgroups of RANK_NT threads, this one being workgroup me
+// (a single query's launch: RANK_GMIN <= G <= RANK_GMAX; a batched launch: one
+// workgroup, G = 1).  INPUT = false: over the filter's survivors
 // (TAIL_SURVIVORS), distances taken from the threshold.  INPUT = true: over
 // the whole input of a query with n <= RANK_CMAX (TAIL_INPUT), distances taken
-// from the input's smallest composite; a.h may be null.
+// from the input's smallest composite; a.h may be null.  A query outside this
+// path's limits is finished by workgroup 0 with the one-workgroup tail.
 template <int KT, int RT, bool INPUT = false>
-__device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char* smem) {
+__device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char* smem,
+                                               uint32_t me, uint32_t G) {
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
   using T = typename Wide<U, R>::T;
@@ -152,7 +155,7 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
   }
   __syncthreads();
   if (!ok) {  // uniform; every thread is past its histogram updates (never with INPUT)
-    if (blockIdx.x == 0) rank_tail_fallback<KT, RT>(a, smem);
+    if (me == 0) rank_tail_fallback<KT, RT>(a, smem);
     return;
   }
   // boundary bucket: thread t holds buckets [t BPT, t BPT + BPT); suffix sums
@@ -184,16 +187,17 @@ __device__ __forceinline__ void rank_tail_body(const TailArgs1& a, unsigned char
   }
   __syncthreads();
   const uint32_t bstar = L.bstar, H = L.hcount;
-  if (H > RANK_HMAX) {
+  // workgroup me owns survivor indices [me * per, me * per + per); it ranks
+  // its hot members among them, at most RANK_MMAX (always so on RANK_GMIN or
+  // more workgroups; on one, the whole hot set must fit)
+  const uint32_t per = (C + G - 1) / G, jlo = me * per, jhi = jlo + per;
+  if (H > RANK_HMAX || (H < per ? H : per) > RANK_MMAX) {
     __syncthreads();  // every thread has read the boundary before the LDS is reused
-    if (blockIdx.x == 0) rank_tail_fallback<KT, RT>(a, smem);
+    if (me == 0) rank_tail_fallback<KT, RT>(a, smem);
     return;
   }
   // the hot set, and the part of it this workgroup ranks: per-thread counts,
   // one block-wide exclusive scan of (hot << 16 | owned), then plain stores
-  // workgroup me owns survivor indices [me * per, me * per + per)
-  const uint32_t G = gridDim.x, me = blockIdx.x;
-  const uint32_t per = (C + G - 1) / G, jlo = me * per, jhi = jlo + per;
   // hot iff D reaches the lower edge of the boundary bucket (the bucket is
   // monotone in D): D itself below 64, then (32 + sub) << (octave - 6)
   const T dlo = bstar < 64u ? (T)bstar

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(TAIL_NT) void k_tail1(TailArgs1 a) {
 template <int KT, int RT>
 __global__ __launch_bounds__(RANK_NT) void k_rtail(TailArgs1 a) {
   __shared__ __align__(16) unsigned char smem[rank_smem_bytes<KT, RT>()];
-  rank_tail_body<KT, RT>(a, smem);
+  rank_tail_body<KT, RT>(a, smem, blockIdx.x, gridDim.x);
 }
 
 template <int KT, int RT>

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(1024) void k_small(const typename Key<KT>::Raw* key
 template <int KT, int RT>
 __global__ __launch_bounds__(RANK_NT) void k_rsmall(TailArgs1 a) {
   __shared__ __align__(16) unsigned char smem[rank_smem_bytes<KT, RT>()];
-  rank_tail_body<KT, RT, true>(a, smem);
+  rank_tail_body<KT, RT, true>(a, smem, blockIdx.x, gridDim.x);
 }
 
 // ---- kernel 4: tail (cooperative) -----------------------------------------------------------
