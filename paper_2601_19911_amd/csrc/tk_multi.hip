@@ -29,14 +29,14 @@ __global__ __launch_bounds__(SAMP_NT) void k_msample(const SampArgs* __restrict_
   __shared__ SelScratch sc;
   const uint2 m = map[blockIdx.x];
   const SampArgs a = sa[m.x];
-  sample_body<KT, RT>(a, sc, m.y);
+  sample_body<KT, RT, false>(a, sc, m.y);
 }
 
 template <int KT, int RT>
 __global__ __launch_bounds__(FILT_NT) void k_msfinal(const FiltArgs* __restrict__ fa) {
   __shared__ SelScratch sc;
   const FiltArgs a = fa[blockIdx.x];
-  sample_final_body<KT, RT>(a, sc);
+  sample_final_body<KT, RT, false>(a, sc);
 }
 
 // Workgroup w streams the slices w, w + grid, w + 2 grid, ... of the block map.

@@ -41,13 +41,13 @@ namespace tk {
 template <int KT, int RT>
 __global__ __launch_bounds__(SAMP_NT) void k_sample(SampArgs a) {
   __shared__ SelScratch sc;
-  sample_body<KT, RT>(a, sc, blockIdx.x);
+  sample_body<KT, RT, true>(a, sc, blockIdx.x);
 }
 
 template <int KT, int RT>
 __global__ __launch_bounds__(FILT_NT) void k_sfinal(FiltArgs a) {
   __shared__ SelScratch sc;
-  sample_final_body<KT, RT>(a, sc);
+  sample_final_body<KT, RT, true>(a, sc);
 }
 
 template <int KT, int RT, int VEC, int UNR>

@@ -105,12 +105,14 @@ __device__ __forceinline__ uint64_t sample_hash(uint64_t c) {
 // select takes several per digit.
 constexpr uint32_t SMALL_R_MAX = 16;
 
-// The tournament pays off for 8-byte composites; with wider ones (two 64-bit
-// words per DPP move and compare) the radix select was faster on MI355X, by
-// 2-3 us a launch for one query and 2x for the batched launches.
-template <typename U, typename R>
+// The tournament shortens one query's latency for 8-byte composites.  With
+// wider ones (two 64-bit words per DPP move and compare) the radix select was
+// faster on MI355X by 2-3 us a launch, and in the batched launches, where
+// thousands of sample workgroups share the device and throughput counts, it
+// was faster for every width (float32: 88 + 13 against 106 + 18 us a batch).
+template <typename U, typename R, bool LATENCY>
 __device__ __forceinline__ bool small_r_tournament(uint32_t r1) {
-  return sizeof(U) + sizeof(R) == 8 && r1 <= SMALL_R_MAX;
+  return LATENCY && sizeof(U) + sizeof(R) == 8 && r1 <= SMALL_R_MAX;
 }
 
 // Wave-wide maximum through DPP lane moves (a few cycles each, where a
@@ -214,8 +216,9 @@ __device__ __forceinline__ void block_top_small(T (&v)[E], uint32_t r, uint64_t*
 // Each keeps the best r1 composites of its SAMPLE_PER_BLOCK sampled keys
 // (the union of these holds the sample's best r1); the next launch selects
 // the r1-th best of the union, so no workgroup hands data to another inside
-// a kernel.
-template <int KT, int RT>
+// a kernel.  LATENCY: a single query's launch (the tournament may serve
+// small r1), not a batched one.
+template <int KT, int RT, bool LATENCY>
 __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, uint32_t blk) {
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
@@ -253,7 +256,7 @@ __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, u
   }
   U* ck = static_cast<U*>(a.ck);
   R* cf = static_cast<R*>(a.cf);
-  if (small_r_tournament<U, R>(a.r1)) {
+  if (small_r_tournament<U, R, LATENCY>(a.r1)) {
     using T = typename Wide<U, R>::T;
     T v[E];
 #pragma unroll
@@ -334,7 +337,7 @@ __device__ __forceinline__ void stage_survivor(bool pass, U kk, R ff, SurvStage<
 // The threshold: the r1-th best of the sample workgroups' candidates (at most
 // SAMPLE_FINAL_MAX, held in registers), selected by one workgroup of FILT_NT
 // threads in a launch of its own and recorded in the query state.
-template <int KT, int RT>
+template <int KT, int RT, bool LATENCY>
 __device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch& sc) {
   using U = typename Key<KT>::U;
   using R = typename Rid<RT>::R;
@@ -360,7 +363,7 @@ __device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch&
   }
   U mk = (U)~(U)0;
   R mf = (R)~(R)0;
-  if (small_r_tournament<U, R>(a.r1)) {
+  if (small_r_tournament<U, R, LATENCY>(a.r1)) {
     // the r1-th entry of the tournament's list (padding 0 never ranks above
     // a candidate it is not equal to)
     using T = typename Wide<U, R>::T;

@@ -355,6 +355,32 @@ def test_exact_select_grid():
         tk.set_tuning(force_exact=2)
 
 
+def test_least_workspace_takes_the_grid_select():
+    """With tk_workspace_min_size bytes (no room for the sort's scratch) a query
+    without a usable sample takes path 5, with the full size path 9; both
+    equal the oracle."""
+    import torch
+    rng = np.random.default_rng(310)
+    for dtype, n, k, order in [("float32", 1 << 20, 600_000, "asc"), ("int64", 100_000, 70_000, "desc")]:
+        keys = inputgen.generate(KINDS[dtype], 310 + n, n)
+        rdt = np.uint64 if dtype == "int64" else np.uint32
+        rids = rng.permutation(n).astype(rdt)
+        exp = oracle.topk(keys, rids, k, order_code(order))
+        kc, rc = tk.key_code(keys.dtype), tk.rid_code(np.dtype(rdt))
+        assert tk.workspace_min_size(n, k, kc, rc) < tk.workspace_size(n, k, kc, rc)
+        for least, want in ((True, 5), (False, 9)):
+            ws = tk.new_workspace(n, k, kc, rc, least=least)
+            ok, orr = tk.topk(to_dev(keys), k, rowids=to_dev(rids), order=order, workspace=ws)
+            torch.cuda.synchronize()
+            info = tk.query_info(ws)
+            say(f"{dtype} n={n} k={k} {order} least={least}: {info}")
+            assert info["path"] == want and info["status"] == 0
+            assert_same(to_np(ok), to_np(orr), exp[0], exp[1], what=f"{dtype} n={n} least={least}")
+        with pytest.raises(tk.TopKError):
+            small = torch.zeros(tk.workspace_min_size(n, k, kc, rc) - 256, dtype=torch.uint8, device="cuda")
+            tk.topk(to_dev(keys), k, rowids=to_dev(rids), order=order, workspace=small)
+
+
 def test_wide_k_sampled():
     """K between N / 16 and N / 2 at N up to 2^20: the sampled path with the
     bucketed tail (path 6), equal to the oracle."""
