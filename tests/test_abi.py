@@ -117,3 +117,27 @@ def test_workspace_min_size():
                     assert full - least >= 2 * n * (kb[kt] + rb[rt])
                 else:
                     assert full == least, (n, k, kt, rt)
+
+
+def test_sort_argument_errors_before_device_work():
+    """tk_sort refuses bad arguments and sizes beyond its 32-bit digit counts
+    before touching the device (no GPU here; fake aligned pointers).  A handle
+    of its own, so that the argument types set here stay local."""
+    L = ctypes.CDLL(tk.LIB_PATH)
+    L.tk_sort_workspace_size.restype = ctypes.c_size_t
+    L.tk_sort_workspace_size.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
+    L.tk_sort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                          ctypes.c_void_p]
+    p = ctypes.c_void_p(1 << 20)
+    assert L.tk_sort_workspace_size(1000, 9, 0) == 0                       # bad key type
+    assert L.tk_sort(p, None, 1000, 0, 0, 2, p, p, p, 1 << 30, None) == -1  # bad order
+    assert L.tk_sort(None, None, 0, 0, 0, 0, None, None, None, 0, None) == 0  # n = 0: nothing
+    assert L.tk_sort(p, None, 1000, 0, 0, 0, p, None, p, 1 << 30, None) == -1  # out_rowids required
+    need = L.tk_sort_workspace_size(1000, 0, 0)
+    assert L.tk_sort(p, None, 1000, 0, 0, 0, p, p, p, need - 256, None) == -1  # small workspace
+    assert L.tk_sort(p, None, 1000, 0, 0, 0, p, p, ctypes.c_void_p((1 << 20) + 64), need, None) == -1
+    n = 1 << 32
+    big = L.tk_sort_workspace_size(n, 0, 1)
+    assert big >= 2 * n * 12
+    assert L.tk_sort(p, p, n, 0, 1, 0, p, p, p, big, None) == -4  # 2^32 pairs: TK_EUNSUPPORTED
