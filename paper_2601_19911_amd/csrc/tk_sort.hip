@@ -9,7 +9,8 @@
 // stable pass per key digit suffices (4 passes for 32-bit keys, 8 for 64-bit);
 // with explicit row-ids the row-id digits are sorted first.  Each pass is three
 // launches with no inter-workgroup waiting:
-//   k_sup    one workgroup per tile of 4096 pairs: the tile's digit counts
+//   k_sup    one workgroup per tile (8192 pairs of 8 bytes, 4096 wider ones):
+//            the tile's digit counts
 //   k_sscan  one workgroup per digit: exclusive scan of that digit's counts
 //            over the tiles, and the digit's total
 //   k_sdown  one workgroup per tile: stable rank of every pair inside the tile
@@ -18,7 +19,9 @@
 //            addresses at the digit's global offset
 // The first pass reads the caller's keys (encoding them) and row-ids (or
 // position), the last writes the caller's outputs (decoding the keys); the
-// passes between ping-pong through the workspace.
+// passes between ping-pong through the workspace.  A Top-K query that the
+// sample cannot serve runs the same passes with the last one writing only the
+// first K positions (topk_by_sort).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
