@@ -178,3 +178,39 @@ def test_periodic_column_and_misjudged_sample_full_size():
         tk.set_tuning(force_cap=-1, recover_min_log2=29)
     say(f"  normal {normal_ms:.3f} ms, recovered {recovered_ms:.3f} ms "
         f"({recovered_ms / normal_ms:.2f}x)")
+
+
+def test_largest_size_2p30_with_device_recovery():
+    """N = 2^30 float32 keys (4 GiB) with implicit row-ids, K = 1000 both
+    orders: past 2^29 keys the default tuning enqueues the cooperative exact
+    select after every sampled query (returning at once when the sample held),
+    and a forced misjudge is taken over by it; every result equals the oracle."""
+    import torch
+    n = 1 << 30
+    k = 1000
+    dev = torch.device("cuda:0")
+    keys = torch.empty(n, dtype=torch.float32, device=dev)
+    gen.device_fill(inputgen.KIND_U_F32, inputgen.config_seed(2, 70), n, keys.data_ptr(), n_total=n,
+                    stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    host = keys.cpu().numpy()
+    ws = tk.new_workspace(n, k, tk.TK_KEY_F32, tk.TK_RID_U32, device=dev)
+    exp = {}
+    try:
+        for order, force_cap, want in (("desc", -1, 3), ("asc", -1, 3), ("desc", 64, 4)):
+            tk.set_tuning(force_cap=force_cap)
+            say(f"2^30 float32 K={k} {order} force_cap={force_cap}")
+            ok, orr = tk.topk(keys, k, order=order, workspace=ws, rid_dtype=torch.uint32)
+            torch.cuda.synchronize()
+            info = tk.query_info(ws)
+            say(f"  path {info['path']} survivors {info['survivors']} status {info['status']}")
+            assert info["status"] == 0 and info["path"] == want
+            if order not in exp:
+                exp[order] = oracle.topk(host, None, k, oracle.DESC if order == "desc" else oracle.ASC,
+                                         rid_dtype=np.uint32)
+            ek, er = exp[order]
+            assert_same(to_np(ok), to_np(orr), ek, er, what=f"2^30 {order} force_cap={force_cap}")
+    finally:
+        tk.set_tuning(force_cap=-1)
+        del keys, ws
+        torch.cuda.empty_cache()
