@@ -111,8 +111,8 @@ constexpr uint32_t SMALL_R_MAX = 16;
 // thousands of sample workgroups share the device and throughput counts, it
 // was faster for every width (float32: 88 + 13 against 106 + 18 us a batch).
 template <typename U, typename R, bool LATENCY>
-__device__ __forceinline__ bool small_r_tournament(uint32_t r1) {
-  return LATENCY && sizeof(U) + sizeof(R) == 8 && r1 <= SMALL_R_MAX;
+constexpr bool tournament_shape() {
+  return LATENCY && sizeof(U) + sizeof(R) == 8;
 }
 
 // Wave-wide maximum through DPP lane moves (a few cycles each, where a
@@ -121,34 +121,23 @@ __device__ __forceinline__ bool small_r_tournament(uint32_t r1) {
 // and half-rows are uniform), then row 0 into row 1 and row 2 into row 3
 // (broadcast of lane 15) and rows 0-1 into rows 2-3 (broadcast of lane 31):
 // lane 63 ends up holding the maximum, which is read into every lane.
-template <int CTRL, int ROWS, typename T>
-__device__ __forceinline__ T dpp_max_step(T v) {
-  if constexpr (sizeof(T) == 8) {
-    const uint64_t w = ((uint64_t)dpp_move<CTRL, ROWS>((uint32_t)(v >> 32), (uint32_t)(v >> 32)) << 32) |
-                       (uint64_t)dpp_move<CTRL, ROWS>((uint32_t)v, (uint32_t)v);
-    return w > v ? (T)w : v;
-  } else {
-    T w = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      w |= (T)dpp_move<CTRL, ROWS>((uint32_t)(v >> (32 * q)), (uint32_t)(v >> (32 * q))) << (32 * q);
-    return w > v ? w : v;
-  }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_max_step(uint64_t v) {
+  const uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
+  const uint64_t w = ((uint64_t)dpp_move<CTRL, ROWS>(hi, hi) << 32) | dpp_move<CTRL, ROWS>(lo, lo);
+  return w > v ? w : v;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_max_wide(T v) {
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   v = dpp_max_step<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
   v = dpp_max_step<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
   v = dpp_max_step<0x141, 0xF>(v);  // row_half_mirror
   v = dpp_max_step<0x140, 0xF>(v);  // row_mirror
   v = dpp_max_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
   v = dpp_max_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  T r = 0;
-#pragma unroll
-  for (int q = 0; q < (int)sizeof(T) / 4; ++q)
-    r |= (T)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> (32 * q)), 63) << (32 * q);
-  return r;
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // odd-even transposition sort of a lane's E composites, best (largest) first
@@ -165,49 +154,39 @@ __device__ __forceinline__ void regs_sort_desc(T (&v)[E]) {
   }
 }
 
-// The r best composites of a workgroup of NT threads, each holding E of them
-// (padding: 0, the smallest composite), as a multiset: out_hi/out_lo (LDS, 64
-// words each) end up holding them in rank order for ranks < r.  Every thread
-// must call it (it holds a barrier); on return the list is visible to all.
-template <int NT, typename T, int E>
-__device__ __forceinline__ void block_top_small(T (&v)[E], uint32_t r, uint64_t* out_hi,
-                                                uint64_t* out_lo, uint64_t* lst_hi,
-                                                uint64_t* lst_lo) {
+// The r best 8-byte composites of a workgroup of NT threads, each holding E of
+// them (padding: 0, the smallest composite), as a multiset: out (LDS, 64
+// words) ends up holding them in rank order for ranks < r; lst is LDS of 64
+// words for the waves' lists.  Every thread must call it (it holds barriers);
+// on return the list is visible to all.
+template <int NT, int E>
+__device__ __forceinline__ void block_top_small(uint64_t (&v)[E], uint32_t r, uint64_t* out,
+                                                uint64_t* lst) {
   constexpr uint32_t NW = NT / 64;
   static_assert(NW * SMALL_R_MAX <= 64, "the waves' lists fit one wave");
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   regs_sort_desc(v);
   for (uint32_t i = 0; i < r; ++i) {
-    const T m = wave_max_wide(v[0]);
+    const uint64_t m = wave_max_u64(v[0]);
     const uint64_t hit = ballot(v[0] == m);
     if (lane == (uint32_t)__builtin_ctzll(hit)) {
 #pragma unroll
       for (int e = 0; e + 1 < E; ++e) v[e] = v[e + 1];
       v[E - 1] = 0;
     }
-    if (lane == 0) {
-      lst_hi[w * r + i] = sizeof(T) == 8 ? 0ull : (uint64_t)((__uint128_t)m >> 64);
-      lst_lo[w * r + i] = (uint64_t)m;
-    }
+    if (lane == 0) lst[w * r + i] = m;
   }
   __syncthreads();
   if (w == 0) {
     const uint32_t tot = NW * r;
-    auto at = [&](uint32_t j) -> T {
-      if constexpr (sizeof(T) == 8) return (T)lst_lo[j];
-      else return (T)(((__uint128_t)lst_hi[j] << 64) | (__uint128_t)lst_lo[j]);
-    };
-    const T c = lane < tot ? at(lane) : (T)0;
+    const uint64_t c = lane < tot ? lst[lane] : 0ull;
     uint32_t rank = 0;
 #pragma unroll 4
     for (uint32_t j = 0; j < tot; ++j) {
-      const T x = at(j);
+      const uint64_t x = lst[j];
       rank += (x > c || (x == c && j < lane)) ? 1u : 0u;
     }
-    if (lane < tot && rank < r) {
-      out_hi[rank] = (uint64_t)((__uint128_t)c >> 64);
-      out_lo[rank] = (uint64_t)c;
-    }
+    if (lane < tot && rank < r) out[rank] = c;
   }
   __syncthreads();
 }
@@ -256,20 +235,20 @@ __device__ __forceinline__ void sample_body(const SampArgs& a, SelScratch& sc, u
   }
   U* ck = static_cast<U*>(a.ck);
   R* cf = static_cast<R*>(a.cf);
-  if (small_r_tournament<U, R, LATENCY>(a.r1)) {
-    using T = typename Wide<U, R>::T;
-    T v[E];
+  if constexpr (tournament_shape<U, R, LATENCY>()) {
+    if (a.r1 <= SMALL_R_MAX) {
+      uint64_t v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = wide(k[e], f[e]);
-    uint64_t* sh = reinterpret_cast<uint64_t*>(sc.hist);  // the waves' lists: 64 + 64 words
-    block_top_small<NT, T, E>(v, a.r1, reinterpret_cast<uint64_t*>(sc.red),
-                              reinterpret_cast<uint64_t*>(sc.red2), sh, sh + 64);
-    if (threadIdx.x < a.r1) {
-      const T c = (T)(((__uint128_t)sc.red[threadIdx.x] << 64) | sc.red2[threadIdx.x]);
-      ck[(uint64_t)blk * a.r1 + threadIdx.x] = (U)(c >> (8 * sizeof(R)));
-      cf[(uint64_t)blk * a.r1 + threadIdx.x] = (R)c;
+      for (int e = 0; e < E; ++e) v[e] = wide(k[e], f[e]);
+      uint64_t* sh = reinterpret_cast<uint64_t*>(sc.hist);  // 128 words: list, then result
+      block_top_small<NT, E>(v, a.r1, sh + 64, sh);
+      if (threadIdx.x < a.r1) {
+        const uint64_t c = sh[64 + threadIdx.x];
+        ck[(uint64_t)blk * a.r1 + threadIdx.x] = (U)(c >> 32);
+        cf[(uint64_t)blk * a.r1 + threadIdx.x] = (R)c;
+      }
+      return;
     }
-    return;
   }
   U lmin = k[0];
 #pragma unroll
@@ -363,20 +342,23 @@ __device__ __forceinline__ void sample_final_body(const FiltArgs& a, SelScratch&
   }
   U mk = (U)~(U)0;
   R mf = (R)~(R)0;
-  if (small_r_tournament<U, R, LATENCY>(a.r1)) {
-    // the r1-th entry of the tournament's list (padding 0 never ranks above
-    // a candidate it is not equal to)
-    using T = typename Wide<U, R>::T;
-    T v[EF];
+  bool done = false;
+  if constexpr (tournament_shape<U, R, LATENCY>()) {
+    if (a.r1 <= SMALL_R_MAX) {
+      // the r1-th entry of the tournament's list (padding 0 never ranks above
+      // a candidate it is not equal to)
+      uint64_t v[EF];
 #pragma unroll
-    for (int e = 0; e < EF; ++e) v[e] = wide(k2[e], f2[e]);
-    uint64_t* sh = reinterpret_cast<uint64_t*>(sc.hist);
-    block_top_small<NT, T, EF>(v, a.r1, reinterpret_cast<uint64_t*>(sc.red),
-                               reinterpret_cast<uint64_t*>(sc.red2), sh, sh + 64);
-    const T c = (T)(((__uint128_t)sc.red[a.r1 - 1] << 64) | (__uint128_t)sc.red2[a.r1 - 1]);
-    mk = (U)(c >> (8 * sizeof(R)));
-    mf = (R)c;
-  } else {
+      for (int e = 0; e < EF; ++e) v[e] = wide(k2[e], f2[e]);
+      uint64_t* sh = reinterpret_cast<uint64_t*>(sc.hist);  // 128 words: list, then result
+      block_top_small<NT, EF>(v, a.r1, sh + 64, sh);
+      const uint64_t c = sh[64 + a.r1 - 1];
+      mk = (U)(c >> 32);
+      mf = (R)c;
+      done = true;
+    }
+  }
+  if (!done) {
     const U base = block_min<NT, U>(cmin, sc);
     const RegElems<U, R, EF> el{k2, f2, nv};
     const Sel<U, R> s = block_radix_select<NT, U, R>(el, a.r1, base, sc);
