@@ -31,7 +31,7 @@ struct SamplePlan {
 };
 
 struct Tuning {
-  double sample_sigma = 3.0;   // safety margin on the sample rank, in std devs
+  double sample_sigma = 4.0;   // safety margin on the sample rank, in std devs
   double cap_sigma = 6.0;      // survivor capacity margin, in std devs
   uint32_t max_sample_log2 = 20;
   uint32_t min_sample_log2 = 11;

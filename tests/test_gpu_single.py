@@ -447,18 +447,18 @@ def test_read_probe():
 
 # ---- the sampled threshold, checked from the outside -------------------------------------------
 
-def _plan_sample(n, k):
+def _plan_sample(n, k, sigma=4.0):
     """(S, r1) of the sampled path at the default tuning: the largest sample of
     2^11..2^20 keys (at least 16 keys per sampled key) whose rank r1 =
-    ceil(m + 3 sqrt(m) + 3), m = K S / N, keeps r1 x S / 2048 candidates within
-    2048 for the final select."""
+    ceil(m + sigma sqrt(m) + 3), m = K S / N, sigma = 4, keeps r1 x S / 2048
+    candidates within 2048 for the final select."""
     import math
     for lg in range(20, 10, -1):
         s = 1 << lg
         if s * 16 > n:
             continue
         m = float(k) * float(s) / float(n)
-        r1 = math.ceil(m + 3.0 * math.sqrt(m) + 3.0)
+        r1 = math.ceil(m + sigma * math.sqrt(m) + 3.0)
         if r1 <= 2048 and r1 * (s // 2048) <= 2048:
             return s, r1
     return None
@@ -499,11 +499,11 @@ def _images(keys, order):
 
 
 @pytest.mark.parametrize("dtype,n,k,order,explicit", [
-    ("float32", (1 << 24) + 12345, 100, "desc", False),   # r1 = 9: the tournament
-    ("float32", (1 << 24) + 12345, 5000, "asc", True),    # r1 = 36: the radix select
-    ("int64", (1 << 22) + 7, 10, "desc", False),          # r1 = 6, 16-byte composites
-    ("float64", 1 << 22, 1000, "asc", False),             # r1 = 31
-    ("int32", 1 << 22, 1, "desc", True),                  # r1 = 4, heavy ties
+    ("float32", (1 << 24) + 12345, 100, "desc", False),   # r1 = 10: the tournament
+    ("float32", (1 << 24) + 12345, 5000, "asc", True),    # r1 = 41: the radix select
+    ("int64", (1 << 22) + 7, 10, "desc", False),          # r1 = 7, 16-byte composites
+    ("float64", 1 << 22, 1000, "asc", False),             # r1 = 35
+    ("int32", 1 << 22, 1, "desc", True),                  # r1 = 5, heavy ties
 ])
 def test_sampled_threshold_is_the_samples_rank(dtype, n, k, order, explicit):
     """The threshold is the r1-th best composite of the stratified sample and the
