@@ -177,7 +177,9 @@ int tk_set_tuning(const tk_tuning* t);
 typedef struct tk_plan tk_plan;
 typedef struct {
   uint32_t tile_keys;        /* keys each filter workgroup streams; 0: 32768 (>= 4096) */
-  uint32_t filter_grid;      /* filter workgroups, each looping over the slices; 0: one per slice */
+  uint32_t filter_grid;      /* filter workgroups, each looping over the slices (the next
+                                slice's record prefetched); 0: three per CU; 0xFFFFFFFF (any
+                                count >= the slices): one per slice */
   uint32_t min_sample_log2;  /* smallest sample; queries under 16x it take the exact select; 0: 12 */
   uint32_t max_sample_log2;  /* largest sample; 0: 14 */
   double sample_sigma;       /* margin of the sampled threshold; 0: the process default (4) */

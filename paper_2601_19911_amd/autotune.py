@@ -11,8 +11,8 @@ efficiency and survivor traffic:
                      survivor buffers and decide how often the exact fallback
                      (a second pass over a query) runs;
 * ``cap_sigma``      the survivor buffers' margin over the expected count;
-* ``filter_grid``    filter workgroups looping over all the slices (0: one
-                     workgroup per slice).
+* ``filter_grid``    filter workgroups looping over all the slices (0: three
+                     per CU; 0xFFFFFFFF: one workgroup per slice).
 
 ``tune()`` times every candidate on the caller's own batch (each run is a
 full, exact ``tk_plan_launch``; the tuner never changes a result, only how
@@ -32,15 +32,16 @@ import time
 import numpy as np
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_plans.json")
+ONE_PER_SLICE = 0xFFFFFFFF  # filter_grid: one filter workgroup per slice
 
 
-def candidates(key_bytes: int, quick: bool = False, cus: int = 256):
+def candidates(key_bytes: int, quick: bool = False):
     """Parameter sets to try, as dicts of tk_plan_params fields."""
     tiles = ([1 << 14, 1 << 15, 1 << 16, 1 << 17] if key_bytes == 8 else
              [1 << 15, 1 << 16, 1 << 17, 1 << 18])
-    sigmas = [(3.0, 14), (2.0, 14), (3.0, 16), (3.0, 20)]
+    sigmas = [(4.0, 14), (3.0, 14), (4.0, 16), (4.0, 20)]
     caps = [6.0, 4.0]
-    grids = [0, 3 * cus]
+    grids = [0, ONE_PER_SLICE]
     if quick:
         tiles, sigmas, caps, grids = tiles[1:3], sigmas[:2], caps[:1], grids
     return [{"tile_keys": t, "sample_sigma": s, "max_sample_log2": m, "cap_sigma": c,
@@ -88,8 +89,7 @@ def tune(offsets, ks, orders, keys, rid_dtype=None, reps: int = 3, quick: bool =
     s = stream or torch.cuda.Stream()
     table = []
     best = None
-    cus = torch.cuda.get_device_properties(keys.device).multi_processor_count
-    for p in candidates(keys.element_size(), quick, cus):
+    for p in candidates(keys.element_size(), quick):
         plan = Plan(offsets, ks, orders, key_dtype=keys.dtype, rid_dtype=rid_dtype, stream=s, **p)
         ok, orr = plan.alloc_outputs()
         torch.cuda.synchronize()

@@ -39,16 +39,31 @@ __global__ __launch_bounds__(FILT_NT) void k_msfinal(const FiltArgs* __restrict_
   sample_final_body<KT, RT, false>(a, sc);
 }
 
-// Workgroup w streams the slices w, w + grid, w + 2 grid, ... of the block map.
+// Workgroup w streams the slices w, w + grid, w + 2 grid, ... of the block map;
+// the next slice's map entry and record are loaded before the current slice
+// is streamed, so that looking them up adds no round trip between slices.
 template <int KT, int RT>
 __global__ __launch_bounds__(FILT_NT) void k_mfilter(const FiltArgs* __restrict__ fa,
                                                      const uint2* __restrict__ map, uint32_t n) {
   __shared__ SurvStage<typename Key<KT>::U, typename Rid<RT>::R> st;
-  for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
-    const uint2 m = map[it];
-    const FiltArgs a = fa[m.x];
+  uint32_t it = blockIdx.x;
+  if (it >= n) return;
+  uint2 m = map[it];
+  FiltArgs a = fa[m.x];
+  while (true) {
+    const uint32_t nx = it + gridDim.x;
+    uint2 mn = m;
+    FiltArgs an = a;
+    if (nx < n) {
+      mn = map[nx];
+      an = fa[mn.x];
+    }
     filter_body<KT, RT, 16 / sizeof(typename Key<KT>::Raw), 4>(a, m.y, st);
+    if (nx >= n) break;
     __syncthreads();  // the stage is reused by the next slice
+    it = nx;
+    m = mn;
+    a = an;
   }
 }
 
@@ -228,7 +243,17 @@ void enqueue_typed(const MLaunch& m, hipStream_t st) {
   if (m.n_samp) hipLaunchKernelGGL((k_msample<KT, RT>), dim3(m.n_samp), dim3(SAMP_NT), 0, st, m.sa, m.smap);
   if (m.n_fa) hipLaunchKernelGGL((k_msfinal<KT, RT>), dim3(m.n_fa), dim3(FILT_NT), 0, st, m.fa);
   profile_mark(st, true);
-  const uint32_t fg = m.filt_grid && m.filt_grid < m.n_filt ? m.filt_grid : m.n_filt;
+  // 0: three workgroups per CU (the streaming pass's occupancy), each looping
+  // over slices with the next one's record prefetched; measured 5 % faster at
+  // C3 than one workgroup per slice, which pays the record lookups of every
+  // slice before its first load
+  uint32_t fg = m.filt_grid;
+  if (fg == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    fg = 3u * (uint32_t)device_cus(dev);
+  }
+  if (fg > m.n_filt) fg = m.n_filt;
   if (m.n_filt) hipLaunchKernelGGL((k_mfilter<KT, RT>), dim3(fg), dim3(FILT_NT), 0, st, m.fa, m.fmap, m.n_filt);
   profile_mark(st, false);
   if (m.n_tail)

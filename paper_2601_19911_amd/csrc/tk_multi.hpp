@@ -72,7 +72,8 @@ struct MLaunch {
   const TailArgs1* ta = nullptr;
   const uint32_t* tq = nullptr;  // query index of each tail record
   uint32_t n_tail = 0;
-  uint32_t filt_grid = 0;  // filter workgroups looping over the slices; 0: one per slice
+  uint32_t filt_grid = 0;  // filter workgroups looping over the slices; 0: three per CU
+                           // (at least the slice count: one per slice)
   // per-query completion stamps (device clock), or nullptr: stamps[0] is the
   // launch's start, stamps[1 + i] the end of query i's tail
   unsigned long long* stamps = nullptr;
