@@ -704,11 +704,13 @@ def suite_join(a):
     """Build 2^b int32/int64 keys (uniform; int64 all distinct), probe 2^26
     foreign keys drawn from twice the build's index range (hit rate 1/2),
     row-ids implicit (uint32).  Times the build and the probe with events on
-    the launch stream; the first probe's pairs are compared with the oracle."""
+    the launch stream, with and without the bloom prefilter; the first probe's
+    pairs are compared with the oracle."""
     torch = _torch()
     import inputgen
     import oracle
     from inputgen import native as gen
+    import paper_2601_19911_amd as tk
     from paper_2601_19911_amd.join import join_build, join_probe
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream()
@@ -722,43 +724,53 @@ def suite_join(a):
         bk_h = gen.host_fill(bkind, seed, nb)
         pk_h = gen.host_fill(pkind, seed, np_, n_total=2 * nb)
         bk, pk = torch.from_numpy(bk_h).to(dev), torch.from_numpy(pk_h).to(dev)
-        t = join_build(bk)
-        op, ob, cnt = join_probe(t, pk)
-        torch.cuda.synchronize()
-        m = int(cnt.view(torch.int64).item())
-        if m > op.numel():
-            op, ob, cnt = join_probe(t, pk, capacity=m)
+        expect = None
+        for bloom in (True, False) if a.join_bloom == 0 else (a.join_bloom == 1,):
+            tk.set_tuning(join_bloom=1 if bloom else 2)
+            t = join_build(bk)
+            op, ob, cnt = join_probe(t, pk)
             torch.cuda.synchronize()
-        ok = None
-        if not a.no_check:
-            gp, gb = dev_view_np(op)[:m].astype(np.uint64), dev_view_np(ob)[:m].astype(np.uint64)
-            o = np.lexsort((gb, gp))
-            ep, eb = oracle.join(bk_h, None, pk_h, None)
-            ok = bool(gp.shape == ep.shape and np.array_equal(gp[o], ep) and np.array_equal(gb[o], eb))
-        bt, pt = [], []
-        for _ in range(a.reps):
-            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-            e0.record(st)
-            t = join_build(bk, table=t.buf)
-            e1.record(st)
-            join_probe(t, pk, capacity=op.numel(), out_probe=op, out_build=ob, count=cnt)
-            e2.record(st)
-            torch.cuda.synchronize()
-            bt.append(e0.elapsed_time(e1))
-            pt.append(e1.elapsed_time(e2))
-        kb = np.dtype(dt).itemsize
-        slot_b = 16 if dt == np.int64 else 8
-        probe_ms = float(np.median(pt))
-        # bytes per probe: the key, one slot, and the matched pairs written
-        alg = np_ * (kb + slot_b) + m * 8
-        emit({"suite": "join", "key_dtype": np.dtype(dt).name, "n_build": nb, "n_probe": np_,
-              "hit_rate_expected": 0.5, "matches": m, "table_bytes": int(t.buf.numel()),
-              "slots": t.slots, "build_ms": float(np.median(bt)), "probe_ms": probe_ms,
-              "probe_ms_p95": pct(pt, 95), "probes_per_s": np_ / (probe_ms * 1e-3),
-              "build_keys_per_s": nb / (float(np.median(bt)) * 1e-3),
-              "alg_bytes_per_probe": alg / np_, "probe_alg_gbs": alg / (probe_ms * 1e-3) / 1e9,
-              "probe_frac_of_peak": alg / (probe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-              "equal_to_oracle": ok, "reps": a.reps})
+            m = int(cnt.view(torch.int64).item())
+            if m > op.numel():
+                op, ob, cnt = join_probe(t, pk, capacity=m)
+                torch.cuda.synchronize()
+            ok = None
+            if not a.no_check:
+                gp = dev_view_np(op)[:m].astype(np.uint64)
+                gb = dev_view_np(ob)[:m].astype(np.uint64)
+                o = np.lexsort((gb, gp))
+                if expect is None:
+                    expect = oracle.join(bk_h, None, pk_h, None)
+                ep, eb = expect
+                ok = bool(gp.shape == ep.shape and np.array_equal(gp[o], ep) and
+                          np.array_equal(gb[o], eb))
+            bt, pt = [], []
+            for _ in range(a.reps):
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                e0.record(st)
+                t = join_build(bk, table=t.buf)
+                e1.record(st)
+                join_probe(t, pk, capacity=op.numel(), out_probe=op, out_build=ob, count=cnt)
+                e2.record(st)
+                torch.cuda.synchronize()
+                bt.append(e0.elapsed_time(e1))
+                pt.append(e1.elapsed_time(e2))
+            kb = np.dtype(dt).itemsize
+            slot_b = 16 if dt == np.int64 else 8
+            probe_ms = float(np.median(pt))
+            # bytes per probe: the key, one slot, and the matched pairs written
+            alg = np_ * (kb + slot_b) + m * 8
+            emit({"suite": "join", "key_dtype": np.dtype(dt).name, "n_build": nb, "n_probe": np_,
+                  "bloom": bloom, "hit_rate_expected": 0.5, "matches": m,
+                  "table_bytes": int(t.buf.numel()), "slots": t.slots,
+                  "build_ms": float(np.median(bt)), "probe_ms": probe_ms,
+                  "probe_ms_p95": pct(pt, 95), "probes_per_s": np_ / (probe_ms * 1e-3),
+                  "build_keys_per_s": nb / (float(np.median(bt)) * 1e-3),
+                  "alg_bytes_per_probe": alg / np_,
+                  "probe_alg_gbs": alg / (probe_ms * 1e-3) / 1e9,
+                  "probe_frac_of_peak": alg / (probe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "equal_to_oracle": ok, "reps": a.reps})
+        tk.set_tuning(join_bloom=1)
 
 
 def main():
@@ -794,6 +806,8 @@ def main():
     ap.add_argument("--fit-log2", type=int, default=20, help="gate: largest N of the model fit")
     ap.add_argument("--fit-lo-log2", type=int, default=10, help="gate: smallest N of the model fit")
     ap.add_argument("--join-probe-log2", type=int, default=26, help="join: probe keys (log2)")
+    ap.add_argument("--join-bloom", type=int, default=0, choices=[0, 1, 2],
+                    help="join: 1 with the bloom prefilter, 2 without, 0 both")
     ap.add_argument("--tune", action="store_true", help="c3: also autotune the plan and time it")
     ap.add_argument("--tune-cache-dir", type=str, default="",
                     help="c3: where the tuned parameters are stored (default: the package's cache)")

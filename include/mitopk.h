@@ -155,6 +155,8 @@ typedef struct {
                                 once unless the sample misjudged (the launch itself costs
                                 about 21 us per query); smaller ones (or all, when < 0) fall
                                 back to one workgroup's select over the input */
+  int32_t join_bloom;        /* 1: join tables are built with the bloom prefilter (default),
+                                2: without (tables built before keep theirs) */
 } tk_tuning;
 int tk_set_tuning(const tk_tuning* t);
 
@@ -443,11 +445,15 @@ typedef struct {
   uint64_t slots;        /* hash slots: a power of two >= 2 * n_build (load <= 1/2) */
   int32_t key_type;      /* TK_KEY_I32 or TK_KEY_I64 */
   int32_t rid_type;      /* build row-id type, also the type of out_build_rowids */
+  uint64_t bloom_words;  /* 64-bit words of the bloom prefilter (slots / 16), or 0 when the
+                            table was built without it (tk_tuning.join_bloom); probes read
+                            a key's word first and skip the slots when it rules the key out */
 } tk_join_table;
 
 /* Device bytes of the table for n_build pairs (0 on a bad type or n_build > 2^31):
  * a 256-byte header, the slots (8 bytes each for int32 keys with uint32 row-ids,
- * 16 bytes otherwise) and room for n_build row-ids. */
+ * 16 bytes otherwise), room for n_build row-ids and the bloom prefilter's
+ * slots / 2 bytes (reserved whether or not the build fills it). */
 size_t tk_join_table_size(uint64_t n_build, int key_type, int rid_type);
 /* Builds the table from n_build build pairs (stream-ordered, asynchronous).
  *   keys     device array of n_build int32/int64 keys

@@ -38,7 +38,7 @@ class tk_tuning(ctypes.Structure):
                 ("max_sample_log2", ctypes.c_int32), ("filter_grid", ctypes.c_int32),
                 ("force_cap", ctypes.c_int64), ("force_exact", ctypes.c_int32),
                 ("tail_mode", ctypes.c_int32), ("filter_unroll", ctypes.c_int32),
-                ("recover_min_log2", ctypes.c_int32)]
+                ("recover_min_log2", ctypes.c_int32), ("join_bloom", ctypes.c_int32)]
 
 
 def lib():
@@ -47,6 +47,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise TopKError(f"{LIB_PATH} is missing: build it with python -m paper_2601_19911_amd.build")
+        # torch first: its wheel bundles a HIP runtime with the soname the
+        # library links (libamdhip64.so.7), and whichever loads first serves
+        # the whole process; the library must run on the runtime that owns
+        # torch's device memory and streams
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
         L.tk_workspace_size.argtypes = [u64, u64, i32, i32]
@@ -319,14 +324,15 @@ def query_info(workspace) -> dict:
 
 
 def set_tuning(sample_sigma=0.0, cap_sigma=0.0, max_sample_log2=0, filter_grid=0, force_cap=0,
-               force_exact=0, tail_mode=0, filter_unroll=0, recover_min_log2=0):
+               force_exact=0, tail_mode=0, filter_unroll=0, recover_min_log2=0, join_bloom=0):
     """Process-wide knobs; 0 leaves a field unchanged (force_cap=-1,
-    force_exact=2, tail_mode=1, filter_grid=-1 and recover_min_log2=29 restore
-    the defaults; tail_mode=2 makes one workgroup select and sort the
-    survivors; filter_unroll is 4 or 8; recover_min_log2=-1 leaves every
-    misjudged sample to one workgroup)."""
+    force_exact=2, tail_mode=1, filter_grid=-1, recover_min_log2=29 and
+    join_bloom=1 restore the defaults; tail_mode=2 makes one workgroup select
+    and sort the survivors; filter_unroll is 4 or 8; recover_min_log2=-1
+    leaves every misjudged sample to one workgroup; join_bloom=2 builds join
+    tables without the bloom prefilter)."""
     t = tk_tuning(sample_sigma, cap_sigma, max_sample_log2, filter_grid, force_cap, force_exact,
-                  tail_mode, filter_unroll, recover_min_log2)
+                  tail_mode, filter_unroll, recover_min_log2, join_bloom)
     check(lib().tk_set_tuning(ctypes.byref(t)), "tk_set_tuning")
 
 

@@ -5,7 +5,7 @@
 // which the host late-materializes.
 //
 // Table (caller-owned device buffer, see tk_join_table_size):
-//   [header, 256 B][slots: S slots of (key word, row-id word)][side list]
+//   [header, 256 B][slots: S slots of (key word, row-id word)][side list][bloom words]
 // S is a power of two >= 2 * n_build, so the load factor is at most 1/2.  Open
 // addressing with linear probing; duplicate build keys take one slot each, so
 // a probe walks its run until an empty slot and returns every equal key.  The
@@ -14,6 +14,13 @@
 // that key reads in full.  The header counts the side list and records whether
 // any build key occurs twice; without duplicates a probe stops at its first
 // hit.
+//
+// The bloom prefilter (sec. III-B names it as an option of the matching
+// primitive): S / 16 words of 64 bits (8-16 bits per build key), each hashed
+// key setting 3 bits of one word.  A probe key reads its word first and walks
+// the slots only when all 3 bits are set, so most probes of absent keys touch
+// one word of a small array (L2- or last-level-cache resident) instead of
+// the slot lines in HBM.
 //
 // Memory behaviour on MI355X: the probe is bound by random reads of slots
 // (one slot usually, in one 128-byte line; adjacent slots of a run share it).
@@ -24,6 +31,7 @@
 
 #include "mitopk.h"
 #include "tk_device.hpp"
+#include "tk_internal.hpp"
 
 namespace {
 
@@ -66,6 +74,21 @@ __device__ __forceinline__ uint64_t slot_of(uint64_t x, uint32_t shift) {
   return x >> shift;
 }
 
+// Bloom word and bits of a key: the 64-bit finalizer of MurmurHash3 (Appleby),
+// a hash independent of the slot's; the top bits pick the word, three 6-bit
+// fields of the low bits the bits inside it.
+__device__ __forceinline__ uint64_t bloom_hash(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xFF51AFD7ED558CCDull;
+  x ^= x >> 33;
+  x *= 0xC4CEB9FE1A85EC53ull;
+  x ^= x >> 33;
+  return x;
+}
+__device__ __forceinline__ unsigned long long bloom_bits(uint64_t z) {
+  return (1ull << (z & 63)) | (1ull << ((z >> 6) & 63)) | (1ull << ((z >> 12) & 63));
+}
+
 uint64_t slots_for(uint64_t n_build) {
   uint64_t s = 64;
   while (s < 2 * n_build) s <<= 1;
@@ -78,18 +101,31 @@ bool wide_slot(int key_type, int rid_type) {
 
 uint64_t round256(uint64_t b) { return (b + 255) & ~255ull; }
 
+uint64_t bloom_words_for(uint64_t nslots) { return nslots / 16; }
+
+// Byte offsets of the side list and the bloom words inside the table.
+uint64_t side_offset(uint64_t nslots, uint64_t slot_b) {
+  return JOIN_HEADER_BYTES + round256(nslots * slot_b);
+}
+uint64_t bloom_offset(uint64_t n_build, uint64_t nslots, uint64_t slot_b, uint64_t rid_b) {
+  return side_offset(nslots, slot_b) + round256((n_build ? n_build : 1) * rid_b);
+}
+
 size_t table_bytes_for(uint64_t n_build, int key_type, int rid_type) {
   const uint64_t slot_b = wide_slot(key_type, rid_type) ? 16 : 8;
   const uint64_t rid_b = rid_type == TK_RID_U64 ? 8 : 4;
-  return (size_t)(JOIN_HEADER_BYTES + round256(slots_for(n_build) * slot_b) +
-                  round256((n_build ? n_build : 1) * rid_b));
+  const uint64_t nslots = slots_for(n_build);
+  return (size_t)(bloom_offset(n_build, nslots, slot_b, rid_b) +
+                  round256(bloom_words_for(nslots) * 8));
 }
 
 // ---- build ------------------------------------------------------------------------------
 
 template <typename W>
 __global__ __launch_bounds__(256) void k_jfill(Slot<W>* __restrict__ slots, uint64_t nslots,
-                                               W empty, JoinHeader* __restrict__ hdr) {
+                                               W empty, JoinHeader* __restrict__ hdr,
+                                               unsigned long long* __restrict__ bloom,
+                                               uint64_t nwords) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     hdr->side_count = 0;
     hdr->dup = 0;
@@ -101,6 +137,8 @@ __global__ __launch_bounds__(256) void k_jfill(Slot<W>* __restrict__ slots, uint
     s.rid = 0;
     slots[i] = s;
   }
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride)
+    bloom[i] = 0ull;
 }
 
 template <int KT, typename W, typename BR>
@@ -108,7 +146,9 @@ __global__ __launch_bounds__(256) void k_jbuild(const typename JKey<KT>::Raw* __
                                                 const BR* __restrict__ rids, uint64_t n,
                                                 Slot<W>* __restrict__ slots, uint64_t mask,
                                                 uint32_t shift, BR* __restrict__ side,
-                                                JoinHeader* __restrict__ hdr) {
+                                                JoinHeader* __restrict__ hdr,
+                                                unsigned long long* __restrict__ bloom,
+                                                uint32_t bshift) {
   using Raw = typename JKey<KT>::Raw;
   constexpr Raw EMPTY = JKey<KT>::EMPTY;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -119,6 +159,10 @@ __global__ __launch_bounds__(256) void k_jbuild(const typename JKey<KT>::Raw* __
       const unsigned long long at = atomicAdd(&hdr->side_count, 1ull);
       side[at] = r;
       continue;
+    }
+    if (bloom) {
+      const uint64_t z = bloom_hash((uint64_t)key);
+      atomicOr(&bloom[z >> bshift], bloom_bits(z));
     }
     const W w = (W)key;
     uint64_t p = slot_of((uint64_t)key, shift);
@@ -147,6 +191,8 @@ struct ProbeArgs {
   uint32_t shift;
   const BR* side;
   const JoinHeader* hdr;
+  const unsigned long long* bloom;  // null: no prefilter
+  uint32_t bshift;                  // 64 - log2(bloom words)
   PR* out_p;
   BR* out_b;
   uint64_t cap;
@@ -254,6 +300,17 @@ __global__ __launch_bounds__(PROBE_NT) void k_jprobe(ProbeArgs<W, BR, PR> a) {
       side[q] = j < a.n && key[q] == EMPTY;
       act[q] = j < a.n && key[q] != EMPTY;
     }
+    if (a.bloom) {  // keys whose 3 bits are not all set are absent from the build side
+      unsigned long long word[PROBE_PER], need[PROBE_PER];
+#pragma unroll
+      for (int q = 0; q < PROBE_PER; ++q) {
+        const uint64_t z = bloom_hash((uint64_t)key[q]);
+        need[q] = bloom_bits(z);
+        word[q] = act[q] ? a.bloom[z >> a.bshift] : 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < PROBE_PER; ++q) act[q] = act[q] && (word[q] & need[q]) == need[q];
+    }
 #pragma unroll
     for (int q = 0; q < PROBE_PER; ++q) {
       pos[q] = slot_of((uint64_t)key[q], a.shift);
@@ -321,21 +378,37 @@ int cus() {
   return v;
 }
 
+uint32_t log2_of(uint64_t pow2) {
+  uint32_t lg = 0;
+  while ((1ull << lg) < pow2) ++lg;
+  return lg;
+}
+
+unsigned long long* bloom_of(const tk_join_table* t, void* table, uint64_t nslots, uint64_t slot_b,
+                             uint64_t rid_b) {
+  return reinterpret_cast<unsigned long long*>(static_cast<char*>(table) +
+                                               bloom_offset(t->n_build, nslots, slot_b, rid_b));
+}
+
+// nwords: bloom words to fill (0: the table is built without the prefilter)
 template <int KT, typename W, typename BR>
 int build_t(const void* keys, const void* rids, uint64_t n, void* table, uint64_t nslots,
-            hipStream_t st) {
+            uint64_t nwords, hipStream_t st) {
   auto* hdr = static_cast<JoinHeader*>(table);
   auto* slots = reinterpret_cast<Slot<W>*>(static_cast<char*>(table) + JOIN_HEADER_BYTES);
-  auto* side = reinterpret_cast<BR*>(reinterpret_cast<char*>(slots) + round256(nslots * sizeof(Slot<W>)));
+  auto* side = reinterpret_cast<BR*>(static_cast<char*>(table) + side_offset(nslots, sizeof(Slot<W>)));
+  auto* bloom = nwords ? reinterpret_cast<unsigned long long*>(
+                             static_cast<char*>(table) +
+                             bloom_offset(n, nslots, sizeof(Slot<W>), sizeof(BR)))
+                       : nullptr;
   const int c = cus();
   hipLaunchKernelGGL(k_jfill<W>, dim3(launch_grid(c, nslots, 256 * 8, 8)), dim3(256), 0, st, slots,
-                     nslots, (W)JKey<KT>::EMPTY, hdr);
+                     nslots, (W)JKey<KT>::EMPTY, hdr, bloom, nwords);
   if (n) {
-    uint32_t lg = 0;
-    while ((1ull << lg) < nslots) ++lg;
     hipLaunchKernelGGL((k_jbuild<KT, W, BR>), dim3(launch_grid(c, n, 256 * 4, 16)), dim3(256), 0, st,
                        static_cast<const typename JKey<KT>::Raw*>(keys), static_cast<const BR*>(rids),
-                       n, slots, nslots - 1, 64u - lg, side, hdr);
+                       n, slots, nslots - 1, 64u - log2_of(nslots), side, hdr, bloom,
+                       nwords ? 64u - log2_of(nwords) : 0u);
   }
   return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
 }
@@ -345,22 +418,22 @@ int probe_t(const tk_join_table* t, const void* keys, const void* rids, uint64_t
             void* out_b, uint64_t cap, uint64_t* d_count, hipStream_t st) {
   auto* hdr = static_cast<const JoinHeader*>(t->table);
   auto* slots = reinterpret_cast<const Slot<W>*>(static_cast<const char*>(t->table) + JOIN_HEADER_BYTES);
-  auto* side = reinterpret_cast<const BR*>(reinterpret_cast<const char*>(slots) +
-                                           round256(t->slots * sizeof(Slot<W>)));
+  auto* side = reinterpret_cast<const BR*>(static_cast<const char*>(t->table) +
+                                           side_offset(t->slots, sizeof(Slot<W>)));
   auto* cnt = reinterpret_cast<unsigned long long*>(d_count);
   hipLaunchKernelGGL(k_jclear, dim3(1), dim3(1), 0, st, cnt);
   if (n) {
-    uint32_t lg = 0;
-    while ((1ull << lg) < t->slots) ++lg;
     ProbeArgs<W, BR, PR> a;
     a.keys = keys;
     a.rids = static_cast<const PR*>(rids);
     a.n = n;
     a.slots = slots;
     a.mask = t->slots - 1;
-    a.shift = 64u - lg;
+    a.shift = 64u - log2_of(t->slots);
     a.side = side;
     a.hdr = hdr;
+    a.bloom = t->bloom_words ? bloom_of(t, t->table, t->slots, sizeof(Slot<W>), sizeof(BR)) : nullptr;
+    a.bshift = t->bloom_words ? 64u - log2_of(t->bloom_words) : 0u;
     a.out_p = static_cast<PR*>(out_p);
     a.out_b = static_cast<BR*>(out_b);
     a.cap = (out_p && out_b) ? cap : 0;
@@ -402,16 +475,20 @@ extern "C" int tk_join_build(const void* keys, const void* rowids, uint64_t n_bu
   if (((uintptr_t)table & 255) != 0) return TK_EINVAL;
   if (table_bytes < table_bytes_for(n_build, key_type, rid_type)) return TK_EINVAL;
   const uint64_t nslots = slots_for(n_build);
+  const uint64_t nwords = tk::current_tuning().join_bloom ? bloom_words_for(nslots) : 0;
   hipStream_t st = (hipStream_t)stream;
   int rc;
   if (key_type == TK_KEY_I32 && rid_type == TK_RID_U32)
-    rc = build_t<TK_KEY_I32, uint32_t, uint32_t>(keys, rowids, n_build, table, nslots, st);
+    rc = build_t<TK_KEY_I32, uint32_t, uint32_t>(keys, rowids, n_build, table, nslots, nwords, st);
   else if (key_type == TK_KEY_I32)
-    rc = build_t<TK_KEY_I32, unsigned long long, unsigned long long>(keys, rowids, n_build, table, nslots, st);
+    rc = build_t<TK_KEY_I32, unsigned long long, unsigned long long>(keys, rowids, n_build, table,
+                                                                     nslots, nwords, st);
   else if (rid_type == TK_RID_U32)
-    rc = build_t<TK_KEY_I64, unsigned long long, uint32_t>(keys, rowids, n_build, table, nslots, st);
+    rc = build_t<TK_KEY_I64, unsigned long long, uint32_t>(keys, rowids, n_build, table, nslots,
+                                                           nwords, st);
   else
-    rc = build_t<TK_KEY_I64, unsigned long long, unsigned long long>(keys, rowids, n_build, table, nslots, st);
+    rc = build_t<TK_KEY_I64, unsigned long long, unsigned long long>(keys, rowids, n_build, table,
+                                                                     nslots, nwords, st);
   if (rc != TK_OK) return rc;
   out->table = table;
   out->table_bytes = table_bytes;
@@ -419,6 +496,7 @@ extern "C" int tk_join_build(const void* keys, const void* rowids, uint64_t n_bu
   out->slots = nslots;
   out->key_type = key_type;
   out->rid_type = rid_type;
+  out->bloom_words = nwords;
   return TK_OK;
 }
 
@@ -432,7 +510,8 @@ extern "C" int tk_join_probe(const tk_join_table* t, const void* keys, const voi
       (rid_type != TK_RID_U32 && rid_type != TK_RID_U64))
     return TK_EINVAL;
   if (t->slots != slots_for(t->n_build) ||
-      t->table_bytes < table_bytes_for(t->n_build, t->key_type, t->rid_type))
+      t->table_bytes < table_bytes_for(t->n_build, t->key_type, t->rid_type) ||
+      (t->bloom_words != 0 && t->bloom_words != bloom_words_for(t->slots)))
     return TK_EINVAL;
   if (n_probe && !keys) return TK_EINVAL;
   if (capacity && (!out_probe_rowids || !out_build_rowids)) return TK_EINVAL;

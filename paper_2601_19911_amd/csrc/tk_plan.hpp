@@ -47,6 +47,7 @@ struct Tuning {
                                    // never; one workgroup selects over the input instead).
                                    // The conditional cooperative launch costs about 21 us on
                                    // every query (MI355X), 11 % at N = 2^28 float32
+  int join_bloom = 1;              // 1: join tables carry the bloom prefilter
 };
 
 // Whether a sampled query of n keys enqueues the cooperative exact select that

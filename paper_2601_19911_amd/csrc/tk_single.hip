@@ -486,6 +486,8 @@ void set_tuning(const tk_tuning* t) {
   if (t->tail_mode == 2) g_tuning.rank_tail = 0;
   if (t->filter_unroll == 4 || t->filter_unroll == 8) g_tuning.filter_unroll = (uint32_t)t->filter_unroll;
   if (t->filter_grid < 0) g_tuning.filter_grid = 0;
+  if (t->join_bloom == 1) g_tuning.join_bloom = 1;
+  if (t->join_bloom == 2) g_tuning.join_bloom = 0;
 }
 
 // with_sort: the bytes tk_workspace_size reports; else the least workspace a

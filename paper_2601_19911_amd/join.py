@@ -14,7 +14,8 @@ from . import _ptr, _stream_handle, check, lib, rid_code, TK_KEY_I32, TK_KEY_I64
 class tk_join_table(ctypes.Structure):
     _fields_ = [("table", ctypes.c_void_p), ("table_bytes", ctypes.c_uint64),
                 ("n_build", ctypes.c_uint64), ("slots", ctypes.c_uint64),
-                ("key_type", ctypes.c_int32), ("rid_type", ctypes.c_int32)]
+                ("key_type", ctypes.c_int32), ("rid_type", ctypes.c_int32),
+                ("bloom_words", ctypes.c_uint64)]
 
 
 _bound = None

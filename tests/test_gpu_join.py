@@ -23,6 +23,15 @@ from tests.gpu_util import say, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True, params=["bloom", "no_bloom"])
+def bloom_mode(request):
+    """Every case runs on tables built with and without the bloom prefilter."""
+    import paper_2601_19911_amd as tk
+    tk.set_tuning(join_bloom=1 if request.param == "bloom" else 2)
+    yield request.param
+    tk.set_tuning(join_bloom=1)
+
+
 def _sorted_pairs(p, b):
     p = np.asarray(p).astype(np.uint64)
     b = np.asarray(b).astype(np.uint64)
@@ -152,6 +161,21 @@ def test_join_rejects_bad_arguments():
                            ctypes.byref(d), None) == -1  # table too small
     assert L.tk_join_build(keys.data_ptr(), None, 16, 1, 0, buf.data_ptr() + 8, buf.numel() - 8,
                            ctypes.byref(d), None) == -1  # misaligned table
+
+
+def test_join_descriptor_bloom_words(bloom_mode):
+    import ctypes
+    import torch
+    from paper_2601_19911_amd.join import _bind, join_build, join_probe
+    bk = torch.arange(1000, dtype=torch.int64, device="cuda")
+    t = join_build(bk)
+    assert t.desc.bloom_words == (t.slots // 16 if bloom_mode == "bloom" else 0)
+    op, ob, cnt = join_probe(t, bk)
+    torch.cuda.synchronize()
+    assert int(cnt.view(torch.int64).item()) == 1000
+    t.desc.bloom_words = 7  # not slots / 16: rejected before any device work
+    assert _bind().tk_join_probe(ctypes.byref(t.desc), bk.data_ptr(), None, 1000, 0,
+                                 op.data_ptr(), ob.data_ptr(), 1000, cnt.data_ptr(), None) == -1
 
 
 @pytest.mark.parametrize("dtype,log2b", [(np.int64, 24), (np.int32, 22)])
