@@ -452,8 +452,9 @@ typedef struct {
 
 /* Device bytes of the table for n_build pairs (0 on a bad type or n_build > 2^31):
  * a 256-byte header, the slots (8 bytes each for int32 keys with uint32 row-ids,
- * 16 bytes otherwise), room for n_build row-ids and the bloom prefilter's
- * slots / 2 bytes (reserved whether or not the build fills it). */
+ * 16 bytes otherwise), room for n_build row-ids, the bloom prefilter's
+ * slots / 2 bytes (reserved whether or not the build fills it) and an 8 KiB
+ * filter of the build keys that occur more than once. */
 size_t tk_join_table_size(uint64_t n_build, int key_type, int rid_type);
 /* Builds the table from n_build build pairs (stream-ordered, asynchronous).
  *   keys     device array of n_build int32/int64 keys

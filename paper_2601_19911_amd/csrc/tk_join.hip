@@ -6,6 +6,7 @@
 //
 // Table (caller-owned device buffer, see tk_join_table_size):
 //   [header, 256 B][slots: S slots of (key word, row-id word)][side list][bloom words]
+//   [repeat filter words]
 // S is a power of two >= 2 * n_build, so the load factor is at most 1/2.  Open
 // addressing with linear probing; duplicate build keys take one slot each, so
 // a probe walks its run until an empty slot and returns every equal key.  The
@@ -13,7 +14,9 @@
 // equal to it are not hashed but appended to the side list, which a probe of
 // that key reads in full.  The header counts the side list and records whether
 // any build key occurs twice; without duplicates a probe stops at its first
-// hit.
+// hit.  With some, a small filter of the repeated keys (REPEAT_WORDS words, 3
+// bits per key, set by the insert that meets an equal key) lets a probe stop
+// at its first hit whenever its key is not among them.
 //
 // The bloom prefilter (sec. III-B names it as an option of the matching
 // primitive): S / 16 words of 64 bits (8-16 bits per build key), each hashed
@@ -40,6 +43,7 @@ constexpr uint64_t JOIN_MAX_BUILD = 1ull << 31;
 constexpr int PROBE_NT = 256;   // threads per probe workgroup
 constexpr int PROBE_PER = 4;    // probe keys per thread per tile
 constexpr int PROBE_WG_PER_CU = 4;
+constexpr uint64_t REPEAT_WORDS = 1024;  // 8 KiB: cache-resident for every probe
 
 struct JoinHeader {
   unsigned long long side_count;  // build keys equal to the empty marker
@@ -88,6 +92,12 @@ __device__ __forceinline__ uint64_t bloom_hash(uint64_t x) {
 __device__ __forceinline__ unsigned long long bloom_bits(uint64_t z) {
   return (1ull << (z & 63)) | (1ull << ((z >> 6) & 63)) | (1ull << ((z >> 12) & 63));
 }
+// The repeat filter's hash: the same finalizer over the key xor a constant,
+// so that its words and bits are not those of the bloom prefilter.
+__device__ __forceinline__ uint64_t repeat_hash(uint64_t x) {
+  return bloom_hash(x ^ 0x5851F42D4C957F2Dull);
+}
+__device__ __forceinline__ uint64_t repeat_word(uint64_t z) { return z >> 54; }  // < 1024
 
 uint64_t slots_for(uint64_t n_build) {
   uint64_t s = 64;
@@ -111,12 +121,15 @@ uint64_t bloom_offset(uint64_t n_build, uint64_t nslots, uint64_t slot_b, uint64
   return side_offset(nslots, slot_b) + round256((n_build ? n_build : 1) * rid_b);
 }
 
+uint64_t repeat_offset(uint64_t n_build, uint64_t nslots, uint64_t slot_b, uint64_t rid_b) {
+  return bloom_offset(n_build, nslots, slot_b, rid_b) + round256(bloom_words_for(nslots) * 8);
+}
+
 size_t table_bytes_for(uint64_t n_build, int key_type, int rid_type) {
   const uint64_t slot_b = wide_slot(key_type, rid_type) ? 16 : 8;
   const uint64_t rid_b = rid_type == TK_RID_U64 ? 8 : 4;
   const uint64_t nslots = slots_for(n_build);
-  return (size_t)(bloom_offset(n_build, nslots, slot_b, rid_b) +
-                  round256(bloom_words_for(nslots) * 8));
+  return (size_t)(repeat_offset(n_build, nslots, slot_b, rid_b) + REPEAT_WORDS * 8);
 }
 
 // ---- build ------------------------------------------------------------------------------
@@ -125,7 +138,8 @@ template <typename W>
 __global__ __launch_bounds__(256) void k_jfill(Slot<W>* __restrict__ slots, uint64_t nslots,
                                                W empty, JoinHeader* __restrict__ hdr,
                                                unsigned long long* __restrict__ bloom,
-                                               uint64_t nwords) {
+                                               uint64_t nwords,
+                                               unsigned long long* __restrict__ rep) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     hdr->side_count = 0;
     hdr->dup = 0;
@@ -139,6 +153,8 @@ __global__ __launch_bounds__(256) void k_jfill(Slot<W>* __restrict__ slots, uint
   }
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride)
     bloom[i] = 0ull;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < REPEAT_WORDS; i += stride)
+    rep[i] = 0ull;
 }
 
 template <int KT, typename W, typename BR>
@@ -148,7 +164,8 @@ __global__ __launch_bounds__(256) void k_jbuild(const typename JKey<KT>::Raw* __
                                                 uint32_t shift, BR* __restrict__ side,
                                                 JoinHeader* __restrict__ hdr,
                                                 unsigned long long* __restrict__ bloom,
-                                                uint32_t bshift) {
+                                                uint32_t bshift,
+                                                unsigned long long* __restrict__ rep) {
   using Raw = typename JKey<KT>::Raw;
   constexpr Raw EMPTY = JKey<KT>::EMPTY;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -167,13 +184,19 @@ __global__ __launch_bounds__(256) void k_jbuild(const typename JKey<KT>::Raw* __
     const W w = (W)key;
     uint64_t p = slot_of((uint64_t)key, shift);
     // at most n < S keys are hashed, so an empty slot is always ahead
+    bool met = false;
     for (uint64_t step = 0; step <= mask; ++step) {
       const W prev = atomicCAS(&slots[p].key, (W)EMPTY, w);
       if (prev == (W)EMPTY) {
         slots[p].rid = (W)r;
         break;
       }
-      if (prev == w && hdr->dup == 0) hdr->dup = 1;
+      if (prev == w && !met) {  // of two equal keys the later insert always meets the earlier
+        met = true;
+        if (hdr->dup == 0) hdr->dup = 1;
+        const uint64_t z = repeat_hash((uint64_t)key);
+        atomicOr(&rep[repeat_word(z)], bloom_bits(z));
+      }
       p = (p + 1) & mask;
     }
   }
@@ -193,6 +216,7 @@ struct ProbeArgs {
   const JoinHeader* hdr;
   const unsigned long long* bloom;  // null: no prefilter
   uint32_t bshift;                  // 64 - log2(bloom words)
+  const unsigned long long* rep;    // repeat filter
   PR* out_p;
   BR* out_b;
   uint64_t cap;
@@ -300,6 +324,18 @@ __global__ __launch_bounds__(PROBE_NT) void k_jprobe(ProbeArgs<W, BR, PR> a) {
       side[q] = j < a.n && key[q] == EMPTY;
       act[q] = j < a.n && key[q] != EMPTY;
     }
+    // with repeated build keys: whether each key may be one of them (its walk
+    // then goes on past a hit), read beside the bloom words
+    unsigned long long rw[PROBE_PER], rneed[PROBE_PER];
+#pragma unroll
+    for (int q = 0; q < PROBE_PER; ++q) {
+      rw[q] = rneed[q] = 0;
+      if (dup) {
+        const uint64_t z = repeat_hash((uint64_t)key[q]);
+        rneed[q] = bloom_bits(z);
+        if (act[q]) rw[q] = a.rep[repeat_word(z)];
+      }
+    }
     if (a.bloom) {  // keys whose 3 bits are not all set are absent from the build side
       unsigned long long word[PROBE_PER], need[PROBE_PER];
 #pragma unroll
@@ -331,7 +367,7 @@ __global__ __launch_bounds__(PROBE_NT) void k_jprobe(ProbeArgs<W, BR, PR> a) {
             if (cur[q].key == (W)key[q]) {
               emit = true;
               brid = (BR)cur[q].rid;
-              if (!dup) act[q] = false;
+              if (!dup || (rw[q] & rneed[q]) != rneed[q]) act[q] = false;  // no other equal key
             }
             if (act[q]) pos[q] = (pos[q] + 1) & a.mask;
           }
@@ -384,10 +420,8 @@ uint32_t log2_of(uint64_t pow2) {
   return lg;
 }
 
-unsigned long long* bloom_of(const tk_join_table* t, void* table, uint64_t nslots, uint64_t slot_b,
-                             uint64_t rid_b) {
-  return reinterpret_cast<unsigned long long*>(static_cast<char*>(table) +
-                                               bloom_offset(t->n_build, nslots, slot_b, rid_b));
+unsigned long long* words_at(void* table, uint64_t off) {
+  return reinterpret_cast<unsigned long long*>(static_cast<char*>(table) + off);
 }
 
 // nwords: bloom words to fill (0: the table is built without the prefilter)
@@ -397,18 +431,17 @@ int build_t(const void* keys, const void* rids, uint64_t n, void* table, uint64_
   auto* hdr = static_cast<JoinHeader*>(table);
   auto* slots = reinterpret_cast<Slot<W>*>(static_cast<char*>(table) + JOIN_HEADER_BYTES);
   auto* side = reinterpret_cast<BR*>(static_cast<char*>(table) + side_offset(nslots, sizeof(Slot<W>)));
-  auto* bloom = nwords ? reinterpret_cast<unsigned long long*>(
-                             static_cast<char*>(table) +
-                             bloom_offset(n, nslots, sizeof(Slot<W>), sizeof(BR)))
+  auto* bloom = nwords ? words_at(table, bloom_offset(n, nslots, sizeof(Slot<W>), sizeof(BR)))
                        : nullptr;
+  auto* rep = words_at(table, repeat_offset(n, nslots, sizeof(Slot<W>), sizeof(BR)));
   const int c = cus();
   hipLaunchKernelGGL(k_jfill<W>, dim3(launch_grid(c, nslots, 256 * 8, 8)), dim3(256), 0, st, slots,
-                     nslots, (W)JKey<KT>::EMPTY, hdr, bloom, nwords);
+                     nslots, (W)JKey<KT>::EMPTY, hdr, bloom, nwords, rep);
   if (n) {
     hipLaunchKernelGGL((k_jbuild<KT, W, BR>), dim3(launch_grid(c, n, 256 * 4, 16)), dim3(256), 0, st,
                        static_cast<const typename JKey<KT>::Raw*>(keys), static_cast<const BR*>(rids),
                        n, slots, nslots - 1, 64u - log2_of(nslots), side, hdr, bloom,
-                       nwords ? 64u - log2_of(nwords) : 0u);
+                       nwords ? 64u - log2_of(nwords) : 0u, rep);
   }
   return hipGetLastError() == hipSuccess ? TK_OK : TK_EHIP;
 }
@@ -432,8 +465,11 @@ int probe_t(const tk_join_table* t, const void* keys, const void* rids, uint64_t
     a.shift = 64u - log2_of(t->slots);
     a.side = side;
     a.hdr = hdr;
-    a.bloom = t->bloom_words ? bloom_of(t, t->table, t->slots, sizeof(Slot<W>), sizeof(BR)) : nullptr;
+    a.bloom = t->bloom_words ? words_at(t->table, bloom_offset(t->n_build, t->slots, sizeof(Slot<W>),
+                                                               sizeof(BR)))
+                             : nullptr;
     a.bshift = t->bloom_words ? 64u - log2_of(t->bloom_words) : 0u;
+    a.rep = words_at(t->table, repeat_offset(t->n_build, t->slots, sizeof(Slot<W>), sizeof(BR)));
     a.out_p = static_cast<PR*>(out_p);
     a.out_b = static_cast<BR*>(out_b);
     a.cap = (out_p && out_b) ? cap : 0;
