@@ -164,6 +164,21 @@ def test_join_rejects_bad_arguments():
                            ctypes.byref(d), None) == -1  # misaligned table
 
 
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+def test_join_few_repeated_keys_among_unique(dtype):
+    """A handful of build keys occur 2-5 times among 2^17 unique ones: probes of
+    the repeated keys return every copy, probes of the others their one match
+    (the filter of repeated keys decides which walks go on past a hit)."""
+    rng = np.random.default_rng(11)
+    uniq = rng.permutation(1 << 18)[: 1 << 17].astype(dtype) - dtype(1 << 17)
+    reps = rng.choice(uniq, 40, replace=False)
+    extra = np.concatenate([np.repeat(r, 1 + (i % 4)) for i, r in enumerate(reps)]).astype(dtype)
+    bk = rng.permutation(np.concatenate([uniq, extra]))
+    pk = np.concatenate([rng.integers(-(1 << 17), 1 << 17, 200003).astype(dtype), reps])
+    m = _check(bk, None, pk, None, f"few repeated {np.dtype(dtype).name}")
+    assert m > 0
+
+
 def test_join_descriptor_bloom_words(bloom_mode):
     import ctypes
     import torch
