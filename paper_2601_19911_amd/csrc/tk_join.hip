@@ -18,8 +18,8 @@
 // bits per key, set by the insert that meets an equal key) lets a probe stop
 // at its first hit whenever its key is not among them.
 //
-// The bloom prefilter (sec. III-B names it as an option of the matching
-// primitive): S / 16 words of 64 bits (8-16 bits per build key), each hashed
+// The bloom prefilter (sec. III-B names a bloom filter as another form of the
+// matching primitive; here it sits in front of the table): S / 16 words of 64 bits (8-16 bits per build key), each hashed
 // key setting 3 bits of one word.  A probe key reads its word first and walks
 // the slots only when all 3 bits are set, so most probes of absent keys touch
 // one word of a small array (L2- or last-level-cache resident) instead of
@@ -295,10 +295,13 @@ __device__ __forceinline__ void flush_stage(ProbeStage<BR, PR>& st, PR* __restri
   __syncthreads();
 }
 
-// Every tile: each thread's PROBE_PER keys are loaded, then their first slots;
-// the linear-probing walks of all of them advance together, one slot each per
-// round, so a thread has up to PROBE_PER dependent slot loads in flight.  Keys
-// equal to the empty marker are served from the side list afterwards.
+// Every tile: each thread's PROBE_PER keys are loaded, then (in one round)
+// their repeat-filter words when the table has repeated keys and their bloom
+// words when it has the prefilter, then the first slots of the keys still in
+// play; the linear-probing walks of all of them advance together, one slot
+// each per round, so a thread has up to PROBE_PER dependent slot loads in
+// flight.  Keys equal to the empty marker are served from the side list
+// afterwards.
 template <int KT, typename W, typename BR, typename PR>
 __global__ __launch_bounds__(PROBE_NT) void k_jprobe(ProbeArgs<W, BR, PR> a) {
   using Raw = typename JKey<KT>::Raw;
